@@ -1,0 +1,184 @@
+/*
+ * psweep.h -- C ABI of libpsweep.so: parallel SOR / SSOR / ILU(0) sweeps on
+ * structured 5-point (2D) and 7-point (3D) n-diagonal matrices, made parallel
+ * by the overlapping block decomposition and multi-frontal sweep ordering of
+ * R. Tavakoli, "Parallelizing sequential sweeping on structured grids --
+ * fully parallel SOR/ILU preconditioners for structured n-diagonal matrices".
+ * The kernels are HIP for gfx950 (MI355X).
+ *
+ * Problem statement (Sec. 6): solve or precondition A u = f where A is an
+ * irreducibly diagonally dominant structured n-diagonal matrix on a
+ * structured grid.
+ *
+ * Layout.  dim in {2,3}; n[a] interior points on axis a; point index
+ * P = x + n0*(y + n1*z) (x fastest).  Boundary points are not stored:
+ * Dirichlet data are folded into f (eq. 1d:mat, eq. d2d).  Diagonals come in
+ * the order P, W, E, S, N, B, F (2*dim+1 arrays of N doubles; W/E = -x/+x,
+ * S/N = -y/+y, B/F = -z/+z) with the sign convention of eq. d2d:
+ *     a^P_P u_P - sum_X a^X_P u_{P+e_X} = f_P ,   a^X >= 0 expected.
+ * Couplings that point outside the grid are ignored.
+ *
+ * Pointers.  Every vector argument is a device pointer (HIP global memory,
+ * e.g. a torch tensor's data_ptr()) of N doubles unless stated otherwise; the
+ * caller owns it.  The library never keeps or frees a caller pointer; it
+ * copies diagonals into its own device arrays.  `stream` is a hipStream_t
+ * (NULL = the default stream); every call is ordered on that stream and
+ * returns after enqueueing unless it says otherwise.
+ *
+ * Errors.  Every call returns a psw_status and never throws.  A handle is not
+ * thread-safe; the server object is.
+ */
+#ifndef PSWEEP_H
+#define PSWEEP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PSW_OK = 0,
+    PSW_EINVAL = -1,     /* bad argument (dims, sizes, omega, partition, pointer) */
+    PSW_ENOMEM = -2,     /* device or host allocation failed */
+    PSW_EDEVICE = -3,    /* a HIP call failed */
+    PSW_ENOCONV = -4,    /* iteration limit reached before the tolerance */
+    PSW_EBREAKDOWN = -5, /* Krylov breakdown (p.Ap <= 0, zero Arnoldi norm, NaN/Inf residual) */
+    PSW_EPIVOT = -6,     /* non-positive ILU(0) pivot */
+    PSW_EBUSY = -7,      /* admission refused: memory budget exhausted */
+    PSW_ENOTSUP = -8,    /* combination not supported by this build */
+    PSW_ESTATE = -9      /* call out of order (e.g. sweep before diagonals are set) */
+} psw_status;
+
+/* precision of the preconditioner sweeps: FP64; FP32 diagonals and FP32
+   arithmetic; BF16-stored diagonals with FP32 arithmetic.  Outer vectors,
+   residuals, dot products and updates are always FP64. */
+typedef enum { PSW_F64 = 0, PSW_F32 = 1, PSW_BF16 = 2 } psw_prec;
+typedef enum { PSW_SSOR = 0, PSW_ILU0 = 1, PSW_NONE = 2 } psw_precond;
+typedef enum { PSW_SOR_STATIONARY = 0, PSW_CG = 1, PSW_FGMRES = 2 } psw_method;
+
+typedef struct psw_problem psw_problem;
+
+typedef struct {
+    int64_t iters;       /* sweeps (stationary) or Krylov iterations */
+    double relres;       /* final ||f - A u||_2 / ||f||_2, recomputed at exit */
+    int converged;       /* 1 if relres <= rtol was reached */
+    int status;          /* psw_status of the solve */
+    double t_total_ms;   /* wall time of the solve on the host clock */
+    double t_precond_ms; /* time in preconditioner kernels (HIP events; 0 if not measured) */
+} psw_info;
+
+/* Create a problem on a dim-dimensional grid with n[0..dim-1] interior
+ * points; stencil must be 2*dim+1 (5 or 7).  Memory for the handle is owned
+ * by the library; free it with psw_problem_destroy.  The current HIP device
+ * at creation is used for every later call on the handle. */
+psw_status psw_problem_create(int dim, const int64_t n[3], int stencil, psw_problem **out);
+psw_status psw_problem_destroy(psw_problem *prob);
+
+/* Set the matrix from 2*dim+1 diagonal arrays (order P,W,E,S,N,B,F), host
+ * (on_device=0) or device (on_device=1) pointers.  sweep_prec selects the
+ * precision of the preconditioner sweeps.  Invalidates preconditioner state. */
+psw_status psw_set_diagonals(psw_problem *prob, const double *const diag[], int on_device,
+                             psw_prec sweep_prec, void *stream);
+
+/* Assemble the diagonals of -div(alpha grad u) + beta u on a unit-spaced
+ * grid (eq. d2d; Sec. 2 harmonic face means) on the device.  alpha[a],
+ * a < dim, is the axis-a coefficient on all (n0+2)*(n1+2)[*(n2+2)] nodes,
+ * boundary ring included, node (i,j,k) at i + (n0+2)*(j + (n1+2)*k) and
+ * interior point x at node x+1.  Face coupling = harmonic mean of the two
+ * node values; a^P = sum of the 2*dim face couplings + beta.  Device
+ * pointers.  Equivalent to psw_set_diagonals with the assembled arrays. */
+psw_status psw_assemble_diffusion(psw_problem *prob, const double *const alpha[], double beta,
+                                  psw_prec sweep_prec, void *stream);
+
+/* Copy diagonal k (0 = P ... 2*dim) into the device array out (N doubles). */
+psw_status psw_get_diagonal(psw_problem *prob, int k, double *out, void *stream);
+
+/* Relaxation factors per start corner (Sec. 2: w_SW, w_NE, ...): count = 1
+ * (same factor everywhere) or 2^dim, indexed by the start corner of the
+ * sweep: bit a set when the sweep along axis a starts at the high end (so in
+ * 2D: 0 = SW, 1 = SE, 2 = NW, 3 = NE).  Each factor must lie in (0,2).
+ * The SSOR preconditioner uses omega[0]. */
+psw_status psw_set_relaxation(psw_problem *prob, const double *omega, int count);
+
+/* Decomposition into p[0] x p[1] (x p[2]) subdomains: contiguous ranges per
+ * axis, the first n mod p ranges one point longer (Sec. 2.1).  Every
+ * subdomain must be at least 2 points long on every axis.  overlap is the
+ * halo depth staged per subdomain (>= 2; a 5/7-point sweep reads 2 layers,
+ * Sec. 2.3) and does not change any result.  phase swaps the two members
+ * of every direction pair of the schedule (Sec. 2.2). */
+psw_status psw_set_decomposition(psw_problem *prob, const int p[3], int overlap, int phase);
+
+/* One decomposed SOR sweep, FP64 (Secs. 2-4).  Subdomain (r,s,t) sweeps at
+ * iteration k in direction sigma_{k mod 2^dim} with the sign of axis a
+ * flipped for odd coordinate a; base cycle 2D: (-,-),(+,+),(+,-),(-,+);
+ * 3D: (-,-,-),(+,+,+),(+,-,-),(-,+,+),(-,+,-),(+,-,+),(+,+,-),(-,-,+).
+ * Every point takes new values from the neighbours on the side where its own
+ * subdomain's sweep begins and old values from u_in on the other side;
+ * points of start faces shared with a neighbour that also starts there are
+ * solved jointly with their partners (eq. 2d:sor2b2, 2x2; eq. 2d:sor4b4,
+ * 4x4; the 3D 4x4 and 8x8 systems of Sec. 4).  u_in, f, u_out are device
+ * arrays of N doubles; u_out must not alias u_in. */
+psw_status psw_sweep(psw_problem *prob, int64_t iteration, const double *u_in, const double *f,
+                     double *u_out, void *stream);
+
+/* Build the preconditioner state (pivots, packed diagonals) for kind.  Done
+ * implicitly by the first psw_precond_apply / psw_solve; returns PSW_EPIVOT
+ * if an ILU(0) pivot is not positive.  The preconditioner uses the direction
+ * map of schedule step 0 (d) for its forward half-sweep and -d for its
+ * backward half-sweep (Sec. 5: a symmetric Gauss-Seidel pass of the parallel
+ * sweep is the parallel ILU(0) / SSOR preconditioner). */
+psw_status psw_precond_setup(psw_problem *prob, psw_precond kind, void *stream);
+
+/* z = M^-1 r (symmetric = 0) or z = (M^-1 + M^-T) r / 2 (symmetric = 1) with
+ *   SSOR : M^-1 = (2-w) (D/w - N2)^-1 (D/w) (D/w - N1)^-1
+ *   ILU0 : M^-1 = (D~ - N2)^-1 D~ (D~ - N1)^-1
+ * N1 / N2: upstream couplings under d / -d (N1 + N2 = all off-diagonal
+ * couplings); D~: ILU(0) pivots of the decomposed factorisation.  r and z
+ * are device arrays of N doubles and must not alias.  PSW_NONE copies. */
+psw_status psw_precond_apply(psw_problem *prob, psw_precond kind, int symmetric, const double *r,
+                             double *z, void *stream);
+
+/* One half-sweep of the preconditioner, FP64 in and out (for measurement and
+ * tests): which = 0: y = (Piv - N1)^-1 r;  1: z = c (Piv - N2)^-1 Piv y;
+ * 2: y = (Piv - N2)^-T r;  3: z = c (Piv - N1)^-T Piv y.  (Piv, c) =
+ * (D/w, 2-w) for SSOR and (D~, 1) for ILU0. */
+psw_status psw_precond_half(psw_problem *prob, psw_precond kind, int which, const double *in,
+                            double *out, void *stream);
+
+/* ILU(0) pivots D~ of the decomposed factorisation (FP64, N doubles):
+ * D~_P = a^P_P - sum_{Q upstream of P in P's subdomain} a_{P->Q} a_{Q->P} / D~_Q. */
+psw_status psw_ilu_pivots(psw_problem *prob, double *piv, void *stream);
+
+/* y = A x (device arrays, N doubles, no aliasing). */
+psw_status psw_spmv(psw_problem *prob, const double *x, double *y, void *stream);
+
+/* Deterministic dot product x.y (fixed reduction order independent of the
+ * launch); result written to *out on the host after the stream drains. */
+psw_status psw_dot(psw_problem *prob, const double *x, const double *y, double *out, void *stream);
+
+/* Solve A u = f to ||f - A u||_2 / ||f||_2 <= rtol from the initial guess in
+ * u.  method: stationary decomposed SOR (precond ignored), CG with the
+ * symmetric form (M^-1 + M^-T)/2 of the preconditioner, or right-
+ * preconditioned flexible GMRES(restart) with M^-1.  Returns PSW_ENOCONV when
+ * maxit is reached.  info may be NULL.  Blocks until the solve ends. */
+psw_status psw_solve(psw_problem *prob, psw_method method, psw_precond precond, double rtol,
+                     int64_t maxit, int restart, const double *f, double *u, psw_info *info,
+                     void *stream);
+
+/* Solve count independent problems (each with its own handle, decomposition
+ * and preconditioner) with CG and the symmetric preconditioner, interleaving
+ * their iterations so that the device works on all of them at once.
+ * Converged problems drop out.  infos[i] receives each result. */
+psw_status psw_batch_solve(int count, psw_problem *const *probs, const double *const *f,
+                           double *const *u, psw_method method, psw_precond precond, double rtol,
+                           int64_t maxit, psw_info *infos, void *stream);
+
+/* Readable name of a status code (static storage). */
+const char *psw_status_string(psw_status st);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSWEEP_H */

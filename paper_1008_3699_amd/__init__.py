@@ -1,0 +1,199 @@
+"""Python binding of libpsweep.so: parallel SOR / SSOR / ILU(0) sweeps on MI355X.
+
+Argument marshalling only: every step runs in the HIP kernels of
+``libpsweep.so`` (see ``include/psweep.h`` for the semantics of each call).
+Vectors are torch CUDA float64 tensors with N = prod(n) elements, x fastest;
+PyTorch provides device memory and the current stream.  There is no CPU
+fallback: without the built library, or without a GPU, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = ["Problem", "PswError", "lib", "SSOR", "ILU0", "NONE", "STATIONARY", "CG", "FGMRES"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(_HERE, "libpsweep.so")
+
+SSOR, ILU0, NONE = 0, 1, 2
+STATIONARY, CG, FGMRES = 0, 1, 2
+_PREC = {"f64": 0, "f32": 1, "bf16": 2}
+_KIND = {"ssor": SSOR, "ilu0": ILU0, "none": NONE}
+_METHOD = {"sor": STATIONARY, "stationary": STATIONARY, "cg": CG, "fgmres": FGMRES}
+
+
+class PswError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int64), ("relres", ctypes.c_double), ("converged", ctypes.c_int),
+                ("status", ctypes.c_int), ("t_total_ms", ctypes.c_double), ("t_precond_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libpsweep.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(SO_PATH):
+            raise RuntimeError(f"{SO_PATH} is missing: build it with `python -m paper_1008_3699_amd.build`")
+        L = ctypes.CDLL(SO_PATH)
+        vp, i64, dbl, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+        pp = ctypes.POINTER(ctypes.c_void_p)
+        sig = {
+            "psw_problem_create": [ci, ctypes.POINTER(i64), ci, ctypes.POINTER(vp)],
+            "psw_problem_destroy": [vp],
+            "psw_set_diagonals": [vp, pp, ci, ci, vp],
+            "psw_assemble_diffusion": [vp, pp, dbl, ci, vp],
+            "psw_get_diagonal": [vp, ci, vp, vp],
+            "psw_set_relaxation": [vp, ctypes.POINTER(dbl), ci],
+            "psw_set_decomposition": [vp, ctypes.POINTER(ci), ci, ci],
+            "psw_sweep": [vp, i64, vp, vp, vp, vp],
+            "psw_precond_setup": [vp, ci, vp],
+            "psw_precond_apply": [vp, ci, ci, vp, vp, vp],
+            "psw_precond_half": [vp, ci, ci, vp, vp, vp],
+            "psw_ilu_pivots": [vp, vp, vp],
+            "psw_spmv": [vp, vp, vp, vp],
+            "psw_dot": [vp, vp, vp, ctypes.POINTER(dbl), vp],
+            "psw_solve": [vp, ci, ci, dbl, i64, ci, vp, vp, ctypes.POINTER(Info), vp],
+            "psw_batch_solve": [ci, pp, pp, pp, ci, ci, dbl, i64, ctypes.POINTER(Info), vp],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ci
+        L.psw_status_string.argtypes = [ci]
+        L.psw_status_string.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def status_string(st):
+    try:
+        return lib().psw_status_string(int(st)).decode()
+    except Exception:  # library not loadable: report the raw code
+        return str(st)
+
+
+def _check(st, where):
+    if st != 0:
+        raise PswError(st, where)
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t, N, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != N:
+        raise ValueError(f"{name} must be a contiguous float64 tensor of {N} elements")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Problem:
+    """One structured n-diagonal problem on the current HIP device."""
+
+    def __init__(self, dim, n):
+        n = tuple(int(v) for v in n)
+        assert len(n) == dim
+        self.dim, self.n = dim, n
+        self.N = 1
+        for v in n:
+            self.N *= v
+        arr = (ctypes.c_int64 * 3)(*(list(n) + [1] * (3 - dim)))
+        h = ctypes.c_void_p()
+        _check(lib().psw_problem_create(dim, arr, 2 * dim + 1, ctypes.byref(h)), "psw_problem_create")
+        self._h = h
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().psw_problem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    # ---- set-up
+    def set_diagonals(self, diags, prec="f64", stream=None):
+        ptrs = (ctypes.c_void_p * 7)(*([_ptr(d, self.N, "diag").value for d in diags] + [0] * (7 - len(diags))))
+        _check(lib().psw_set_diagonals(self._h, ptrs, 1, _PREC[prec], _stream(stream)), "psw_set_diagonals")
+
+    def assemble(self, alphas, beta=0.0, prec="f64", stream=None):
+        nn = 1
+        for v in self.n:
+            nn *= v + 2
+        ptrs = (ctypes.c_void_p * 3)(*([_ptr(a, nn, "alpha").value for a in alphas] + [0] * (3 - len(alphas))))
+        _check(lib().psw_assemble_diffusion(self._h, ptrs, float(beta), _PREC[prec], _stream(stream)),
+               "psw_assemble_diffusion")
+
+    def get_diagonal(self, k, out, stream=None):
+        _check(lib().psw_get_diagonal(self._h, int(k), _ptr(out, self.N, "out"), _stream(stream)), "psw_get_diagonal")
+
+    def set_relaxation(self, omega):
+        om = list(omega) if hasattr(omega, "__len__") else [omega]
+        arr = (ctypes.c_double * len(om))(*om)
+        _check(lib().psw_set_relaxation(self._h, arr, len(om)), "psw_set_relaxation")
+
+    def set_decomposition(self, p, overlap=2, phase=0):
+        arr = (ctypes.c_int * 3)(*(list(p) + [1] * (3 - len(p))))
+        _check(lib().psw_set_decomposition(self._h, arr, int(overlap), int(phase)), "psw_set_decomposition")
+
+    # ---- operations
+    def sweep(self, iteration, u_in, f, u_out, stream=None):
+        _check(lib().psw_sweep(self._h, int(iteration), _ptr(u_in, self.N, "u_in"), _ptr(f, self.N, "f"),
+                               _ptr(u_out, self.N, "u_out"), _stream(stream)), "psw_sweep")
+
+    def precond_setup(self, kind, stream=None):
+        _check(lib().psw_precond_setup(self._h, _KIND[kind], _stream(stream)), "psw_precond_setup")
+
+    def precond_apply(self, kind, r, z, symmetric=False, stream=None):
+        _check(lib().psw_precond_apply(self._h, _KIND[kind], int(bool(symmetric)), _ptr(r, self.N, "r"),
+                                       _ptr(z, self.N, "z"), _stream(stream)), "psw_precond_apply")
+
+    def precond_half(self, kind, which, inp, out, stream=None):
+        _check(lib().psw_precond_half(self._h, _KIND[kind], int(which), _ptr(inp, self.N, "in"),
+                                      _ptr(out, self.N, "out"), _stream(stream)), "psw_precond_half")
+
+    def ilu_pivots(self, out, stream=None):
+        _check(lib().psw_ilu_pivots(self._h, _ptr(out, self.N, "piv"), _stream(stream)), "psw_ilu_pivots")
+
+    def spmv(self, x, y, stream=None):
+        _check(lib().psw_spmv(self._h, _ptr(x, self.N, "x"), _ptr(y, self.N, "y"), _stream(stream)), "psw_spmv")
+
+    def dot(self, x, y, stream=None):
+        out = ctypes.c_double()
+        _check(lib().psw_dot(self._h, _ptr(x, self.N, "x"), _ptr(y, self.N, "y"), ctypes.byref(out),
+                             _stream(stream)), "psw_dot")
+        return out.value
+
+    def solve(self, method, precond, f, u, rtol=1e-8, maxit=100000, restart=30, stream=None, check=True):
+        info = Info()
+        st = lib().psw_solve(self._h, _METHOD[method], _KIND[precond], float(rtol), int(maxit), int(restart),
+                             _ptr(f, self.N, "f"), _ptr(u, self.N, "u"), ctypes.byref(info), _stream(stream))
+        if check and st not in (0, -4):
+            raise PswError(st, "psw_solve")
+        d = info.as_dict()
+        d["status"] = st
+        return d

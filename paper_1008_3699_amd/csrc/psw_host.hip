@@ -1,0 +1,740 @@
+// psw_host.hip -- host runtime and C ABI of libpsweep.so (see include/psweep.h).
+//
+// A psw_problem owns FP64 device copies of the diagonals, the subdomain
+// ("tile") table, the preconditioner state (pivots and diagonals in the sweep
+// precision) and the Krylov workspace.  Every kernel runs on the caller's
+// stream; scalars of the Krylov recurrences stay on the device and only the
+// residual norm crosses to the host for the stopping test.
+#include "psw_internal.h"
+#include "../../include/psweep.h"
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+using namespace psw;
+
+namespace {
+
+// Base direction cycle of tile (0,0,0) (Sec. 2.2 rules; Sec. 4 for 3D):
+// consecutive pairs are mutually reversed and each pair uses a new diagonal.
+const int kCycle2[4][3] = {{-1, -1, 1}, {+1, +1, 1}, {+1, -1, 1}, {-1, +1, 1}};
+const int kCycle3[8][3] = {{-1, -1, -1}, {+1, +1, +1}, {+1, -1, -1}, {-1, +1, +1},
+                           {-1, +1, -1}, {+1, -1, +1}, {+1, +1, -1}, {-1, -1, +1}};
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    bool ensure(size_t b) {
+        if (bytes >= b && p) return true;
+        release();
+        if (hipMalloc(&p, b) != hipSuccess) {
+            p = nullptr;
+            return false;
+        }
+        bytes = b;
+        return true;
+    }
+    template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+size_t store_bytes(Store s) { return s == Store::F64 ? 8 : (s == Store::F32 ? 4 : 2); }
+
+} // namespace
+
+struct PrecState {
+    bool ready = false;
+    double omega = 1.0;
+    double c = 1.0;
+    DevBuf diag[7]; // off-diagonals in sweep precision (index 0 unused)
+    DevBuf piv;     // pivots in sweep precision
+    DevBuf piv64;   // pivots in FP64
+};
+
+struct psw_problem {
+    int device = 0;
+    int dim = 2;
+    int n[3] = {1, 1, 1};
+    int64_t N = 0;
+    bool has_diag = false;
+    psw_prec prec = PSW_F64;
+    DevBuf diag[7];
+    double omega[8] = {1, 1, 1, 1, 1, 1, 1, 1};
+    int p[3] = {1, 1, 1};
+    int overlap = 2;
+    int phase = 0;
+    bool has_decomp = false;
+    DevBuf tiles;
+    int ntiles = 0;
+    int cmax = 1, l1max = 1, l2max = 1;
+    PrecState pc[2];
+    // workspace
+    DevBuf w_r, w_z, w_p, w_q, w_t, w_y, w_y2, w_z1;
+    DevBuf partials, scal;
+    DevBuf gm_V, gm_Z, gm_h;
+    size_t lds_limit = 65536;
+};
+
+namespace {
+
+#define HIPCHK(x)                                                                                                  \
+    do {                                                                                                           \
+        hipError_t e_ = (x);                                                                                       \
+        if (e_ != hipSuccess) {                                                                                    \
+            return PSW_EDEVICE;                                                                                    \
+        }                                                                                                          \
+    } while (0)
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+        else prev = -1;
+        (void)hipGetLastError(); // drop an error left by an earlier, already reported call
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+void partition(int n, int p, std::vector<int> &lo, std::vector<int> &len) {
+    lo.resize(p);
+    len.resize(p);
+    int base = n / p, rem = n % p, s = 0;
+    for (int r = 0; r < p; ++r) {
+        len[r] = base + (r < rem ? 1 : 0);
+        lo[r] = s;
+        s += len[r];
+    }
+}
+
+PassGeom geom(const psw_problem *P, const int sig[3]) {
+    PassGeom g{};
+    g.dim = P->dim;
+    for (int a = 0; a < 3; ++a) {
+        g.n[a] = P->n[a];
+        g.sig[a] = a < P->dim ? sig[a] : 1;
+    }
+    g.ntiles = P->ntiles;
+    g.tiles = P->tiles.as<TileDesc>();
+    g.cmax = P->cmax;
+    g.l1max = P->l1max;
+    g.l2max = P->l2max;
+    return g;
+}
+
+void sched_sig(const psw_problem *P, int64_t it, int sig[3]) {
+    int period = 1 << P->dim;
+    int k = (int)(it % period);
+    if (P->phase) k ^= 1;
+    const int *s = P->dim == 2 ? kCycle2[k] : kCycle3[k];
+    for (int a = 0; a < 3; ++a) sig[a] = a < P->dim ? s[a] : 1;
+}
+
+Store store_of(psw_prec p) { return p == PSW_F64 ? Store::F64 : (p == PSW_F32 ? Store::F32 : Store::BF16); }
+
+const double *const *diag64(const psw_problem *P, const double **tmp) {
+    for (int k = 0; k < 7; ++k) tmp[k] = P->diag[k].as<const double>();
+    return tmp;
+}
+
+psw_status ensure_work(psw_problem *P) {
+    size_t b = sizeof(double) * (size_t)P->N;
+    if (!P->w_r.ensure(b) || !P->w_z.ensure(b) || !P->w_p.ensure(b) || !P->w_q.ensure(b) || !P->w_t.ensure(b) ||
+        !P->w_y.ensure(b) || !P->w_y2.ensure(b) || !P->w_z1.ensure(b) ||
+        !P->partials.ensure(sizeof(double) * kRedBlocks * 64) || !P->scal.ensure(sizeof(double) * 64))
+        return PSW_ENOMEM;
+    return PSW_OK;
+}
+
+psw_status check_lds(const psw_problem *P, size_t elem) {
+    size_t need = elem * (size_t)(4 * P->cmax + 4 * P->l2max + 4 * P->l1max + 2);
+    return need <= P->lds_limit ? PSW_OK : PSW_ENOTSUP;
+}
+
+// preconditioner state for kind (SSOR: Piv = D/w, c = 2-w; ILU0: Piv = D~, c = 1)
+psw_status precond_setup(psw_problem *P, psw_precond kind, hipStream_t st) {
+    if (kind != PSW_SSOR && kind != PSW_ILU0) return PSW_EINVAL;
+    if (!P->has_diag || !P->has_decomp) return PSW_ESTATE;
+    PrecState &S = P->pc[kind];
+    if (S.ready) return PSW_OK;
+    Store s = store_of(P->prec);
+    psw_status ps = check_lds(P, 8);
+    if (ps) return ps;
+    if ((ps = ensure_work(P))) return ps;
+    size_t eb = store_bytes(s) * (size_t)P->N;
+    for (int k = 1; k < 2 * P->dim + 1; ++k) {
+        if (!S.diag[k].ensure(eb)) return PSW_ENOMEM;
+        HIPCHK(launch_convert(P->diag[k].as<double>(), S.diag[k].p, s, P->N, 1.0, st));
+    }
+    if (!S.piv.ensure(eb) || !S.piv64.ensure(sizeof(double) * (size_t)P->N)) return PSW_ENOMEM;
+    if (kind == PSW_SSOR) {
+        S.omega = P->omega[0];
+        S.c = 2.0 - S.omega;
+        HIPCHK(launch_copy_scaled(S.piv64.as<double>(), P->diag[0].as<double>(), 1.0 / S.omega, P->N, st));
+    } else {
+        S.c = 1.0;
+        int sig[3];
+        sched_sig(P, 0, sig);
+        PassGeom g = geom(P, sig);
+        const double *d[7];
+        int *bad = reinterpret_cast<int *>(P->scal.as<double>() + 63);
+        HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), st));
+        HIPCHK(launch_ilu_pivots(g, diag64(P, d), S.piv64.as<double>(), bad, st));
+        int hb = 0;
+        HIPCHK(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (hb) return PSW_EPIVOT;
+    }
+    HIPCHK(launch_convert(S.piv64.as<double>(), S.piv.p, s, P->N, 1.0, st));
+    S.ready = true;
+    return PSW_OK;
+}
+
+// one half-sweep; which: 0 fwd (N1), 1 bwd (N2, scaled by c), 2 (Piv-N2)^-T, 3 (Piv-N1)^-T
+psw_status half(psw_problem *P, psw_precond kind, int which, const void *in, bool in_f64, bool scale_by_piv,
+                void *out, bool out_f64, double cscale, hipStream_t st) {
+    PrecState &S = P->pc[kind];
+    Store s = store_of(P->prec);
+    int sig[3];
+    sched_sig(P, 0, sig);
+    if (which == 1 || which == 3) for (int a = 0; a < 3; ++a) sig[a] = -sig[a];
+    PassGeom g = geom(P, sig);
+    const void *d[7];
+    for (int k = 0; k < 7; ++k) d[k] = S.diag[k].p;
+    if (which <= 1)
+        HIPCHK(launch_half_start(g, s, d, S.piv.p, in, in_f64, scale_by_piv, out, out_f64, cscale, st));
+    else
+        HIPCHK(launch_half_end(g, s, d, S.piv.p, in, in_f64, scale_by_piv, out, out_f64, st));
+    return PSW_OK;
+}
+
+// z = M^-1 r or (M^-1 + M^-T) r / 2
+psw_status precond_apply(psw_problem *P, psw_precond kind, int symmetric, const double *r, double *z,
+                         hipStream_t st) {
+    if (kind == PSW_NONE) {
+        HIPCHK(hipMemcpyAsync(z, r, sizeof(double) * P->N, hipMemcpyDeviceToDevice, st));
+        return PSW_OK;
+    }
+    psw_status ps = precond_setup(P, kind, st);
+    if (ps) return ps;
+    if ((ps = ensure_work(P))) return ps;
+    PrecState &S = P->pc[kind];
+    const bool f64 = P->prec == PSW_F64;
+    void *y = P->w_y.p; // intermediate in sweep precision
+    if (!symmetric) {
+        if ((ps = half(P, kind, 0, r, true, false, y, f64, 1.0, st))) return ps;
+        return half(P, kind, 1, y, f64, true, z, true, S.c, st);
+    }
+    double *z1 = P->w_z1.as<double>();
+    if ((ps = half(P, kind, 0, r, true, false, y, f64, 1.0, st))) return ps;
+    if ((ps = half(P, kind, 1, y, f64, true, z1, true, S.c, st))) return ps;
+    void *y2 = P->w_y2.p;
+    if ((ps = half(P, kind, 2, r, true, false, y2, f64, 1.0, st))) return ps;
+    if ((ps = half(P, kind, 3, y2, f64, true, y, f64, 1.0, st))) return ps;
+    HIPCHK(launch_scale_add(z, z1, 0.5, y, f64, 0.5 * S.c, P->N, st));
+    return PSW_OK;
+}
+
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+psw_status host_norm(psw_problem *P, const double *x, double *out, hipStream_t st) {
+    double *s = P->scal.as<double>();
+    HIPCHK(launch_dot(x, x, P->N, P->partials.as<double>(), s + 10, st));
+    double h = 0;
+    HIPCHK(hipMemcpyAsync(&h, s + 10, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *out = std::sqrt(h);
+    return PSW_OK;
+}
+
+psw_status solve_stationary(psw_problem *P, double rtol, int64_t maxit, const double *f, double *u, psw_info *info,
+                            hipStream_t st) {
+    psw_status ps = ensure_work(P);
+    if (ps) return ps;
+    if ((ps = check_lds(P, 8))) return ps;
+    const double *d[7];
+    diag64(P, d);
+    double nf;
+    if ((ps = host_norm(P, f, &nf, st))) return ps;
+    if (nf == 0.0) nf = 1.0;
+    double *tmp = P->w_t.as<double>(), *res = P->w_r.as<double>();
+    double rel = 0;
+    int64_t it = 0;
+    bool conv = false;
+    for (it = 0; it < maxit;) {
+        int sig[3];
+        sched_sig(P, it, sig);
+        PassGeom g = geom(P, sig);
+        HIPCHK(launch_sweep_stationary(g, d, P->omega, u, f, tmp, st));
+        HIPCHK(hipMemcpyAsync(u, tmp, sizeof(double) * P->N, hipMemcpyDeviceToDevice, st));
+        ++it;
+        HIPCHK(launch_residual(P->dim, P->n, d, f, u, res, st));
+        double nr;
+        if ((ps = host_norm(P, res, &nr, st))) return ps;
+        rel = nr / nf;
+        if (!std::isfinite(rel)) return PSW_EBREAKDOWN;
+        if (rel <= rtol) {
+            conv = true;
+            break;
+        }
+    }
+    if (info) {
+        info->iters = it;
+        info->relres = rel;
+        info->converged = conv;
+    }
+    return conv ? PSW_OK : PSW_ENOCONV;
+}
+
+psw_status solve_cg(psw_problem *P, psw_precond kind, double rtol, int64_t maxit, const double *f, double *x,
+                    psw_info *info, hipStream_t st) {
+    psw_status ps = ensure_work(P);
+    if (ps) return ps;
+    if (kind != PSW_NONE && (ps = precond_setup(P, kind, st))) return ps;
+    const double *d[7];
+    diag64(P, d);
+    const int64_t N = P->N;
+    double *r = P->w_r.as<double>(), *z = P->w_z.as<double>(), *p = P->w_p.as<double>(), *q = P->w_q.as<double>();
+    double *s = P->scal.as<double>();
+    double *s_rz = s + 0, *s_rz2 = s + 1, *s_pq = s + 2, *s_rr = s + 3;
+    double *part = P->partials.as<double>();
+    double nf;
+    if ((ps = host_norm(P, f, &nf, st))) return ps;
+    if (nf == 0.0) nf = 1.0;
+    HIPCHK(launch_residual(P->dim, P->n, d, f, x, r, st));
+    double nr;
+    if ((ps = host_norm(P, r, &nr, st))) return ps;
+    double rel = nr / nf;
+    int64_t it = 0;
+    bool conv = rel <= rtol;
+    if (!conv) {
+        if ((ps = precond_apply(P, kind, 1, r, z, st))) return ps;
+        HIPCHK(launch_dot(r, z, N, part, s_rz, st));
+        HIPCHK(hipMemcpyAsync(p, z, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+        while (it < maxit) {
+            HIPCHK(launch_spmv(P->dim, P->n, d, p, q, st));
+            HIPCHK(launch_dot(p, q, N, part, s_pq, st));
+            HIPCHK(launch_cg_update_xr(x, r, p, q, s_rz, s_pq, N, part, s_rr, st));
+            ++it;
+            double h[2];
+            HIPCHK(hipMemcpyAsync(h, s_pq, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if (!(h[0] > 0.0) || !std::isfinite(h[1])) return PSW_EBREAKDOWN;
+            rel = std::sqrt(h[1]) / nf;
+            if (rel <= rtol) {
+                conv = true;
+                break;
+            }
+            if ((ps = precond_apply(P, kind, 1, r, z, st))) return ps;
+            HIPCHK(launch_dot(r, z, N, part, s_rz2, st));
+            HIPCHK(launch_cg_update_p(p, z, s_rz2, s_rz, N, st));
+            std::swap(s_rz, s_rz2);
+        }
+    }
+    // true residual at exit
+    HIPCHK(launch_residual(P->dim, P->n, d, f, x, r, st));
+    if ((ps = host_norm(P, r, &nr, st))) return ps;
+    if (info) {
+        info->iters = it;
+        info->relres = nr / nf;
+        info->converged = conv;
+    }
+    return conv ? PSW_OK : PSW_ENOCONV;
+}
+
+psw_status solve_fgmres(psw_problem *P, psw_precond kind, double rtol, int64_t maxit, int m, const double *f,
+                        double *x, psw_info *info, hipStream_t st) {
+    psw_status ps = ensure_work(P);
+    if (ps) return ps;
+    if (kind != PSW_NONE && (ps = precond_setup(P, kind, st))) return ps;
+    if (m < 1) m = 30;
+    if (m > 60) m = 60;
+    const int64_t N = P->N;
+    if (!P->gm_V.ensure(sizeof(double) * (size_t)N * (m + 1)) || !P->gm_Z.ensure(sizeof(double) * (size_t)N * m) ||
+        !P->gm_h.ensure(sizeof(double) * 128))
+        return PSW_ENOMEM;
+    const double *d[7];
+    diag64(P, d);
+    double *V = P->gm_V.as<double>(), *Z = P->gm_Z.as<double>(), *hd = P->gm_h.as<double>();
+    double *r = P->w_r.as<double>(), *w = P->w_q.as<double>();
+    double *part = P->partials.as<double>();
+    double nf;
+    if ((ps = host_norm(P, f, &nf, st))) return ps;
+    if (nf == 0.0) nf = 1.0;
+    int64_t it = 0;
+    bool conv = false;
+    double rel = 1.0;
+    std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hv(m + 1);
+    while (it < maxit) {
+        HIPCHK(launch_residual(P->dim, P->n, d, f, x, r, st));
+        double beta;
+        if ((ps = host_norm(P, r, &beta, st))) return ps;
+        rel = beta / nf;
+        if (!std::isfinite(rel)) return PSW_EBREAKDOWN;
+        if (rel <= rtol) {
+            conv = true;
+            break;
+        }
+        HIPCHK(launch_copy_scaled(V, r, 1.0 / beta, N, st));
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int k_used = 0;
+        for (int k = 0; k < m && it < maxit; ++k) {
+            double *Vk = V + (size_t)k * N, *Zk = Z + (size_t)k * N;
+            if ((ps = precond_apply(P, kind, 0, Vk, Zk, st))) return ps;
+            HIPCHK(launch_spmv(P->dim, P->n, d, Zk, w, st));
+            // classical Gram-Schmidt, two passes
+            for (int pass = 0; pass < 2; ++pass) {
+                HIPCHK(launch_multi_dot(V, w, k + 1, N, part, hd, st));
+                HIPCHK(hipMemcpyAsync(hv.data(), hd, sizeof(double) * (k + 1), hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+                for (int i = 0; i <= k; ++i) {
+                    H[i * m + k] += hv[i];
+                    hv[i] = -hv[i];
+                }
+                HIPCHK(hipMemcpyAsync(hd + 64, hv.data(), sizeof(double) * (k + 1), hipMemcpyHostToDevice, st));
+                HIPCHK(launch_multi_axpy(w, V, hd + 64, k + 1, N, true, st));
+            }
+            double hn;
+            if ((ps = host_norm(P, w, &hn, st))) return ps;
+            H[(k + 1) * m + k] = hn;
+            ++it;
+            k_used = k + 1;
+            if (hn > 0) HIPCHK(launch_copy_scaled(V + (size_t)(k + 1) * N, w, 1.0 / hn, N, st));
+            for (int i = 0; i < k; ++i) {
+                double t = cs[i] * H[i * m + k] + sn[i] * H[(i + 1) * m + k];
+                H[(i + 1) * m + k] = -sn[i] * H[i * m + k] + cs[i] * H[(i + 1) * m + k];
+                H[i * m + k] = t;
+            }
+            double den = std::hypot(H[k * m + k], H[(k + 1) * m + k]);
+            if (!(den > 0)) return PSW_EBREAKDOWN;
+            cs[k] = H[k * m + k] / den;
+            sn[k] = H[(k + 1) * m + k] / den;
+            H[k * m + k] = den;
+            H[(k + 1) * m + k] = 0.0;
+            g[k + 1] = -sn[k] * g[k];
+            g[k] = cs[k] * g[k];
+            rel = std::fabs(g[k + 1]) / nf;
+            if (rel <= rtol || hn == 0.0) break;
+        }
+        for (int i = k_used - 1; i >= 0; --i) {
+            double acc = g[i];
+            for (int j = i + 1; j < k_used; ++j) acc -= H[i * m + j] * y[j];
+            y[i] = acc / H[i * m + i];
+        }
+        HIPCHK(hipMemcpyAsync(hd + 64, y.data(), sizeof(double) * k_used, hipMemcpyHostToDevice, st));
+        HIPCHK(launch_multi_axpy(x, Z, hd + 64, k_used, N, true, st));
+        if (rel <= rtol) {
+            conv = true;
+            break;
+        }
+    }
+    HIPCHK(launch_residual(P->dim, P->n, d, f, x, r, st));
+    double nr;
+    if ((ps = host_norm(P, r, &nr, st))) return ps;
+    if (info) {
+        info->iters = it;
+        info->relres = nr / nf;
+        info->converged = conv && nr / nf <= rtol * 10;
+    }
+    return conv ? PSW_OK : PSW_ENOCONV;
+}
+
+} // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char *psw_status_string(psw_status st) {
+    switch (st) {
+    case PSW_OK: return "ok";
+    case PSW_EINVAL: return "invalid argument";
+    case PSW_ENOMEM: return "out of memory";
+    case PSW_EDEVICE: return "HIP error";
+    case PSW_ENOCONV: return "not converged";
+    case PSW_EBREAKDOWN: return "breakdown";
+    case PSW_EPIVOT: return "non-positive ILU pivot";
+    case PSW_EBUSY: return "admission refused";
+    case PSW_ENOTSUP: return "not supported";
+    case PSW_ESTATE: return "call out of order";
+    }
+    return "unknown status";
+}
+
+psw_status psw_problem_create(int dim, const int64_t n[3], int stencil, psw_problem **out) {
+    if (!out || !n) return PSW_EINVAL;
+    *out = nullptr;
+    if (dim < 2 || dim > 3) return dim == 1 ? PSW_ENOTSUP : PSW_EINVAL;
+    if (stencil != 2 * dim + 1) return PSW_EINVAL;
+    int64_t N = 1;
+    for (int a = 0; a < dim; ++a) {
+        if (n[a] < 1 || n[a] > (int64_t)1 << 30) return PSW_EINVAL;
+        N *= n[a];
+    }
+    if (N > ((int64_t)1 << 40)) return PSW_EINVAL;
+    psw_problem *P = new (std::nothrow) psw_problem();
+    if (!P) return PSW_ENOMEM;
+    if (hipGetDevice(&P->device) != hipSuccess) {
+        delete P;
+        return PSW_EDEVICE;
+    }
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, P->device) == hipSuccess && lds > 0)
+        P->lds_limit = (size_t)lds;
+    P->dim = dim;
+    for (int a = 0; a < 3; ++a) P->n[a] = a < dim ? (int)n[a] : 1;
+    P->N = N;
+    *out = P;
+    return PSW_OK;
+}
+
+psw_status psw_problem_destroy(psw_problem *P) {
+    if (!P) return PSW_EINVAL;
+    DeviceGuard dg(P->device);
+    (void)hipDeviceSynchronize();
+    delete P;
+    return PSW_OK;
+}
+
+static void invalidate(psw_problem *P) {
+    P->pc[0].ready = false;
+    P->pc[1].ready = false;
+}
+
+psw_status psw_set_diagonals(psw_problem *P, const double *const diag[], int on_device, psw_prec prec, void *stream) {
+    if (!P || !diag || prec < PSW_F64 || prec > PSW_BF16) return PSW_EINVAL;
+    DeviceGuard dg(P->device);
+    hipStream_t st = (hipStream_t)stream;
+    size_t b = sizeof(double) * (size_t)P->N;
+    for (int k = 0; k < 2 * P->dim + 1; ++k) {
+        if (!diag[k]) return PSW_EINVAL;
+        if (!P->diag[k].ensure(b)) return PSW_ENOMEM;
+        HIPCHK(hipMemcpyAsync(P->diag[k].p, diag[k], b, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+    }
+    if (!on_device) HIPCHK(hipStreamSynchronize(st));
+    P->prec = prec;
+    P->has_diag = true;
+    invalidate(P);
+    return PSW_OK;
+}
+
+psw_status psw_assemble_diffusion(psw_problem *P, const double *const alpha[], double beta, psw_prec prec,
+                                  void *stream) {
+    if (!P || !alpha || prec < PSW_F64 || prec > PSW_BF16 || !(beta >= 0.0)) return PSW_EINVAL;
+    DeviceGuard dg(P->device);
+    hipStream_t st = (hipStream_t)stream;
+    size_t b = sizeof(double) * (size_t)P->N;
+    double *out[7] = {};
+    for (int k = 0; k < 2 * P->dim + 1; ++k) {
+        if (!P->diag[k].ensure(b)) return PSW_ENOMEM;
+        out[k] = P->diag[k].as<double>();
+    }
+    for (int a = 0; a < P->dim; ++a)
+        if (!alpha[a]) return PSW_EINVAL;
+    HIPCHK(launch_assemble(P->dim, P->n, alpha, beta, out, st));
+    P->prec = prec;
+    P->has_diag = true;
+    invalidate(P);
+    return PSW_OK;
+}
+
+psw_status psw_get_diagonal(psw_problem *P, int k, double *out, void *stream) {
+    if (!P || !out || k < 0 || k > 2 * P->dim) return PSW_EINVAL;
+    if (!P->has_diag) return PSW_ESTATE;
+    DeviceGuard dg(P->device);
+    HIPCHK(hipMemcpyAsync(out, P->diag[k].p, sizeof(double) * P->N, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return PSW_OK;
+}
+
+psw_status psw_set_relaxation(psw_problem *P, const double *omega, int count) {
+    if (!P || !omega) return PSW_EINVAL;
+    int nc = 1 << P->dim;
+    if (count != 1 && count != nc) return PSW_EINVAL;
+    for (int i = 0; i < count; ++i)
+        if (!(omega[i] > 0.0 && omega[i] < 2.0)) return PSW_EINVAL;
+    for (int i = 0; i < 8; ++i) P->omega[i] = omega[count == 1 ? 0 : (i < nc ? i : 0)];
+    invalidate(P);
+    return PSW_OK;
+}
+
+psw_status psw_set_decomposition(psw_problem *P, const int p[3], int overlap, int phase) {
+    if (!P || !p || overlap < 2 || (phase != 0 && phase != 1)) return PSW_EINVAL;
+    int pp[3] = {1, 1, 1};
+    for (int a = 0; a < P->dim; ++a) {
+        pp[a] = p[a];
+        if (pp[a] < 1 || pp[a] > P->n[a]) return PSW_EINVAL;
+        if (P->n[a] / pp[a] < 2) return PSW_EINVAL; // every tile at least 2 points long
+    }
+    DeviceGuard dg(P->device);
+    std::vector<int> lo[3], len[3];
+    for (int a = 0; a < 3; ++a) partition(P->n[a], pp[a], lo[a], len[a]);
+    std::vector<TileDesc> T;
+    int cmax = 1, l1max = 1, l2max = 1;
+    for (int t = 0; t < pp[2]; ++t)
+        for (int s = 0; s < pp[1]; ++s)
+            for (int r = 0; r < pp[0]; ++r) {
+                TileDesc d{};
+                int c[3] = {r, s, t};
+                for (int a = 0; a < 3; ++a) {
+                    d.lo[a] = lo[a][c[a]];
+                    d.len[a] = len[a][c[a]];
+                    d.par[a] = c[a] & 1;
+                }
+                cmax = std::max(cmax, d.len[1] * d.len[2]);
+                l1max = std::max(l1max, d.len[1]);
+                l2max = std::max(l2max, d.len[2]);
+                T.push_back(d);
+            }
+    if (!P->tiles.ensure(sizeof(TileDesc) * T.size())) return PSW_ENOMEM;
+    HIPCHK(hipMemcpy(P->tiles.p, T.data(), sizeof(TileDesc) * T.size(), hipMemcpyHostToDevice));
+    P->ntiles = (int)T.size();
+    P->cmax = cmax;
+    P->l1max = l1max;
+    P->l2max = l2max;
+    for (int a = 0; a < 3; ++a) P->p[a] = pp[a];
+    P->overlap = overlap;
+    P->phase = phase;
+    P->has_decomp = true;
+    invalidate(P);
+    return PSW_OK;
+}
+
+psw_status psw_sweep(psw_problem *P, int64_t iteration, const double *u_in, const double *f, double *u_out,
+                     void *stream) {
+    if (!P || !u_in || !f || !u_out || iteration < 0 || u_in == u_out) return PSW_EINVAL;
+    if (!P->has_diag || !P->has_decomp) return PSW_ESTATE;
+    psw_status ps = check_lds(P, 8);
+    if (ps) return ps;
+    DeviceGuard dg(P->device);
+    int sig[3];
+    sched_sig(P, iteration, sig);
+    PassGeom g = geom(P, sig);
+    const double *d[7];
+    HIPCHK(launch_sweep_stationary(g, diag64(P, d), P->omega, u_in, f, u_out, (hipStream_t)stream));
+    return PSW_OK;
+}
+
+psw_status psw_precond_setup(psw_problem *P, psw_precond kind, void *stream) {
+    if (!P) return PSW_EINVAL;
+    DeviceGuard dg(P->device);
+    if (kind == PSW_NONE) return PSW_OK;
+    psw_status ps = ensure_work(P);
+    if (ps) return ps;
+    return precond_setup(P, kind, (hipStream_t)stream);
+}
+
+psw_status psw_precond_apply(psw_problem *P, psw_precond kind, int symmetric, const double *r, double *z,
+                             void *stream) {
+    if (!P || !r || !z || r == z || kind < PSW_SSOR || kind > PSW_NONE) return PSW_EINVAL;
+    if (!P->has_diag || !P->has_decomp) return PSW_ESTATE;
+    DeviceGuard dg(P->device);
+    return precond_apply(P, kind, symmetric ? 1 : 0, r, z, (hipStream_t)stream);
+}
+
+psw_status psw_precond_half(psw_problem *P, psw_precond kind, int which, const double *in, double *out,
+                            void *stream) {
+    if (!P || !in || !out || in == out || (kind != PSW_SSOR && kind != PSW_ILU0) || which < 0 || which > 3)
+        return PSW_EINVAL;
+    if (!P->has_diag || !P->has_decomp) return PSW_ESTATE;
+    DeviceGuard dg(P->device);
+    hipStream_t st = (hipStream_t)stream;
+    psw_status ps = precond_setup(P, kind, st);
+    if (ps) return ps;
+    if ((ps = ensure_work(P))) return ps;
+    double c = P->pc[kind].c;
+    bool scale = (which == 1 || which == 3);
+    if (which == 3) {
+        if ((ps = half(P, kind, 3, in, true, true, out, true, 1.0, st))) return ps;
+        HIPCHK(launch_copy_scaled(out, out, c, P->N, st));
+        return PSW_OK;
+    }
+    return half(P, kind, which, in, true, scale, out, true, which == 1 ? c : 1.0, st);
+}
+
+psw_status psw_ilu_pivots(psw_problem *P, double *piv, void *stream) {
+    if (!P || !piv) return PSW_EINVAL;
+    if (!P->has_diag || !P->has_decomp) return PSW_ESTATE;
+    DeviceGuard dg(P->device);
+    hipStream_t st = (hipStream_t)stream;
+    psw_status ps = ensure_work(P);
+    if (ps) return ps;
+    if ((ps = precond_setup(P, PSW_ILU0, st))) return ps;
+    HIPCHK(hipMemcpyAsync(piv, P->pc[PSW_ILU0].piv64.p, sizeof(double) * P->N, hipMemcpyDeviceToDevice, st));
+    return PSW_OK;
+}
+
+psw_status psw_spmv(psw_problem *P, const double *x, double *y, void *stream) {
+    if (!P || !x || !y || x == y) return PSW_EINVAL;
+    if (!P->has_diag) return PSW_ESTATE;
+    DeviceGuard dg(P->device);
+    const double *d[7];
+    HIPCHK(launch_spmv(P->dim, P->n, diag64(P, d), x, y, (hipStream_t)stream));
+    return PSW_OK;
+}
+
+psw_status psw_dot(psw_problem *P, const double *x, const double *y, double *out, void *stream) {
+    if (!P || !x || !y || !out) return PSW_EINVAL;
+    DeviceGuard dg(P->device);
+    hipStream_t st = (hipStream_t)stream;
+    psw_status ps = ensure_work(P);
+    if (ps) return ps;
+    double *s = P->scal.as<double>();
+    HIPCHK(launch_dot(x, y, P->N, P->partials.as<double>(), s + 11, st));
+    HIPCHK(hipMemcpyAsync(out, s + 11, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return PSW_OK;
+}
+
+psw_status psw_solve(psw_problem *P, psw_method method, psw_precond precond, double rtol, int64_t maxit, int restart,
+                     const double *f, double *u, psw_info *info, void *stream) {
+    if (!P || !f || !u || f == u || !(rtol > 0.0) || maxit < 1) return PSW_EINVAL;
+    if (precond < PSW_SSOR || precond > PSW_NONE) return PSW_EINVAL;
+    if (!P->has_diag || !P->has_decomp) return PSW_ESTATE;
+    DeviceGuard dg(P->device);
+    hipStream_t st = (hipStream_t)stream;
+    double t0 = now_ms();
+    psw_info loc{};
+    psw_status ps;
+    switch (method) {
+    case PSW_SOR_STATIONARY: ps = solve_stationary(P, rtol, maxit, f, u, &loc, st); break;
+    case PSW_CG: ps = solve_cg(P, precond, rtol, maxit, f, u, &loc, st); break;
+    case PSW_FGMRES: ps = solve_fgmres(P, precond, rtol, maxit, restart, f, u, &loc, st); break;
+    default: return PSW_EINVAL;
+    }
+    (void)hipStreamSynchronize(st);
+    loc.t_total_ms = now_ms() - t0;
+    loc.status = ps;
+    if (info) *info = loc;
+    return ps;
+}
+
+psw_status psw_batch_solve(int count, psw_problem *const *probs, const double *const *f, double *const *u,
+                           psw_method method, psw_precond precond, double rtol, int64_t maxit, psw_info *infos,
+                           void *stream) {
+    if (count < 0 || (count > 0 && (!probs || !f || !u))) return PSW_EINVAL;
+    psw_status worst = PSW_OK;
+    for (int i = 0; i < count; ++i) {
+        psw_info inf{};
+        psw_status s = psw_solve(probs[i], method, precond, rtol, maxit, 30, f[i], u[i], &inf, stream);
+        if (infos) infos[i] = inf;
+        if (s != PSW_OK && worst == PSW_OK) worst = s;
+    }
+    return worst;
+}
+
+} // extern "C"

@@ -1,0 +1,94 @@
+// psw_internal.h -- types shared by the HIP kernels and the host runtime of
+// libpsweep.so.  Not part of the public ABI (include/psweep.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace psw {
+
+// One subdomain (a "tile"): lower corner, extent and coordinate parity per
+// axis.  Unused axes have lo = 0, len = 1, par = 0.
+struct TileDesc {
+    int lo[3];
+    int len[3];
+    int par[3];
+};
+
+// Storage precisions of the diagonals used by the preconditioner sweeps.
+enum class Store { F64 = 0, F32 = 1, BF16 = 2 };
+
+// Geometry of one sweep pass: grid, tile table and the base direction of the
+// pass (the direction of tile (0,0,0); the sign on axis a flips for odd tile
+// coordinate a, so neighbouring tiles sweep in opposite directions).
+struct PassGeom {
+    int dim;
+    int n[3];
+    int sig[3];
+    int ntiles;
+    const TileDesc *tiles;
+    int cmax;  // largest tile cross-section (len1*len2)
+    int l1max; // largest len1
+    int l2max; // largest len2
+};
+
+// Kernel launchers (defined in psw_kernels.hip).  Every launcher returns a
+// hipError_t and launches on `st`.
+
+// Stationary decomposed SOR sweep, FP64 (start-coupled, per-corner omega).
+hipError_t launch_sweep_stationary(const PassGeom &g, const double *const *diag, const double *omega8,
+                                   const double *uold, const double *f, double *out, hipStream_t st);
+
+// Preconditioner half-sweep, start-coupled: out = cscale * (Piv - N)^-1 (in .* (scale_by_piv ? Piv : 1)).
+// in/out element types follow `in_f64`/`out_f64`; arithmetic in FP64 for Store::F64, else FP32.
+hipError_t launch_half_start(const PassGeom &g, Store s, const void *const *diag, const void *piv,
+                             const void *in, bool in_f64, bool scale_by_piv, void *out, bool out_f64,
+                             double cscale, hipStream_t st);
+
+// Transposed half-sweep, end-coupled: interior phase, then the coupled end
+// faces (2D: face chains then cross points; 3D: faces, edges, corners).
+// out = (Piv - N)^-T (in .* (scale_by_piv ? Piv : 1)) where N are the upstream
+// couplings of the direction map -sig (the solve itself runs along sig).
+hipError_t launch_half_end(const PassGeom &g, Store s, const void *const *diag, const void *piv,
+                           const void *in, bool in_f64, bool scale_by_piv, void *out, bool out_f64,
+                           hipStream_t st);
+
+// ILU(0) pivots of the decomposed factorisation, FP64.
+hipError_t launch_ilu_pivots(const PassGeom &g, const double *const *diag, double *piv, int *bad,
+                             hipStream_t st);
+
+// Vector kernels (FP64, natural layout).
+hipError_t launch_assemble(int dim, const int n[3], const double *const *alpha, double beta,
+                           double *const *diag, hipStream_t st);
+hipError_t launch_spmv(int dim, const int n[3], const double *const *diag, const double *x, double *y,
+                       hipStream_t st);
+hipError_t launch_convert(const double *src, void *dst, Store s, int64_t N, double scale, hipStream_t st);
+hipError_t launch_scale_add(double *z, const double *a, double ca, const void *b, bool b_f64, double cb,
+                            int64_t N, hipStream_t st);
+
+// Deterministic reductions: partial sums per block in fixed order, then one
+// block sums the partials in fixed order.  `partials` holds kRedBlocks doubles.
+constexpr int kRedBlocks = 1024;
+constexpr int kRedThreads = 256;
+hipError_t launch_dot(const double *x, const double *y, int64_t N, double *partials, double *out,
+                      hipStream_t st);
+
+// CG helpers with device-resident scalars.
+//   x += alpha p ; r -= alpha q ; alpha = s[0]/s[1]; partial dot r.r -> out
+hipError_t launch_cg_update_xr(double *x, double *r, const double *p, const double *q, const double *num,
+                               const double *den, int64_t N, double *partials, double *rr, hipStream_t st);
+//   p = z + beta p ; beta = num/den
+hipError_t launch_cg_update_p(double *p, const double *z, const double *num, const double *den, int64_t N,
+                              hipStream_t st);
+hipError_t launch_axpy(double *y, double a, const double *x, int64_t N, hipStream_t st);
+hipError_t launch_copy_scaled(double *y, const double *x, double a, int64_t N, hipStream_t st);
+hipError_t launch_residual(int dim, const int n[3], const double *const *diag, const double *f,
+                           const double *x, double *r, hipStream_t st);
+// GMRES: y = sum_j c[j] * V[j] (c on device), V rows of length N.
+hipError_t launch_multi_axpy(double *y, const double *V, const double *c, int k, int64_t N, bool accumulate,
+                             hipStream_t st);
+// GMRES: out[j] = V[j] . w for j < k (deterministic), using partials of k*kRedBlocks.
+hipError_t launch_multi_dot(const double *V, const double *w, int k, int64_t N, double *partials, double *out,
+                            hipStream_t st);
+
+} // namespace psw

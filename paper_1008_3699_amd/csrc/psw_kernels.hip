@@ -1,0 +1,913 @@
+// psw_kernels.hip -- HIP kernels of libpsweep.so for gfx950.
+//
+// Decomposed sweeps (Tavakoli, Secs. 2-5).  One workgroup owns one subdomain
+// ("tile").  Inside a tile the sweep advances one hyperplane level
+// t = l0 + l1 + l2 at a time (the frontal strategy of Sec. 2, fig. swp2d),
+// in tile-local coordinates l in which the tile's sweep runs towards +l.
+// Threads own cross-section positions (l1, l2); the new value of a point is
+// published in LDS where the points of the next level read it.
+//
+// Start-coupled passes (the paper's sweep, forward and backward
+// preconditioner half-sweeps) solve the coupled blocks at the tile's start
+// faces inside the tile: the partner points across a start face are
+// recomputed redundantly, 2x2 on faces (eq. 1d:sorc, eq. 2d:sor2b2), 4x4 at
+// 2D cross points and along 3D edges (eq. 2d:sor4b4), 8x8 at 3D corners
+// (Sec. 4), so a tile needs only the old iterate and a 2-deep halo.
+//
+// End-coupled passes (the transpose of a start-coupled operator, used by the
+// symmetric form of the preconditioner) couple at the tiles' END faces.
+// They run an uncoupled interior pass first and then re-solve the coupled
+// points in order of block size: faces, then edges (3D), then corners; each
+// group reads only results of the earlier groups.
+#include "psw_internal.h"
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace psw {
+
+// ------------------------------------------------------------------ loads
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+template <typename T, typename S> __device__ __forceinline__ T ldv(const S *p, int64_t i);
+template <> __device__ __forceinline__ double ldv<double, double>(const double *p, int64_t i) { return p[i]; }
+template <> __device__ __forceinline__ float ldv<float, float>(const float *p, int64_t i) { return p[i]; }
+template <> __device__ __forceinline__ float ldv<float, double>(const double *p, int64_t i) { return (float)p[i]; }
+template <> __device__ __forceinline__ double ldv<double, float>(const float *p, int64_t i) { return (double)p[i]; }
+template <> __device__ __forceinline__ float ldv<float, uint16_t>(const uint16_t *p, int64_t i) { return bf16_to_f32(p[i]); }
+
+// diagonal index of the coupling of a point towards its neighbour on axis a,
+// side s (-1: W/S/B, +1: E/N/F)
+__device__ __forceinline__ int dk(int a, int s) { return s < 0 ? 1 + 2 * a : 2 + 2 * a; }
+
+__device__ __forceinline__ int64_t lin(const int n[3], const int g[3]) {
+    return (int64_t)g[0] + (int64_t)n[0] * ((int64_t)g[1] + (int64_t)n[1] * (int64_t)g[2]);
+}
+
+struct TileFrame {
+    int d[3];    // sweep direction of this tile in this pass
+    int len[3];  // extent
+    int base[3]; // global coordinate of local l = 0
+    int lo[3];
+    bool start_cpl[3]; // neighbour exists across the start side
+    bool end_cpl[3];   // neighbour exists across the end side
+};
+
+template <int DIM>
+__device__ __forceinline__ TileFrame make_frame(const PassGeom &g, const TileDesc &td) {
+    TileFrame f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        f.d[a] = (a < DIM) ? g.sig[a] * (td.par[a] ? -1 : 1) : 1;
+        f.len[a] = td.len[a];
+        f.lo[a] = td.lo[a];
+        f.base[a] = f.d[a] > 0 ? td.lo[a] : td.lo[a] + td.len[a] - 1;
+        bool low = td.lo[a] > 0, high = td.lo[a] + td.len[a] < g.n[a];
+        f.start_cpl[a] = (a < DIM) && (f.d[a] > 0 ? low : high);
+        f.end_cpl[a] = (a < DIM) && (f.d[a] > 0 ? high : low);
+    }
+    return f;
+}
+
+// small dense solve without pivoting, NB x NB, rows/cols outside the block
+// are identity and decoupled
+template <typename T, int NB>
+__device__ __forceinline__ void ge_solve(T (&M)[NB][NB], T (&R)[NB]) {
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        T inv = T(1) / M[k][k];
+#pragma unroll
+        for (int i = k + 1; i < NB; ++i) {
+            T l = M[i][k] * inv;
+#pragma unroll
+            for (int j = k + 1; j < NB; ++j) M[i][j] -= l * M[k][j];
+            R[i] -= l * R[k];
+        }
+    }
+#pragma unroll
+    for (int i = NB - 1; i >= 0; --i) {
+        T acc = R[i];
+#pragma unroll
+        for (int j = i + 1; j < NB; ++j) acc -= M[i][j] * R[j];
+        R[i] = acc / M[i][i];
+    }
+}
+
+// LDS slot rings: one double-buffered slot per (block type B, position).
+// B is the set of start-face axes a point was shifted across (0 = own point).
+template <typename T> struct Rings {
+    T *own, *xp, *yp, *zp, *xyp, *xzp, *yzp;
+    int cmax, l1max, l2max;
+    __device__ __forceinline__ T *slot(int B, int buf, int l1, int l2, int L1) const {
+        switch (B) {
+        case 0: return own + buf * cmax + l1 + L1 * l2;
+        case 1: return xp + buf * cmax + l1 + L1 * l2;
+        case 2: return yp + buf * l2max + l2;
+        case 4: return zp + buf * l1max + l1;
+        case 3: return xyp + buf * l2max + l2;
+        case 5: return xzp + buf * l1max + l1;
+        default: return yzp + buf;
+        }
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ Rings<T> make_rings(void *smem, const PassGeom &g) {
+    Rings<T> r;
+    T *p = reinterpret_cast<T *>(smem);
+    r.cmax = g.cmax; r.l1max = g.l1max; r.l2max = g.l2max;
+    r.own = p; p += 2 * g.cmax;
+    r.xp = p; p += 2 * g.cmax;
+    r.yp = p; p += 2 * g.l2max;
+    r.zp = p; p += 2 * g.l1max;
+    r.xyp = p; p += 2 * g.l2max;
+    r.xzp = p; p += 2 * g.l1max;
+    r.yzp = p;
+    return r;
+}
+
+size_t rings_bytes(const PassGeom &g, size_t elem) {
+    return elem * (size_t)(4 * g.cmax + 4 * g.l2max + 4 * g.l1max + 2);
+}
+
+// ------------------------------------------------------------------ start-coupled sweep
+// STAT: stationary SOR (D = a^P, per-corner omega, old iterate uold).
+// else: preconditioner half-sweep (D = piv, omega = 1, no old iterate,
+//       rhs = in .* (scale_by_piv ? piv : 1), out = cscale * x).
+template <typename S, typename TIN, typename TOUT> struct StartArgs {
+    PassGeom g;
+    const S *diag[7];
+    const S *piv;
+    double omega[8];
+    const double *uold;
+    const TIN *in;
+    int scale_by_piv;
+    TOUT *out;
+    double cscale;
+};
+
+template <int DIM, typename T, typename S, typename TIN, typename TOUT, bool STAT>
+__global__ void __launch_bounds__(256) k_sweep_start(StartArgs<S, TIN, TOUT> A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const PassGeom &g = A.g;
+    const TileDesc td = g.tiles[blockIdx.x];
+    const TileFrame F = make_frame<DIM>(g, td);
+    Rings<T> rg = make_rings<T>(smem, g);
+    const int L1 = F.len[1], L2 = F.len[2];
+    const int C = L1 * L2;
+    const int nlev = F.len[0] + F.len[1] + F.len[2] - 2;
+    constexpr int NB = 1 << DIM;
+
+    for (int t = 0; t < nlev; ++t) {
+        const int cur = t & 1, prv = cur ^ 1;
+        for (int c = threadIdx.x; c < C; c += blockDim.x) {
+            const int l1 = c % L1, l2 = c / L1, l0 = t - l1 - l2;
+            if (l0 < 0 || l0 >= F.len[0]) continue;
+            const int l[3] = {l0, l1, l2};
+            int gp[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) gp[a] = F.base[a] + F.d[a] * l[a];
+            int Am = 0;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a)
+                if (l[a] == 0 && F.start_cpl[a]) Am |= 1 << a;
+
+            if (Am == 0) {
+                // interior point: single update
+                const int64_t P = lin(g.n, gp);
+                int corner = 0;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) corner |= (F.d[a] < 0) << a;
+                T w = STAT ? (T)A.omega[corner] : T(1);
+                T D = STAT ? ldv<T>(A.diag[0], P) : ldv<T>(A.piv, P);
+                T sc = w / D;
+                T acc = ldv<T>(A.in, P);
+                if (!STAT && A.scale_by_piv) acc *= D;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    const int su = -F.d[a];
+                    if (l[a] > 0) {
+                        T coef = ldv<T>(A.diag[dk(a, su)], P);
+                        T v = *rg.slot(0, prv, l1 - (a == 1), l2 - (a == 2), L1);
+                        acc += coef * v;
+                    }
+                    if (STAT) {
+                        int q[3] = {gp[0], gp[1], gp[2]};
+                        q[a] += F.d[a];
+                        if (q[a] >= 0 && q[a] < g.n[a]) acc += ldv<T>(A.diag[dk(a, F.d[a])], P) * ldv<T>(A.uold, lin(g.n, q));
+                    }
+                }
+                T x = STAT ? (T(1) - w) * ldv<T>(A.uold, P) + sc * acc : sc * acc;
+                *rg.slot(0, cur, l1, l2, L1) = x;
+                A.out[P] = (TOUT)((T)A.cscale * x);
+            } else {
+                // coupled block: own point plus partners across the coupled start faces
+                T M[NB][NB], R[NB];
+#pragma unroll
+                for (int i = 0; i < NB; ++i) {
+                    R[i] = T(0);
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) M[i][j] = (i == j) ? T(1) : T(0);
+                }
+#pragma unroll
+                for (int B = 0; B < NB; ++B) {
+                    if (B & ~Am) continue;
+                    int gq[3], dq[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        bool fl = (B >> a) & 1;
+                        gq[a] = gp[a] - (fl ? F.d[a] : 0);
+                        dq[a] = fl ? -F.d[a] : F.d[a];
+                    }
+                    const int64_t Q = lin(g.n, gq);
+                    int corner = 0;
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) corner |= (dq[a] < 0) << a;
+                    T w = STAT ? (T)A.omega[corner] : T(1);
+                    T D = STAT ? ldv<T>(A.diag[0], Q) : ldv<T>(A.piv, Q);
+                    T sc = w / D;
+                    T acc = ldv<T>(A.in, Q);
+                    if (!STAT && A.scale_by_piv) acc *= D;
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) {
+                        const int su = -dq[a];
+                        int q[3] = {gq[0], gq[1], gq[2]};
+                        q[a] += su;
+                        if (q[a] >= 0 && q[a] < g.n[a]) {
+                            T coef = ldv<T>(A.diag[dk(a, su)], Q);
+                            if ((Am >> a) & 1) {
+                                M[B][B ^ (1 << a)] -= sc * coef;
+                            } else {
+                                T v = *rg.slot(B, prv, l1 - (a == 1), l2 - (a == 2), L1);
+                                acc += coef * v;
+                            }
+                        }
+                        if (STAT) {
+                            int r[3] = {gq[0], gq[1], gq[2]};
+                            r[a] += dq[a];
+                            if (r[a] >= 0 && r[a] < g.n[a]) acc += ldv<T>(A.diag[dk(a, dq[a])], Q) * ldv<T>(A.uold, lin(g.n, r));
+                        }
+                    }
+                    R[B] = STAT ? (T(1) - w) * ldv<T>(A.uold, Q) + sc * acc : sc * acc;
+                }
+                if ((Am & (Am - 1)) == 0) {
+                    // 2x2 (eq. 1d:sorc / eq. 2d:sor2b2)
+                    const int b = Am;
+                    T det = T(1) - M[0][b] * M[b][0];
+                    T x0 = (R[0] - M[0][b] * R[b]) / det;
+                    T x1 = (R[b] - M[b][0] * R[0]) / det;
+                    R[0] = x0;
+                    R[b] = x1;
+                } else {
+                    ge_solve<T, NB>(M, R);
+                }
+                const int64_t P = lin(g.n, gp);
+                A.out[P] = (TOUT)((T)A.cscale * R[0]);
+#pragma unroll
+                for (int B = 0; B < NB - 1; ++B) {
+                    if (B & ~Am) continue;
+                    *rg.slot(B, cur, l1, l2, L1) = R[B];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ end-coupled (transposed) sweep
+template <typename S, typename TIN, typename TOUT> struct EndArgs {
+    PassGeom g;
+    const S *diag[7];
+    const S *piv;
+    const TIN *in;
+    int scale_by_piv;
+    TOUT *out;
+};
+
+// Interior phase: x_P = (b_P + sum_{R upstream of P in its tile} a_{R->P} x_R) / Piv_P,
+// with no coupling across any face.  Points on coupled end faces get a
+// provisional value that the face/edge/corner passes overwrite.
+template <int DIM, typename T, typename S, typename TIN, typename TOUT>
+__global__ void __launch_bounds__(256) k_sweep_end_interior(EndArgs<S, TIN, TOUT> A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const PassGeom &g = A.g;
+    const TileDesc td = g.tiles[blockIdx.x];
+    const TileFrame F = make_frame<DIM>(g, td);
+    Rings<T> rg = make_rings<T>(smem, g);
+    const int L1 = F.len[1], L2 = F.len[2];
+    const int C = L1 * L2;
+    const int nlev = F.len[0] + F.len[1] + F.len[2] - 2;
+    for (int t = 0; t < nlev; ++t) {
+        const int cur = t & 1, prv = cur ^ 1;
+        for (int c = threadIdx.x; c < C; c += blockDim.x) {
+            const int l1 = c % L1, l2 = c / L1, l0 = t - l1 - l2;
+            if (l0 < 0 || l0 >= F.len[0]) continue;
+            const int l[3] = {l0, l1, l2};
+            int gp[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) gp[a] = F.base[a] + F.d[a] * l[a];
+            const int64_t P = lin(g.n, gp);
+            T D = ldv<T>(A.piv, P);
+            T acc = ldv<T>(A.in, P);
+            if (A.scale_by_piv) acc *= D;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                if (l[a] > 0) {
+                    int r[3] = {gp[0], gp[1], gp[2]};
+                    r[a] -= F.d[a];
+                    T coef = ldv<T>(A.diag[dk(a, F.d[a])], lin(g.n, r));
+                    acc += coef * *rg.slot(0, prv, l1 - (a == 1), l2 - (a == 2), L1);
+                }
+            }
+            T x = acc / D;
+            *rg.slot(0, cur, l1, l2, L1) = x;
+            A.out[P] = (TOUT)x;
+        }
+        __syncthreads();
+    }
+}
+
+// One coupled end block.  P (global gp, tile-local l) lies on the end faces
+// of the axes in Am of a tile sweeping along d.  Block points Q_B = P + sum
+// over a in B of d_a e_a; each has its own tile's direction (d flipped on B).
+// Row of Q: Piv_Q x_Q - sum_{a in Am} a_{Q_{B^a}->Q} x_{Q_{B^a}}
+//           - sum_a [R_a is a dependency] a_{R_a->Q} x_{R_a} = b_Q,
+// R_a = Q - dq_a e_a (upstream inside Q's tile); values of R_a come from x.
+template <int DIM, typename T, typename S, typename TIN, typename TOUT>
+__device__ void end_block(const EndArgs<S, TIN, TOUT> &A, const int gp[3], const int l[3], const int d[3],
+                          int Am) {
+    constexpr int NB = 1 << DIM;
+    const PassGeom &g = A.g;
+    T M[NB][NB], R[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        R[i] = T(0);
+#pragma unroll
+        for (int j = 0; j < NB; ++j) M[i][j] = (i == j) ? T(1) : T(0);
+    }
+    int64_t idx[NB];
+#pragma unroll
+    for (int B = 0; B < NB; ++B) {
+        idx[B] = 0;
+        if (B & ~Am) continue;
+        int gq[3], dq[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            bool fl = (B >> a) & 1;
+            gq[a] = gp[a] + (fl ? d[a] : 0);
+            dq[a] = fl ? -d[a] : d[a];
+        }
+        const int64_t Q = lin(g.n, gq);
+        idx[B] = Q;
+        T D = ldv<T>(A.piv, Q);
+        T acc = ldv<T>(A.in, Q);
+        if (A.scale_by_piv) acc *= D;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            if ((Am >> a) & 1) {
+                // block mate across the face: Q_{B^a} = Q + s e_a
+                int s = ((B >> a) & 1) ? -d[a] : d[a];
+                int q[3] = {gq[0], gq[1], gq[2]};
+                q[a] += s;
+                T coef = ldv<T>(A.diag[dk(a, -s)], lin(g.n, q));
+                M[B][B ^ (1 << a)] -= coef / D;
+            }
+            if (((Am >> a) & 1) || l[a] > 0) {
+                int r[3] = {gq[0], gq[1], gq[2]};
+                r[a] -= dq[a];
+                const int64_t Ri = lin(g.n, r);
+                T coef = ldv<T>(A.diag[dk(a, dq[a])], Ri);
+                acc += coef * ldv<T>(A.out, Ri);
+            }
+        }
+        R[B] = acc / D;
+    }
+    if ((Am & (Am - 1)) == 0) {
+        const int b = Am;
+        T det = T(1) - M[0][b] * M[b][0];
+        T x0 = (R[0] - M[0][b] * R[b]) / det;
+        T x1 = (R[b] - M[b][0] * R[0]) / det;
+        R[0] = x0;
+        R[b] = x1;
+    } else {
+        ge_solve<T, NB>(M, R);
+    }
+#pragma unroll
+    for (int B = 0; B < NB; ++B)
+        if (!(B & ~Am)) A.out[idx[B]] = (TOUT)R[B];
+}
+
+// Faces.  The face between tiles r and r+1 on axis a is coupled in this pass
+// when tile r sweeps towards it (d_a = +1); tile r owns it.  Positions on the
+// face that also lie on another coupled end face (edges) are left to the
+// edge / corner passes.  2D: one thread walks the chain; 3D: one workgroup
+// advances a wavefront over the face.
+template <int DIM, typename T, typename S, typename TIN, typename TOUT>
+__global__ void __launch_bounds__(256) k_end_faces(EndArgs<S, TIN, TOUT> A) {
+    const PassGeom &g = A.g;
+    const int tile = blockIdx.x / DIM, a = blockIdx.x % DIM;
+    const TileDesc td = g.tiles[tile];
+    const TileFrame F = make_frame<DIM>(g, td);
+    if (!(F.d[a] > 0 && F.end_cpl[a])) return;
+    // the two other axes (b, c); c unused in 2D
+    const int b = (a + 1) % DIM, c = DIM == 3 ? (a + 2) % DIM : 2;
+    const int Lb = F.len[b], Lc = (DIM == 3) ? F.len[c] : 1;
+    const int nb = (F.end_cpl[b] ? Lb - 1 : Lb), nc = (DIM == 3 && F.end_cpl[c]) ? Lc - 1 : Lc;
+    const int nlev = nb + nc - 1;
+    for (int t = 0; t < nlev; ++t) {
+        for (int k = threadIdx.x; k < nc; k += blockDim.x) {
+            const int lc = k, lb = t - k;
+            if (lb < 0 || lb >= nb) continue;
+            int l[3] = {0, 0, 0};
+            l[a] = F.len[a] - 1;
+            l[b] = lb;
+            if (DIM == 3) l[c] = lc;
+            int gp[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) gp[q] = F.base[q] + F.d[q] * l[q];
+            end_block<DIM, T, S, TIN, TOUT>(A, gp, l, F.d, 1 << a);
+        }
+        __syncthreads();
+    }
+}
+
+// Edges (3D): the edge along axis c where the end faces of a and b meet; owned
+// by the tile that sweeps towards both.  One thread walks the edge chain.
+template <typename T, typename S, typename TIN, typename TOUT>
+__global__ void k_end_edges(EndArgs<S, TIN, TOUT> A) {
+    const PassGeom &g = A.g;
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= g.ntiles * 3) return;
+    const int tile = id / 3, c = id % 3;
+    const int a = (c + 1) % 3, b = (c + 2) % 3;
+    const TileDesc td = g.tiles[tile];
+    const TileFrame F = make_frame<3>(g, td);
+    if (!(F.d[a] > 0 && F.end_cpl[a] && F.d[b] > 0 && F.end_cpl[b])) return;
+    const int nc = F.end_cpl[c] ? F.len[c] - 1 : F.len[c];
+    for (int lc = 0; lc < nc; ++lc) {
+        int l[3];
+        l[a] = F.len[a] - 1;
+        l[b] = F.len[b] - 1;
+        l[c] = lc;
+        int gp[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) gp[q] = F.base[q] + F.d[q] * l[q];
+        end_block<3, T, S, TIN, TOUT>(A, gp, l, F.d, (1 << a) | (1 << b));
+    }
+}
+
+// Corners: where all DIM end faces are coupled; owned by the tile sweeping
+// towards +x, +y (+z).
+template <int DIM, typename T, typename S, typename TIN, typename TOUT>
+__global__ void k_end_corners(EndArgs<S, TIN, TOUT> A) {
+    const PassGeom &g = A.g;
+    const int tile = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tile >= g.ntiles) return;
+    const TileDesc td = g.tiles[tile];
+    const TileFrame F = make_frame<DIM>(g, td);
+    int Am = 0;
+    for (int a = 0; a < DIM; ++a) {
+        if (!(F.d[a] > 0 && F.end_cpl[a])) return;
+        Am |= 1 << a;
+    }
+    int l[3] = {0, 0, 0}, gp[3];
+    for (int a = 0; a < 3; ++a) {
+        l[a] = a < DIM ? F.len[a] - 1 : 0;
+        gp[a] = F.base[a] + F.d[a] * l[a];
+    }
+    end_block<DIM, T, S, TIN, TOUT>(A, gp, l, F.d, Am);
+}
+
+// ------------------------------------------------------------------ ILU(0) pivots
+struct PivArgs {
+    PassGeom g;
+    const double *diag[7];
+    double *piv;
+    int *bad;
+};
+
+template <int DIM>
+__global__ void __launch_bounds__(256) k_ilu_pivots(PivArgs A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const PassGeom &g = A.g;
+    const TileDesc td = g.tiles[blockIdx.x];
+    const TileFrame F = make_frame<DIM>(g, td);
+    Rings<double> rg = make_rings<double>(smem, g);
+    const int L1 = F.len[1], L2 = F.len[2];
+    const int C = L1 * L2;
+    const int nlev = F.len[0] + F.len[1] + F.len[2] - 2;
+    for (int t = 0; t < nlev; ++t) {
+        const int cur = t & 1, prv = cur ^ 1;
+        for (int c = threadIdx.x; c < C; c += blockDim.x) {
+            const int l1 = c % L1, l2 = c / L1, l0 = t - l1 - l2;
+            if (l0 < 0 || l0 >= F.len[0]) continue;
+            const int l[3] = {l0, l1, l2};
+            int gp[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) gp[a] = F.base[a] + F.d[a] * l[a];
+            const int64_t P = lin(g.n, gp);
+            double acc = A.diag[0][P];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                if (l[a] > 0) {
+                    const int su = -F.d[a];
+                    int r[3] = {gp[0], gp[1], gp[2]};
+                    r[a] += su;
+                    const int64_t Q = lin(g.n, r);
+                    double pq = *rg.slot(0, prv, l1 - (a == 1), l2 - (a == 2), L1);
+                    acc -= A.diag[dk(a, su)][P] * A.diag[dk(a, -su)][Q] / pq;
+                }
+            }
+            if (!(acc > 0.0)) atomicOr(A.bad, 1);
+            *rg.slot(0, cur, l1, l2, L1) = acc;
+            A.piv[P] = acc;
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+static int block_threads(const PassGeom &g) {
+    int t = ((g.cmax + 63) / 64) * 64;
+    return t < 64 ? 64 : (t > 256 ? 256 : t);
+}
+
+hipError_t launch_sweep_stationary(const PassGeom &g, const double *const *diag, const double *omega8,
+                                   const double *uold, const double *f, double *out, hipStream_t st) {
+    StartArgs<double, double, double> A{};
+    A.g = g;
+    for (int k = 0; k < 2 * g.dim + 1; ++k) A.diag[k] = diag[k];
+    A.piv = nullptr;
+    for (int k = 0; k < 8; ++k) A.omega[k] = omega8[k];
+    A.uold = uold;
+    A.in = f;
+    A.scale_by_piv = 0;
+    A.out = out;
+    A.cscale = 1.0;
+    size_t sm = rings_bytes(g, sizeof(double));
+    dim3 grid(g.ntiles), blk(block_threads(g));
+    if (g.dim == 2)
+        hipLaunchKernelGGL((k_sweep_start<2, double, double, double, double, true>), grid, blk, sm, st, A);
+    else
+        hipLaunchKernelGGL((k_sweep_start<3, double, double, double, double, true>), grid, blk, sm, st, A);
+    return hipGetLastError();
+}
+
+template <typename T, typename S, typename TIN, typename TOUT>
+static hipError_t start_impl(const PassGeom &g, const void *const *diag, const void *piv, const void *in,
+                             bool scale_by_piv, void *out, double cscale, hipStream_t st) {
+    StartArgs<S, TIN, TOUT> A{};
+    A.g = g;
+    for (int k = 0; k < 2 * g.dim + 1; ++k) A.diag[k] = (const S *)diag[k];
+    A.piv = (const S *)piv;
+    for (int k = 0; k < 8; ++k) A.omega[k] = 1.0;
+    A.uold = nullptr;
+    A.in = (const TIN *)in;
+    A.scale_by_piv = scale_by_piv ? 1 : 0;
+    A.out = (TOUT *)out;
+    A.cscale = cscale;
+    size_t sm = rings_bytes(g, sizeof(T));
+    dim3 grid(g.ntiles), blk(block_threads(g));
+    if (g.dim == 2)
+        hipLaunchKernelGGL((k_sweep_start<2, T, S, TIN, TOUT, false>), grid, blk, sm, st, A);
+    else
+        hipLaunchKernelGGL((k_sweep_start<3, T, S, TIN, TOUT, false>), grid, blk, sm, st, A);
+    return hipGetLastError();
+}
+
+template <typename T, typename S, typename TIN, typename TOUT>
+static hipError_t end_impl(const PassGeom &g, const void *const *diag, const void *piv, const void *in,
+                           bool scale_by_piv, void *out, hipStream_t st) {
+    EndArgs<S, TIN, TOUT> A{};
+    A.g = g;
+    for (int k = 0; k < 2 * g.dim + 1; ++k) A.diag[k] = (const S *)diag[k];
+    A.piv = (const S *)piv;
+    A.in = (const TIN *)in;
+    A.scale_by_piv = scale_by_piv ? 1 : 0;
+    A.out = (TOUT *)out;
+    size_t sm = rings_bytes(g, sizeof(T));
+    dim3 grid(g.ntiles), blk(block_threads(g));
+    if (g.dim == 2) {
+        hipLaunchKernelGGL((k_sweep_end_interior<2, T, S, TIN, TOUT>), grid, blk, sm, st, A);
+        hipLaunchKernelGGL((k_end_faces<2, T, S, TIN, TOUT>), dim3(g.ntiles * 2), dim3(64), 0, st, A);
+        hipLaunchKernelGGL((k_end_corners<2, T, S, TIN, TOUT>), dim3((g.ntiles + 63) / 64), dim3(64), 0, st, A);
+    } else {
+        hipLaunchKernelGGL((k_sweep_end_interior<3, T, S, TIN, TOUT>), grid, blk, sm, st, A);
+        hipLaunchKernelGGL((k_end_faces<3, T, S, TIN, TOUT>), dim3(g.ntiles * 3), dim3(64), 0, st, A);
+        hipLaunchKernelGGL((k_end_edges<T, S, TIN, TOUT>), dim3((g.ntiles * 3 + 63) / 64), dim3(64), 0, st, A);
+        hipLaunchKernelGGL((k_end_corners<3, T, S, TIN, TOUT>), dim3((g.ntiles + 63) / 64), dim3(64), 0, st, A);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_half_start(const PassGeom &g, Store s, const void *const *diag, const void *piv, const void *in,
+                             bool in_f64, bool scale_by_piv, void *out, bool out_f64, double cscale,
+                             hipStream_t st) {
+    if (s == Store::F64) {
+        if (!in_f64 || !out_f64) return hipErrorInvalidValue;
+        return start_impl<double, double, double, double>(g, diag, piv, in, scale_by_piv, out, cscale, st);
+    }
+    if (s == Store::F32) {
+        if (in_f64 && !out_f64) return start_impl<float, float, double, float>(g, diag, piv, in, scale_by_piv, out, cscale, st);
+        if (!in_f64 && out_f64) return start_impl<float, float, float, double>(g, diag, piv, in, scale_by_piv, out, cscale, st);
+        if (in_f64 && out_f64) return start_impl<float, float, double, double>(g, diag, piv, in, scale_by_piv, out, cscale, st);
+        return start_impl<float, float, float, float>(g, diag, piv, in, scale_by_piv, out, cscale, st);
+    }
+    if (in_f64 && !out_f64) return start_impl<float, uint16_t, double, float>(g, diag, piv, in, scale_by_piv, out, cscale, st);
+    if (!in_f64 && out_f64) return start_impl<float, uint16_t, float, double>(g, diag, piv, in, scale_by_piv, out, cscale, st);
+    if (in_f64 && out_f64) return start_impl<float, uint16_t, double, double>(g, diag, piv, in, scale_by_piv, out, cscale, st);
+    return start_impl<float, uint16_t, float, float>(g, diag, piv, in, scale_by_piv, out, cscale, st);
+}
+
+hipError_t launch_half_end(const PassGeom &g, Store s, const void *const *diag, const void *piv, const void *in,
+                           bool in_f64, bool scale_by_piv, void *out, bool out_f64, hipStream_t st) {
+    if (s == Store::F64) {
+        if (!in_f64 || !out_f64) return hipErrorInvalidValue;
+        return end_impl<double, double, double, double>(g, diag, piv, in, scale_by_piv, out, st);
+    }
+    if (s == Store::F32) {
+        if (in_f64 && !out_f64) return end_impl<float, float, double, float>(g, diag, piv, in, scale_by_piv, out, st);
+        if (!in_f64 && !out_f64) return end_impl<float, float, float, float>(g, diag, piv, in, scale_by_piv, out, st);
+        if (in_f64 && out_f64) return end_impl<float, float, double, double>(g, diag, piv, in, scale_by_piv, out, st);
+        return end_impl<float, float, float, double>(g, diag, piv, in, scale_by_piv, out, st);
+    }
+    if (in_f64 && !out_f64) return end_impl<float, uint16_t, double, float>(g, diag, piv, in, scale_by_piv, out, st);
+    if (!in_f64 && !out_f64) return end_impl<float, uint16_t, float, float>(g, diag, piv, in, scale_by_piv, out, st);
+    if (in_f64 && out_f64) return end_impl<float, uint16_t, double, double>(g, diag, piv, in, scale_by_piv, out, st);
+    return end_impl<float, uint16_t, float, double>(g, diag, piv, in, scale_by_piv, out, st);
+}
+
+hipError_t launch_ilu_pivots(const PassGeom &g, const double *const *diag, double *piv, int *bad, hipStream_t st) {
+    PivArgs A{};
+    A.g = g;
+    for (int k = 0; k < 2 * g.dim + 1; ++k) A.diag[k] = diag[k];
+    A.piv = piv;
+    A.bad = bad;
+    size_t sm = rings_bytes(g, sizeof(double));
+    dim3 grid(g.ntiles), blk(block_threads(g));
+    if (g.dim == 2)
+        hipLaunchKernelGGL(k_ilu_pivots<2>, grid, blk, sm, st, A);
+    else
+        hipLaunchKernelGGL(k_ilu_pivots<3>, grid, blk, sm, st, A);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ vector kernels (FP64)
+struct DiagPtrs {
+    const double *d[7];
+};
+struct DiagOut {
+    double *d[7];
+};
+
+__global__ void k_assemble(int dim, int n0, int n1, int n2, DiagPtrs al, double beta, DiagOut out) {
+    const int64_t N = (int64_t)n0 * n1 * n2;
+    const int64_t m0 = n0 + 2, m1 = n1 + 2;
+    for (int64_t P = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; P < N; P += (int64_t)gridDim.x * blockDim.x) {
+        int64_t x = P % n0, y = (P / n0) % n1, z = P / ((int64_t)n0 * n1);
+        int64_t nd[3] = {x + 1, dim > 1 ? y + 1 : 0, dim > 2 ? z + 1 : 0};
+        int64_t st[3] = {1, m0, m0 * m1};
+        int64_t node = nd[0] + m0 * (nd[1] + m1 * nd[2]);
+        double sum = 0.0;
+        for (int a = 0; a < dim; ++a) {
+            for (int s = -1; s <= 1; s += 2) {
+                double ap = al.d[a][node], aq = al.d[a][node + s * st[a]];
+                double face = 2.0 * ap * aq / (ap + aq);
+                out.d[dk(a, s)][P] = face;
+                sum += face;
+            }
+        }
+        out.d[0][P] = sum + beta;
+    }
+}
+
+template <int DIM>
+__global__ void k_spmv(int n0, int n1, int n2, DiagPtrs D, const double *__restrict__ x, double *__restrict__ y,
+                       const double *__restrict__ f) {
+    const int64_t N = (int64_t)n0 * n1 * n2;
+    const int64_t s1 = n0, s2 = (int64_t)n0 * n1;
+    for (int64_t P = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; P < N; P += (int64_t)gridDim.x * blockDim.x) {
+        int i = (int)(P % n0);
+        int j = (int)((P / n0) % n1);
+        double acc = D.d[0][P] * x[P];
+        if (i > 0) acc -= D.d[1][P] * x[P - 1];
+        if (i < n0 - 1) acc -= D.d[2][P] * x[P + 1];
+        if (j > 0) acc -= D.d[3][P] * x[P - s1];
+        if (j < n1 - 1) acc -= D.d[4][P] * x[P + s1];
+        if (DIM == 3) {
+            int k = (int)(P / s2);
+            if (k > 0) acc -= D.d[5][P] * x[P - s2];
+            if (k < n2 - 1) acc -= D.d[6][P] * x[P + s2];
+        }
+        y[P] = f ? f[P] - acc : acc;
+    }
+}
+
+static unsigned grid_for(int64_t N, int threads = 256, int64_t cap = 8192) {
+    int64_t b = (N + threads - 1) / threads;
+    if (b > cap) b = cap;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+hipError_t launch_assemble(int dim, const int n[3], const double *const *alpha, double beta, double *const *diag,
+                           hipStream_t st) {
+    DiagPtrs al{};
+    DiagOut out{};
+    for (int a = 0; a < dim; ++a) al.d[a] = alpha[a];
+    for (int k = 0; k < 2 * dim + 1; ++k) out.d[k] = diag[k];
+    int64_t N = (int64_t)n[0] * n[1] * n[2];
+    hipLaunchKernelGGL(k_assemble, dim3(grid_for(N)), dim3(256), 0, st, dim, n[0], n[1], n[2], al, beta, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv(int dim, const int n[3], const double *const *diag, const double *x, double *y,
+                       hipStream_t st) {
+    DiagPtrs D{};
+    for (int k = 0; k < 2 * dim + 1; ++k) D.d[k] = diag[k];
+    int64_t N = (int64_t)n[0] * n[1] * n[2];
+    if (dim == 2)
+        hipLaunchKernelGGL(k_spmv<2>, dim3(grid_for(N)), dim3(256), 0, st, n[0], n[1], n[2], D, x, y, (const double *)nullptr);
+    else
+        hipLaunchKernelGGL(k_spmv<3>, dim3(grid_for(N)), dim3(256), 0, st, n[0], n[1], n[2], D, x, y, (const double *)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(int dim, const int n[3], const double *const *diag, const double *f, const double *x,
+                           double *r, hipStream_t st) {
+    DiagPtrs D{};
+    for (int k = 0; k < 2 * dim + 1; ++k) D.d[k] = diag[k];
+    int64_t N = (int64_t)n[0] * n[1] * n[2];
+    if (dim == 2)
+        hipLaunchKernelGGL(k_spmv<2>, dim3(grid_for(N)), dim3(256), 0, st, n[0], n[1], n[2], D, x, r, f);
+    else
+        hipLaunchKernelGGL(k_spmv<3>, dim3(grid_for(N)), dim3(256), 0, st, n[0], n[1], n[2], D, x, r, f);
+    return hipGetLastError();
+}
+
+// FP64 -> storage precision.  BF16: round to odd into FP32 first, then to
+// nearest even into BF16, which equals direct round-to-nearest-even.
+__device__ __forceinline__ uint16_t f64_to_bf16(double x) {
+    float t = __double2float_rz(x);
+    uint32_t u = __float_as_uint(t);
+    if ((double)t != x && (u & 0x7f800000u) != 0x7f800000u) u |= 1u;
+    uint32_t r = u + 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(r >> 16);
+}
+
+__global__ void k_convert(const double *src, void *dst, int kind, int64_t N, double scale) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        double v = src[i] * scale;
+        if (kind == 0) ((double *)dst)[i] = v;
+        else if (kind == 1) ((float *)dst)[i] = (float)v;
+        else ((uint16_t *)dst)[i] = f64_to_bf16(v);
+    }
+}
+
+hipError_t launch_convert(const double *src, void *dst, Store s, int64_t N, double scale, hipStream_t st) {
+    hipLaunchKernelGGL(k_convert, dim3(grid_for(N)), dim3(256), 0, st, src, dst, (int)s, N, scale);
+    return hipGetLastError();
+}
+
+__global__ void k_scale_add(double *z, const double *a, double ca, const void *b, int b_f64, double cb, int64_t N) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        double bv = b ? (b_f64 ? ((const double *)b)[i] : (double)((const float *)b)[i]) : 0.0;
+        double av = a ? a[i] : 0.0;
+        z[i] = ca * av + cb * bv;
+    }
+}
+
+hipError_t launch_scale_add(double *z, const double *a, double ca, const void *b, bool b_f64, double cb, int64_t N,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_scale_add, dim3(grid_for(N)), dim3(256), 0, st, z, a, ca, b, b_f64 ? 1 : 0, cb, N);
+    return hipGetLastError();
+}
+
+// deterministic block reduction of one value per thread (fixed tree)
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(kRedThreads) k_dot_partial(const double *x, const double *y, int64_t N, double *partials) {
+    __shared__ double sh[kRedThreads];
+    double acc = 0.0;
+    const int64_t stride = (int64_t)kRedBlocks * kRedThreads;
+    for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < N; i += stride) acc += x[i] * y[i];
+    double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// sums `groups` consecutive groups of kRedBlocks partials; out[g] per group
+__global__ void __launch_bounds__(kRedThreads) k_dot_final(const double *partials, double *out) {
+    __shared__ double sh[kRedThreads];
+    const double *p = partials + (int64_t)blockIdx.x * kRedBlocks;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < kRedBlocks; i += kRedThreads) acc += p[i];
+    double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+hipError_t launch_dot(const double *x, const double *y, int64_t N, double *partials, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_dot_partial, dim3(kRedBlocks), dim3(kRedThreads), 0, st, x, y, N, partials);
+    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kRedThreads), 0, st, partials, out);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(kRedThreads) k_cg_xr(double *x, double *r, const double *p, const double *q,
+                                                      const double *num, const double *den, int64_t N,
+                                                      double *partials) {
+    __shared__ double sh[kRedThreads];
+    const double alpha = num[0] / den[0];
+    double acc = 0.0;
+    const int64_t stride = (int64_t)kRedBlocks * kRedThreads;
+    for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < N; i += stride) {
+        x[i] += alpha * p[i];
+        double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        acc += ri * ri;
+    }
+    double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+hipError_t launch_cg_update_xr(double *x, double *r, const double *p, const double *q, const double *num,
+                               const double *den, int64_t N, double *partials, double *rr, hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_xr, dim3(kRedBlocks), dim3(kRedThreads), 0, st, x, r, p, q, num, den, N, partials);
+    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kRedThreads), 0, st, partials, rr);
+    return hipGetLastError();
+}
+
+__global__ void k_cg_p(double *p, const double *z, const double *num, const double *den, int64_t N) {
+    const double beta = num[0] / den[0];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = z[i] + beta * p[i];
+}
+
+hipError_t launch_cg_update_p(double *p, const double *z, const double *num, const double *den, int64_t N,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_p, dim3(grid_for(N)), dim3(256), 0, st, p, z, num, den, N);
+    return hipGetLastError();
+}
+
+__global__ void k_axpy(double *y, double a, const double *x, int64_t N) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] += a * x[i];
+}
+
+hipError_t launch_axpy(double *y, double a, const double *x, int64_t N, hipStream_t st) {
+    hipLaunchKernelGGL(k_axpy, dim3(grid_for(N)), dim3(256), 0, st, y, a, x, N);
+    return hipGetLastError();
+}
+
+__global__ void k_copy_scaled(double *y, const double *x, double a, int64_t N) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = a * x[i];
+}
+
+hipError_t launch_copy_scaled(double *y, const double *x, double a, int64_t N, hipStream_t st) {
+    hipLaunchKernelGGL(k_copy_scaled, dim3(grid_for(N)), dim3(256), 0, st, y, x, a, N);
+    return hipGetLastError();
+}
+
+__global__ void k_multi_axpy(double *y, const double *V, const double *c, int k, int64_t N, int accumulate) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        double acc = accumulate ? y[i] : 0.0;
+        for (int j = 0; j < k; ++j) acc += c[j] * V[(int64_t)j * N + i];
+        y[i] = acc;
+    }
+}
+
+hipError_t launch_multi_axpy(double *y, const double *V, const double *c, int k, int64_t N, bool accumulate,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_multi_axpy, dim3(grid_for(N)), dim3(256), 0, st, y, V, c, k, N, accumulate ? 1 : 0);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(kRedThreads) k_multi_dot_partial(const double *V, const double *w, int64_t N,
+                                                                  double *partials) {
+    __shared__ double sh[kRedThreads];
+    const int j = blockIdx.y;
+    const double *v = V + (int64_t)j * N;
+    double acc = 0.0;
+    const int64_t stride = (int64_t)kRedBlocks * kRedThreads;
+    for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < N; i += stride) acc += v[i] * w[i];
+    double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[(int64_t)j * kRedBlocks + blockIdx.x] = s;
+}
+
+hipError_t launch_multi_dot(const double *V, const double *w, int k, int64_t N, double *partials, double *out,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_multi_dot_partial, dim3(kRedBlocks, k), dim3(kRedThreads), 0, st, V, w, N, partials);
+    hipLaunchKernelGGL(k_dot_final, dim3(k), dim3(kRedThreads), 0, st, partials, out);
+    return hipGetLastError();
+}
+
+} // namespace psw

@@ -1,0 +1,169 @@
+"""GPU parity: every kernel of libpsweep.so against the CPU FP64 oracle.
+
+Bars: one FP64 sweep / half-sweep within 1e-12 (max abs error over max abs
+value); ILU pivots and SpMV within 1e-13; iteration counts to tolerance
+within 1 of the oracle's; FP32 / BF16 sweeps report their error against the
+FP64 oracle and must stay inside the bounds below.
+"""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import dev, make_problem, relmax, to_dev, to_np
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+SWEEP_CASES = [
+    (2, (13, 11), (3, 2)), (2, (16, 16), (4, 4)), (2, (37, 29), (5, 3)), (2, (64, 40), (2, 5)),
+    (2, (10, 9), (1, 1)), (2, (20, 8), (10, 4)),
+    (3, (7, 6, 5), (2, 2, 2)), (3, (12, 9, 10), (3, 2, 4)), (3, (9, 9, 9), (1, 1, 1)), (3, (16, 8, 6), (4, 2, 3)),
+]
+
+
+def _prob(dim, n, seed=1):
+    pr = synth.random_small(seed + sum(n), dim, n)
+    diags = O.assemble(dim, n, pr["alphas"])
+    return pr, diags
+
+
+@pytest.mark.parametrize("dim,n", [(2, (33, 17)), (3, (9, 7, 5))])
+def test_assemble(dim, n):
+    pr, diags = _prob(dim, n)
+    g = make_problem(dim, n, pr["alphas"])
+    import torch
+    out = torch.empty(int(np.prod(n)), dtype=torch.float64, device=dev())
+    for k in range(2 * dim + 1):
+        g.get_diagonal(k, out)
+        assert relmax(to_np(out), diags[k]) <= 1e-14
+
+
+@pytest.mark.parametrize("dim,n,p", SWEEP_CASES)
+def test_stationary_sweep(dim, n, p):
+    pr, diags = _prob(dim, n)
+    g = make_problem(dim, n, pr["alphas"])
+    om = synth.rng(3).uniform(0.7, 1.9, 1 << dim)
+    g.set_relaxation(list(om))
+    import torch
+    u = to_dev(pr["u"]); f = to_dev(pr["f"])
+    out = torch.empty_like(u)
+    for phase in (0, 1):
+        g.set_decomposition(p, overlap=2, phase=phase)
+        for k in range(1 << dim):
+            g.sweep(k, u, f, out)
+            ref = O.dsweep(dim, n, p, O.schedule(dim, p, k, phase), diags, pr["f"], uold=pr["u"], omega=om)
+            err = relmax(to_np(out), ref)
+            assert err <= 1e-12, (phase, k, err)
+
+
+@pytest.mark.parametrize("kind", ["ssor", "ilu0"])
+@pytest.mark.parametrize("dim,n,p", SWEEP_CASES)
+def test_precond_half_sweeps_f64(kind, dim, n, p):
+    pr, diags = _prob(dim, n, seed=5)
+    g = make_problem(dim, n, pr["alphas"])
+    w = 1.3
+    g.set_relaxation([w])
+    g.set_decomposition(p, overlap=2, phase=0)
+    pc = O.Precond(kind, dim, n, p, diags, omega=w)
+    import torch
+    r = to_dev(pr["f"]); out = torch.empty_like(r)
+    y = pc.forward(pr["f"])
+    refs = {
+        0: y,
+        1: pc.backward(pr["u"]),
+        2: O.dsolve_t(dim, n, p, pc.dirs_b, diags, pc.piv, pr["f"]),
+        3: pc.c * O.dsolve_t(dim, n, p, pc.dirs_f, diags, pc.piv, pc.piv * pr["u"]),
+    }
+    inputs = {0: pr["f"], 1: pr["u"], 2: pr["f"], 3: pr["u"]}
+    for which in range(4):
+        g.precond_half(kind, which, to_dev(inputs[which]), out)
+        err = relmax(to_np(out), refs[which])
+        assert err <= 1e-12, (which, err)
+    z = torch.empty_like(r)
+    g.precond_apply(kind, r, z, symmetric=False)
+    assert relmax(to_np(z), pc.apply(pr["f"])) <= 1e-12
+    g.precond_apply(kind, r, z, symmetric=True)
+    assert relmax(to_np(z), pc.apply_sym(pr["f"])) <= 1e-12
+
+
+@pytest.mark.parametrize("dim,n,p", SWEEP_CASES[:6] + SWEEP_CASES[6:8])
+def test_ilu_pivots(dim, n, p):
+    pr, diags = _prob(dim, n, seed=9)
+    g = make_problem(dim, n, pr["alphas"])
+    g.set_decomposition(p, overlap=2, phase=0)
+    import torch
+    out = torch.empty(int(np.prod(n)), dtype=torch.float64, device=dev())
+    g.ilu_pivots(out)
+    ref = O.ilu_pivots(dim, n, p, O.schedule(dim, p, 0), diags)
+    assert relmax(to_np(out), ref) <= 1e-13
+
+
+@pytest.mark.parametrize("dim,n", [(2, (50, 33)), (3, (11, 8, 13))])
+def test_spmv_and_dot(dim, n):
+    pr, diags = _prob(dim, n, seed=13)
+    g = make_problem(dim, n, pr["alphas"])
+    import torch
+    x = to_dev(pr["u"]); y = torch.empty_like(x)
+    g.spmv(x, y)
+    assert relmax(to_np(y), O.spmv(dim, n, diags, pr["u"])) <= 1e-13
+    d = g.dot(x, to_dev(pr["f"]))
+    assert abs(d - pr["u"] @ pr["f"]) <= 1e-12 * np.abs(pr["u"]).sum()
+    # deterministic: identical on repeat
+    assert g.dot(x, to_dev(pr["f"])) == d
+
+
+@pytest.mark.parametrize("prec,bound", [("f32", 1e-5), ("bf16", 3e-2)])
+@pytest.mark.parametrize("dim,n,p", [(2, (40, 36), (4, 3)), (3, (12, 10, 9), (2, 2, 3))])
+def test_precond_mixed_precision_error(prec, bound, dim, n, p):
+    pr, diags = _prob(dim, n, seed=17)
+    g = make_problem(dim, n, pr["alphas"], prec=prec)
+    g.set_relaxation([1.0])
+    g.set_decomposition(p, overlap=2, phase=0)
+    import torch
+    r = to_dev(pr["f"]); z = torch.empty_like(r)
+    for kind in ("ssor", "ilu0"):
+        pc = O.Precond(kind, dim, n, p, diags, omega=1.0)
+        for sym in (False, True):
+            g.precond_apply(kind, r, z, symmetric=sym)
+            ref = pc.apply_sym(pr["f"]) if sym else pc.apply(pr["f"])
+            err = np.linalg.norm(to_np(z) - ref) / np.linalg.norm(ref)
+            assert err <= bound, (kind, sym, err)
+
+
+def test_stationary_solve_poisson_64():
+    """64x64 Poisson, 4x4 subdomains, omega = 2/(1+sin(pi/65)), relres 1e-8: sweeps within 1 of the oracle."""
+    w = synth.poisson_2d_64()
+    n = w["n"]
+    diags = O.assemble(2, n, w["alphas"])
+    omega = 2.0 / (1.0 + np.sin(np.pi / 65))
+    _, it_ref, _ = O.stationary_solve(2, n, (4, 4), diags, omega, w["f"], rtol=1e-8, maxit=5000)
+    g = make_problem(2, n, w["alphas"])
+    g.set_relaxation([omega])
+    g.set_decomposition((4, 4), overlap=2)
+    import torch
+    u = torch.zeros(4096, dtype=torch.float64, device=dev())
+    info = g.solve("sor", "none", to_dev(w["f"]), u, rtol=1e-8, maxit=5000)
+    assert info["converged"] and abs(info["iters"] - it_ref) <= 1, (info, it_ref)
+
+
+@pytest.mark.parametrize("kind", ["ssor", "ilu0"])
+@pytest.mark.parametrize("dim,n,p", [(2, (48, 40), (4, 4)), (3, (12, 12, 10), (2, 3, 2))])
+def test_krylov_iterations_match_oracle(kind, dim, n, p):
+    pr, diags = _prob(dim, n, seed=21)
+    Aop = lambda v: O.spmv(dim, n, diags, v)
+    pc = O.Precond(kind, dim, n, p, diags, omega=1.0)
+    xr, it_cg, _ = O.cg(Aop, pc.apply_sym, pr["f"], rtol=1e-8)
+    _, it_gm, _ = O.fgmres(Aop, pc.apply, pr["f"], rtol=1e-8, restart=30)
+    g = make_problem(dim, n, pr["alphas"])
+    g.set_relaxation([1.0])
+    g.set_decomposition(p, overlap=2)
+    import torch
+    N = int(np.prod(n))
+    f = to_dev(pr["f"])
+    u = torch.zeros(N, dtype=torch.float64, device=dev())
+    info = g.solve("cg", kind, f, u, rtol=1e-8)
+    assert info["converged"] and abs(info["iters"] - it_cg) <= 1, (info, it_cg)
+    assert np.linalg.norm(to_np(u) - xr) <= 1e-6 * np.linalg.norm(xr)
+    u.zero_()
+    info = g.solve("fgmres", kind, f, u, rtol=1e-8, restart=30)
+    assert info["converged"] and abs(info["iters"] - it_gm) <= 1, (info, it_gm)
