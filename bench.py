@@ -1,0 +1,172 @@
+"""Benchmark: preconditioned CG on the 2D variable-coefficient diffusion problem.
+
+Workload (one step = one full solve on inputs resident in HBM): 2048x2048
+interior grid, 5-point operator -div(alpha grad u) with cell coefficients
+log-uniform in [1e-2, 1e2] (seed 2001) and harmonic face means, rhs U[-1,1]
+(seed 2002), 16x16 subdomains, overlap 4, CG with the symmetric form of the
+parallel ILU(0) preconditioner (SSOR with omega = 1 via --precond ssor) to
+relative residual 1e-8, FP64.
+
+Printed: one JSON line.  `value` is sweep Gpoints/s over the whole job:
+interior points x half-sweeps executed / wall time of the timed steps.  The
+roofline object times the dominant kernel (the start-coupled forward
+half-sweep) with HIP events on the stream it runs on.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--p", type=int, default=16)
+    ap.add_argument("--overlap", type=int, default=4)
+    ap.add_argument("--precond", default="ilu0", choices=["ilu0", "ssor"])
+    ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--maxit", type=int, default=100000)
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-sample-s", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1008_3699_amd as P
+    import synth
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    n, p = args.n, args.p
+    w = synth.varcoef_2d(n=n)
+    N = n * n
+    al = torch.from_numpy(w["alphas"][0]).to(dev)
+    f = torch.from_numpy(w["f"]).to(dev)
+    g = P.Problem(2, (n, n))
+    g.assemble([al, al], 0.0, args.prec)
+    g.set_relaxation([1.0])
+    g.set_decomposition((p, p), overlap=args.overlap, phase=0)
+    g.precond_setup(args.precond)
+    u = torch.zeros(N, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+
+    def one_solve():
+        u.zero_()
+        return g.solve("cg", args.precond, f, u, rtol=args.rtol, maxit=args.maxit)
+
+    for _ in range(args.warmup):
+        one_solve()
+    torch.cuda.synchronize()
+    lat = []
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        infos.append(one_solve())
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - s0)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    iters = [i["iters"] for i in infos]
+    # half-sweeps per CG iteration with the symmetric preconditioner: 4, plus the initial application
+    half_sweeps = sum(4 * (it + 1) for it in iters)
+    value = N * half_sweeps / elapsed / 1e9
+
+    # dominant kernel: forward start-coupled half-sweep, timed with HIP events on its stream
+    r = torch.randn(N, dtype=torch.float64, device=dev)
+    y = torch.empty_like(r)
+    for _ in range(3):
+        g.precond_half(args.precond, 0, r, y)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.kernel_reps):
+        g.precond_half(args.precond, 0, r, y)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    k_ms = e0.elapsed_time(e1) / args.kernel_reps
+    bpp = {"f64": 40, "f32": 28, "bf16": 20}[args.prec]  # r(8) + Piv + 2 upstream couplings + y
+    alg_bytes = bpp * N
+    achieved = alg_bytes / (k_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_sweep_start (forward half-sweep)", "kernel_ms": round(k_ms, 4),
+                "bytes_per_point": bpp}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(w, n, p, args.precond, args.cpu_sample_s)
+
+    rec = {
+        "metric": "sweep Gpoints/s (whole job, PCG to 1e-8)",
+        "value": round(value, 3),
+        "unit": "Gpoints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": f"2D var-coef diffusion {n}x{n}, {p}x{p} subdomains, overlap {args.overlap}, "
+                               f"{args.precond.upper()}-PCG (symmetric form) to {args.rtol:g}",
+                   "n": n, "subdomains": [p, p], "overlap": args.overlap, "precond": args.precond},
+        "solves_per_s": round(args.steps / elapsed, 4),
+        "latency_p50_s": round(float(np.percentile(lat, 50)), 4),
+        "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
+        "iterations": iters,
+        "relres": [i["relres"] for i in infos],
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+def cpu_baseline(w, n, p, kind, budget_s):
+    """The CPU oracle timed on this host: preconditioner half-sweeps on the full grid."""
+    import numpy as np
+
+    from oracle import oracle as O
+    diags = O.assemble(2, (n, n), w["alphas"])
+    pc = O.Precond(kind, 2, (n, n), (p, p), diags, omega=1.0)
+    r = w["f"]
+    t0 = time.perf_counter()
+    halves = 0
+    while True:
+        pc.forward(r)
+        halves += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": round(n * n * halves / dt / 1e9, 5), "unit": "Gpoints/s", "cores": 1, "kind": "oracle",
+            "sample": f"{halves} forward half-sweeps of the {kind} preconditioner on the full {n}x{n} grid "
+                      f"({p}x{p} subdomains), single-threaded C oracle"}
+
+
+if __name__ == "__main__":
+    main()

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libpsweep.so")
-SOURCES = ["psw_kernels.hip", "psw_host.hip"]
+SOURCES = ["psw_kernels.hip", "psw_fast2d.hip", "psw_host.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -6,13 +6,16 @@
 // stream; scalars of the Krylov recurrences stay on the device and only the
 // residual norm crosses to the host for the stopping test.
 #include "psw_internal.h"
+#include "psw_fast2d.h"
 #include "../../include/psweep.h"
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -53,6 +56,10 @@ size_t store_bytes(Store s) { return s == Store::F64 ? 8 : (s == Store::F32 ? 4 
 
 } // namespace
 
+struct FastPassBuf {
+    DevBuf inv, ax, ay, face;
+};
+
 struct PrecState {
     bool ready = false;
     double omega = 1.0;
@@ -60,6 +67,11 @@ struct PrecState {
     DevBuf diag[7]; // off-diagonals in sweep precision (index 0 unused)
     DevBuf piv;     // pivots in sweep precision
     DevBuf piv64;   // pivots in FP64
+    // pipelined 2D path: packed coefficients of the four passes
+    bool fast = false;
+    int R = 1, lxmax = 1, lymax = 1;
+    FastPassBuf fp[4];
+    DevBuf toff, foff;
 };
 
 struct psw_problem {
@@ -163,6 +175,72 @@ psw_status check_lds(const psw_problem *P, size_t elem) {
     return need <= P->lds_limit ? PSW_OK : PSW_ENOTSUP;
 }
 
+// direction of pass `which` (0: d, 1: -d, 2: d transposed, 3: -d transposed)
+void pass_sig(const psw_problem *P, int which, int sig[3]) {
+    sched_sig(P, 0, sig);
+    if (which == 1 || which == 3)
+        for (int a = 0; a < 3; ++a) sig[a] = -sig[a];
+}
+
+bool fast_eligible(const psw_problem *P, int &R, int &lxmax, int &lymax) {
+    if (P->dim != 2) return false;
+    const char *e = std::getenv("PSW_FORCE_GENERIC");
+    if (e && e[0] == '1') return false;
+    std::vector<int> lo, len;
+    partition(P->n[0], P->p[0], lo, len);
+    lxmax = *std::max_element(len.begin(), len.end());
+    partition(P->n[1], P->p[1], lo, len);
+    lymax = *std::max_element(len.begin(), len.end());
+    R = (lymax + 63) / 64;
+    if (R > 2) return false;
+    size_t elem = P->prec == PSW_F64 ? 8 : 4;
+    return fast2d_lds_bytes(lxmax, lymax, R, elem) <= P->lds_limit;
+}
+
+psw_status fast_setup(psw_problem *P, PrecState &S, hipStream_t st) {
+    int R, lxmax, lymax;
+    S.fast = false;
+    if (!fast_eligible(P, R, lxmax, lymax)) return PSW_OK;
+    std::vector<int> lo0, len0, lo1, len1;
+    partition(P->n[0], P->p[0], lo0, len0);
+    partition(P->n[1], P->p[1], lo1, len1);
+    std::vector<int64_t> toff, foff;
+    int64_t t = 0, f = 0;
+    for (int s1 = 0; s1 < P->p[1]; ++s1)
+        for (int s0 = 0; s0 < P->p[0]; ++s0) {
+            int lx = len0[s0], ly = len1[s1];
+            int L = (ly + R - 1) / R;
+            toff.push_back(t);
+            foff.push_back(f);
+            t += (int64_t)(lx + L - 1 + kFast2dDepth) * 64 * R;
+            f += 3 * (int64_t)(lx + ly) + 3;
+            f = (f + 7) & ~(int64_t)7;
+        }
+    Store s = store_of(P->prec);
+    size_t eb = store_bytes(s);
+    if (!S.toff.ensure(sizeof(int64_t) * toff.size()) || !S.foff.ensure(sizeof(int64_t) * foff.size()))
+        return PSW_ENOMEM;
+    HIPCHK(hipMemcpy(S.toff.p, toff.data(), sizeof(int64_t) * toff.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(S.foff.p, foff.data(), sizeof(int64_t) * foff.size(), hipMemcpyHostToDevice));
+    const double *d[7];
+    diag64(P, d);
+    for (int w = 0; w < 4; ++w) {
+        FastPassBuf &B = S.fp[w];
+        if (!B.inv.ensure(eb * t) || !B.ax.ensure(eb * t) || !B.ay.ensure(eb * t) || !B.face.ensure(eb * (f + 8)))
+            return PSW_ENOMEM;
+        int sig[3];
+        pass_sig(P, w, sig);
+        PassGeom g = geom(P, sig);
+        HIPCHK(launch_pack2d(g, s, R, w >= 2, d, S.piv64.as<double>(), S.toff.as<int64_t>(), S.foff.as<int64_t>(),
+                             B.inv.p, B.ax.p, B.ay.p, B.face.p, st));
+    }
+    S.R = R;
+    S.lxmax = lxmax;
+    S.lymax = lymax;
+    S.fast = true;
+    return PSW_OK;
+}
+
 // preconditioner state for kind (SSOR: Piv = D/w, c = 2-w; ILU0: Piv = D~, c = 1)
 psw_status precond_setup(psw_problem *P, psw_precond kind, hipStream_t st) {
     if (kind != PSW_SSOR && kind != PSW_ILU0) return PSW_EINVAL;
@@ -198,6 +276,7 @@ psw_status precond_setup(psw_problem *P, psw_precond kind, hipStream_t st) {
         if (hb) return PSW_EPIVOT;
     }
     HIPCHK(launch_convert(S.piv64.as<double>(), S.piv.p, s, P->N, 1.0, st));
+    if ((ps = fast_setup(P, S, st))) return ps;
     S.ready = true;
     return PSW_OK;
 }
@@ -208,11 +287,33 @@ psw_status half(psw_problem *P, psw_precond kind, int which, const void *in, boo
     PrecState &S = P->pc[kind];
     Store s = store_of(P->prec);
     int sig[3];
-    sched_sig(P, 0, sig);
-    if (which == 1 || which == 3) for (int a = 0; a < 3; ++a) sig[a] = -sig[a];
+    pass_sig(P, which, sig);
     PassGeom g = geom(P, sig);
     const void *d[7];
     for (int k = 0; k < 7; ++k) d[k] = S.diag[k].p;
+    if (S.fast) {
+        Fast2dPass fp{};
+        fp.g = g;
+        fp.R = S.R;
+        fp.coupled = which <= 1;
+        fp.lxmax = S.lxmax;
+        fp.lymax = S.lymax;
+        fp.s_inv = S.fp[which].inv.p;
+        fp.s_ax = S.fp[which].ax.p;
+        fp.s_ay = S.fp[which].ay.p;
+        fp.face = S.fp[which].face.p;
+        fp.toff = S.toff.as<int64_t>();
+        fp.foff = S.foff.as<int64_t>();
+        if (which <= 1) {
+            HIPCHK(launch_fast2d(fp, s, in, in_f64, scale_by_piv, out, out_f64, cscale, st));
+        } else {
+            HIPCHK(launch_fast2d(fp, s, in, in_f64, scale_by_piv, out, out_f64, 1.0, st));
+            HIPCHK(launch_end_faces2d_fast(g, s, d, S.piv.p, in, in_f64, scale_by_piv, out, out_f64,
+                                           std::max(S.lxmax, S.lymax), st));
+            HIPCHK(launch_end_corners(g, s, d, S.piv.p, in, in_f64, scale_by_piv, out, out_f64, st));
+        }
+        return PSW_OK;
+    }
     if (which <= 1)
         HIPCHK(launch_half_start(g, s, d, S.piv.p, in, in_f64, scale_by_piv, out, out_f64, cscale, st));
     else

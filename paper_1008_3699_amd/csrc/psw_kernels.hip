@@ -20,6 +20,7 @@
 // points in order of block size: faces, then edges (3D), then corners; each
 // group reads only results of the earlier groups.
 #include "psw_internal.h"
+#include "psw_fast2d.h"
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -598,6 +599,58 @@ static hipError_t end_impl(const PassGeom &g, const void *const *diag, const voi
         hipLaunchKernelGGL((k_end_corners<3, T, S, TIN, TOUT>), dim3((g.ntiles + 63) / 64), dim3(64), 0, st, A);
     }
     return hipGetLastError();
+}
+
+template <typename T, typename S, typename TIN, typename TOUT>
+static hipError_t end_part_impl(const PassGeom &g, const void *const *diag, const void *piv, const void *in,
+                                bool scale_by_piv, void *out, int part, hipStream_t st) {
+    EndArgs<S, TIN, TOUT> A{};
+    A.g = g;
+    for (int k = 0; k < 2 * g.dim + 1; ++k) A.diag[k] = (const S *)diag[k];
+    A.piv = (const S *)piv;
+    A.in = (const TIN *)in;
+    A.scale_by_piv = scale_by_piv ? 1 : 0;
+    A.out = (TOUT *)out;
+    if (part == 0) {
+        size_t sm = rings_bytes(g, sizeof(T));
+        dim3 grid(g.ntiles), blk(block_threads(g));
+        if (g.dim == 2) hipLaunchKernelGGL((k_sweep_end_interior<2, T, S, TIN, TOUT>), grid, blk, sm, st, A);
+        else hipLaunchKernelGGL((k_sweep_end_interior<3, T, S, TIN, TOUT>), grid, blk, sm, st, A);
+    } else {
+        if (g.dim == 2)
+            hipLaunchKernelGGL((k_end_corners<2, T, S, TIN, TOUT>), dim3((g.ntiles + 63) / 64), dim3(64), 0, st, A);
+        else
+            hipLaunchKernelGGL((k_end_corners<3, T, S, TIN, TOUT>), dim3((g.ntiles + 63) / 64), dim3(64), 0, st, A);
+    }
+    return hipGetLastError();
+}
+
+static hipError_t end_part(const PassGeom &g, Store s, const void *const *diag, const void *piv, const void *in,
+                           bool in_f64, bool scale_by_piv, void *out, bool out_f64, int part, hipStream_t st) {
+    if (s == Store::F64) {
+        if (!in_f64 || !out_f64) return hipErrorInvalidValue;
+        return end_part_impl<double, double, double, double>(g, diag, piv, in, scale_by_piv, out, part, st);
+    }
+    if (s == Store::F32) {
+        if (in_f64 && !out_f64) return end_part_impl<float, float, double, float>(g, diag, piv, in, scale_by_piv, out, part, st);
+        if (!in_f64 && !out_f64) return end_part_impl<float, float, float, float>(g, diag, piv, in, scale_by_piv, out, part, st);
+        if (in_f64 && out_f64) return end_part_impl<float, float, double, double>(g, diag, piv, in, scale_by_piv, out, part, st);
+        return end_part_impl<float, float, float, double>(g, diag, piv, in, scale_by_piv, out, part, st);
+    }
+    if (in_f64 && !out_f64) return end_part_impl<float, uint16_t, double, float>(g, diag, piv, in, scale_by_piv, out, part, st);
+    if (!in_f64 && !out_f64) return end_part_impl<float, uint16_t, float, float>(g, diag, piv, in, scale_by_piv, out, part, st);
+    if (in_f64 && out_f64) return end_part_impl<float, uint16_t, double, double>(g, diag, piv, in, scale_by_piv, out, part, st);
+    return end_part_impl<float, uint16_t, float, double>(g, diag, piv, in, scale_by_piv, out, part, st);
+}
+
+hipError_t launch_end_corners(const PassGeom &g, Store s, const void *const *diag, const void *piv, const void *in,
+                              bool in_f64, bool scale_by_piv, void *out, bool out_f64, hipStream_t st) {
+    return end_part(g, s, diag, piv, in, in_f64, scale_by_piv, out, out_f64, 1, st);
+}
+
+hipError_t launch_end_interior(const PassGeom &g, Store s, const void *const *diag, const void *piv, const void *in,
+                               bool in_f64, bool scale_by_piv, void *out, bool out_f64, hipStream_t st) {
+    return end_part(g, s, diag, piv, in, in_f64, scale_by_piv, out, out_f64, 0, st);
 }
 
 hipError_t launch_half_start(const PassGeom &g, Store s, const void *const *diag, const void *piv, const void *in,

@@ -56,9 +56,24 @@ def test_stationary_sweep(dim, n, p):
             assert err <= 1e-12, (phase, k, err)
 
 
+PRECOND_CASES = SWEEP_CASES + [(2, (300, 250), (3, 2)), (2, (130, 128), (1, 1)), (2, (256, 190), (4, 3))]
+
+
+@pytest.fixture(params=["pipelined", "generic"])
+def path(request, monkeypatch):
+    """2D problems run the wavefront-pipelined kernels unless PSW_FORCE_GENERIC=1."""
+    if request.param == "generic":
+        monkeypatch.setenv("PSW_FORCE_GENERIC", "1")
+    else:
+        monkeypatch.delenv("PSW_FORCE_GENERIC", raising=False)
+    return request.param
+
+
 @pytest.mark.parametrize("kind", ["ssor", "ilu0"])
-@pytest.mark.parametrize("dim,n,p", SWEEP_CASES)
-def test_precond_half_sweeps_f64(kind, dim, n, p):
+@pytest.mark.parametrize("dim,n,p", PRECOND_CASES)
+def test_precond_half_sweeps_f64(kind, dim, n, p, path):
+    if dim == 3 and path == "pipelined":
+        pytest.skip("3D problems use the generic kernels only")
     pr, diags = _prob(dim, n, seed=5)
     g = make_problem(dim, n, pr["alphas"])
     w = 1.3
@@ -113,8 +128,10 @@ def test_spmv_and_dot(dim, n):
 
 
 @pytest.mark.parametrize("prec,bound", [("f32", 1e-5), ("bf16", 3e-2)])
-@pytest.mark.parametrize("dim,n,p", [(2, (40, 36), (4, 3)), (3, (12, 10, 9), (2, 2, 3))])
-def test_precond_mixed_precision_error(prec, bound, dim, n, p):
+@pytest.mark.parametrize("dim,n,p", [(2, (40, 36), (4, 3)), (2, (260, 200), (2, 2)), (3, (12, 10, 9), (2, 2, 3))])
+def test_precond_mixed_precision_error(prec, bound, dim, n, p, path):
+    if dim == 3 and path == "pipelined":
+        pytest.skip("3D problems use the generic kernels only")
     pr, diags = _prob(dim, n, seed=17)
     g = make_problem(dim, n, pr["alphas"], prec=prec)
     g.set_relaxation([1.0])
@@ -167,3 +184,23 @@ def test_krylov_iterations_match_oracle(kind, dim, n, p):
     u.zero_()
     info = g.solve("fgmres", kind, f, u, rtol=1e-8, restart=30)
     assert info["converged"] and abs(info["iters"] - it_gm) <= 1, (info, it_gm)
+
+
+@pytest.mark.parametrize("kind", ["ssor", "ilu0"])
+def test_full_size_varcoef_2048_half_sweeps(kind):
+    """The benchmark workload at full size: 2048^2, 16x16 subdomains, overlap 4; every output point."""
+    w = synth.varcoef_2d(n=2048)
+    n, p = (2048, 2048), (16, 16)
+    diags = O.assemble(2, n, w["alphas"])
+    pc = O.Precond(kind, 2, n, p, diags, omega=1.0)
+    g = make_problem(2, n, w["alphas"])
+    g.set_relaxation([1.0])
+    g.set_decomposition(p, overlap=4, phase=0)
+    import torch
+    r = to_dev(w["f"]); out = torch.empty_like(r)
+    g.precond_half(kind, 0, r, out)
+    y = pc.forward(w["f"])
+    assert relmax(to_np(out), y) <= 1e-12
+    g.precond_half(kind, 2, r, out)
+    yt = O.dsolve_t(2, n, p, pc.dirs_b, diags, pc.piv, w["f"])
+    assert relmax(to_np(out), yt) <= 1e-12
