@@ -6,7 +6,7 @@
 namespace psw {
 
 // steps of coefficient loads each lane keeps in flight
-constexpr int kFast2dDepth = 16;
+constexpr int kFast2dDepth = 12;
 
 struct Fast2dDiag {
     const double *d[5];

@@ -134,37 +134,44 @@ __global__ void k_pack2d(PassGeom g, int R, int transposed, Fast2dDiag dg, const
         s_ax[base + sl] = from_f64<S>(ax);
         s_ay[base + sl] = from_f64<S>(ay);
     }
-    // partner data of the coupled start faces: [inv, a'_{Q->P}, a'_{Q->upstream}] per row / column
+    // partner data of the coupled start faces, per row (x face) / column (y face):
+    // [1/Piv_Q, a'_{Q->P}, a'_{Q->upstream along the face}, 1/(1 - a'_{P->Q} a'_{Q->P})]
     S *fc = face + foff[blockIdx.x];
     for (int y = threadIdx.x; y < F.ly; y += blockDim.x) {
-        double v0 = 0, v1 = 0, v2 = 0;
+        double v0 = 0, v1 = 0, v2 = 0, v3 = 1;
         if (cx) {
             const int gx = gx_of(F, -1), gy = gy_of(F, y);
-            const int64_t Q = lin2(n0, gx, gy);
+            const int64_t Q = lin2(n0, gx, gy), P = lin2(n0, gx_of(F, 0), gy);
             v0 = 1.0 / piv[Q];
             v1 = dg.d[dkk(0, +F.d0)][Q] * v0;
             if (y > 0 || cy) v2 = dg.d[dkk(1, -F.d1)][Q] * v0;
+            const double apq = dg.d[dkk(0, -F.d0)][P] / piv[P];
+            v3 = 1.0 / (1.0 - apq * v1);
         }
-        fc[y] = from_f64<S>(v0);
-        fc[F.ly + y] = from_f64<S>(v1);
-        fc[2 * F.ly + y] = from_f64<S>(v2);
+        fc[4 * y + 0] = from_f64<S>(v0);
+        fc[4 * y + 1] = from_f64<S>(v1);
+        fc[4 * y + 2] = from_f64<S>(v2);
+        fc[4 * y + 3] = from_f64<S>(v3);
     }
-    S *fr = fc + 3 * F.ly;
+    S *fr = fc + 4 * F.ly;
     for (int x = threadIdx.x; x < F.lx; x += blockDim.x) {
-        double v0 = 0, v1 = 0, v2 = 0;
+        double v0 = 0, v1 = 0, v2 = 0, v3 = 1;
         if (cy) {
             const int gx = gx_of(F, x), gy = gy_of(F, -1);
-            const int64_t Q = lin2(n0, gx, gy);
+            const int64_t Q = lin2(n0, gx, gy), P = lin2(n0, gx, gy_of(F, 0));
             v0 = 1.0 / piv[Q];
             v1 = dg.d[dkk(1, +F.d1)][Q] * v0;
             if (x > 0 || cx) v2 = dg.d[dkk(0, -F.d0)][Q] * v0;
+            const double apq = dg.d[dkk(1, -F.d1)][P] / piv[P];
+            v3 = 1.0 / (1.0 - apq * v1);
         }
-        fr[x] = from_f64<S>(v0);
-        fr[F.lx + x] = from_f64<S>(v1);
-        fr[2 * F.lx + x] = from_f64<S>(v2);
+        fr[4 * x + 0] = from_f64<S>(v0);
+        fr[4 * x + 1] = from_f64<S>(v1);
+        fr[4 * x + 2] = from_f64<S>(v2);
+        fr[4 * x + 3] = from_f64<S>(v3);
     }
     if (threadIdx.x == 0) {
-        S *fk = fr + 3 * F.lx;
+        S *fk = fr + 4 * F.lx;
         double v0 = 0, v1 = 0, v2 = 0;
         if (cx && cy) {
             const int64_t Q = lin2(n0, gx_of(F, -1), gy_of(F, -1));
@@ -191,9 +198,45 @@ template <typename S, typename TIN, typename TOUT> struct Fast2dArgs {
     int pitch_max;
 };
 
-template <typename T> __device__ __forceinline__ T shfl_up1(T v) { return __shfl_up(v, 1, 64); }
+// value of lane j-1 in lane j (0 in lane 0): one DPP wave shift per 32 bits
+__device__ __forceinline__ float lane_up(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double lane_up(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), 0x138, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 
-template <int R, typename T, typename S, typename TIN, typename TOUT>
+// Raw buffer loads of one lane's R coefficients: lanes with nothing to do
+// pass an offset beyond the buffer's range and read zero without a memory
+// access, so every ring refill is an unconditional instruction.
+constexpr int kBufCfg = 0x00020000; // gfx9 buffer resource word 3
+constexpr int kOutOfRange = 0x7ffffff0;
+constexpr int kStageBatch = 16; // global loads in flight per thread while staging
+
+template <typename V> __device__ __forceinline__ V ldbuf(__amdgpu_buffer_rsrc_t r, int off);
+template <> __device__ __forceinline__ double2 ldbuf<double2>(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ double ldbuf<double>(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ float2 ldbuf<float2>(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ float ldbuf<float>(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ uint32_t ldbuf<uint32_t>(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+template <> __device__ __forceinline__ uint16_t ldbuf<uint16_t>(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+}
+
+template <int R, typename T, typename S, typename TIN, typename TOUT, bool SC, bool CPL>
 __global__ void __launch_bounds__(256) k_fast2d(Fast2dArgs<S, TIN, TOUT> A) {
     using V = typename Pack<S, R>::V;
     constexpr int D = kFast2dDepth;
@@ -201,24 +244,40 @@ __global__ void __launch_bounds__(256) k_fast2d(Fast2dArgs<S, TIN, TOUT> A) {
     const PassGeom &g = A.g;
     const TileDesc td = g.tiles[blockIdx.x];
     const Frame2 F = frame2(g, td);
-    const bool cx = A.coupled && F.cx, cy = A.coupled && F.cy;
+    const bool cx = CPL && F.cx, cy = CPL && F.cy;
     const int lx = F.lx, ly = F.ly;
     // LDS: vector tile in global orientation with a one-point ring, pitch chosen
     // so that the wave's anti-diagonal reads hit distinct banks
     int pitch = lx + 2;
     if ((R * pitch) & 1) ++pitch;
     T *vt = reinterpret_cast<T *>(smem);
-    T *fx = vt + (size_t)(ly + 2) * pitch; // x-face partners: inv, a'QP, a'Qy (ly each)
-    T *fy = fx + 3 * ly;                   // y-face partners (lx each)
-    T *fk = fy + 3 * lx;                   // cross point partner
+    T *fx = vt + (size_t)(ly + 2) * pitch; // x-face partner records (4 values per row)
+    T *fy = fx + 4 * ly;                   // y-face partner records (4 values per column)
+    T *fk = fy + 4 * lx;                   // cross point partner (3)
+    const int sink = (int)((fk + 4) - vt);  // scratch slot for writes of idle lanes
     const int n0 = g.n[0];
     const int tid = threadIdx.x, nth = blockDim.x;
 
-    // ---- stage the input tile (+ partners) into LDS, coalesced along rows
-    for (int idx = tid; idx < lx * ly; idx += nth) {
-        const int row = idx / lx, col = idx - row * lx;
-        const int gx = F.lox + col, gy = F.loy + row;
-        vt[(row + 1) * pitch + col + 1] = cvt<T>(A.in[lin2(n0, gx, gy)]);
+    // ---- stage the input tile (+ partners) into LDS: each wave takes whole
+    // rows in 64-column chunks and keeps kStageBatch loads in flight
+    const int wid = tid >> 6, ln = tid & 63, nw = nth >> 6;
+    const int cpr = (lx + 63) >> 6; // 64-column chunks per row
+    const int nitems = ly * cpr;
+    for (int it0 = wid; it0 < nitems; it0 += nw * kStageBatch) {
+        T v[kStageBatch];
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int it = it0 + u * nw;
+            const int row = it / cpr, col = (it - row * cpr) * 64 + ln;
+            const bool ok = it < nitems && col < lx;
+            v[u] = ok ? cvt<T>(A.in[lin2(n0, F.lox + col, F.loy + row)]) : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int it = it0 + u * nw;
+            const int row = it / cpr, col = (it - row * cpr) * 64 + ln;
+            if (it < nitems && col < lx) vt[(row + 1) * pitch + col + 1] = v[u];
+        }
     }
     if (cx) {
         const int gx = gx_of(F, -1), col = F.d0 > 0 ? 0 : lx + 1;
@@ -233,7 +292,7 @@ __global__ void __launch_bounds__(256) k_fast2d(Fast2dArgs<S, TIN, TOUT> A) {
         vt[row * pitch + col] = cvt<T>(A.in[lin2(n0, gx_of(F, -1), gy_of(F, -1))]);
     }
     const S *fsrc = A.face + A.foff[blockIdx.x];
-    for (int i = tid; i < 3 * (lx + ly) + 3; i += nth) fx[i] = cvt<T>(fsrc[i]);
+    for (int i = tid; i < 4 * (lx + ly) + 3; i += nth) fx[i] = cvt<T>(fsrc[i]);
     __syncthreads();
 
     // ---- the recurrence: wave 0
@@ -241,144 +300,258 @@ __global__ void __launch_bounds__(256) k_fast2d(Fast2dArgs<S, TIN, TOUT> A) {
         const int lane = tid;
         const int L = (ly + R - 1) / R;
         const int nr = lane < L ? min(R, ly - R * lane) : 0;
+        const int rlast = nr > 0 ? nr - 1 : 0;
         const int nsteps = lx + L - 1;
         const int64_t sbase = A.toff[blockIdx.x];
-        const V *pinv = reinterpret_cast<const V *>(A.s_inv + sbase);
-        const V *pax = reinterpret_cast<const V *>(A.s_ax + sbase);
-        const V *pay = reinterpret_cast<const V *>(A.s_ay + sbase);
-        const bool sc = A.scale_by_piv != 0;
+        const int nbytes = (lx + L - 1 + D) * 64 * R * (int)sizeof(S);
+        const __amdgpu_buffer_rsrc_t rinv = __builtin_amdgcn_make_buffer_rsrc((void *)(A.s_inv + sbase), 0, nbytes, kBufCfg);
+        const __amdgpu_buffer_rsrc_t rax = __builtin_amdgcn_make_buffer_rsrc((void *)(A.s_ax + sbase), 0, nbytes, kBufCfg);
+        const __amdgpu_buffer_rsrc_t ray = __builtin_amdgcn_make_buffer_rsrc((void *)(A.s_ay + sbase), 0, nbytes, kBufCfg);
+        constexpr bool sc = SC;
+        const int vbytes = R * (int)sizeof(S);
+        auto boff = [&](int s) -> int {
+            const int x = s - lane;
+            return (nr > 0 && x >= 0 && x < lx) ? (s * 64 + lane) * vbytes : kOutOfRange;
+        };
         // LDS addressing in local orientation
         const int cstep = F.d0 > 0 ? 1 : -1, col0 = F.d0 > 0 ? 1 : lx; // column of local x = 0
         const int rstep = F.d1 > 0 ? pitch : -pitch, row0 = (F.d1 > 0 ? 1 : ly) * pitch;
-        const int rowbase = row0 + rstep * (R * lane);
+        const int lane_c = min(lane, L - 1); // idle lanes address the last active lane's rows
+        const int rowbase = row0 + rstep * (R * lane_c);
         V ri[D], ra[D], rb[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            const int x = k - lane;
-            const bool act = nr > 0 && x >= 0 && x < lx;
-            if (act) {
-                const int64_t o = (int64_t)k * 64 + lane;
-                if (!sc) ri[k] = pinv[o];
-                ra[k] = pax[o];
-                rb[k] = pay[o];
-            }
+            const int o = boff(k);
+            if (!sc) ri[k] = ldbuf<V>(rinv, o);
+            ra[k] = ldbuf<V>(rax, o);
+            rb[k] = ldbuf<V>(ray, o);
         }
         T left[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) left[r] = T(0);
-        T last = T(0);    // value of this lane's last row at the previous step
-        T xplast = T(0);  // x-face partner of this lane's last row (set at x = 0)
-        T yprev = T(0);   // y-face partner at the previous column (lane 0)
-        for (int s0 = 0; s0 < nsteps; s0 += D) {
+        T last = T(0);   // value of this lane's last row at the previous step
+        T xplast = T(0); // x-face partner of this lane's last row (set at x = 0)
+        T yprev = T(0);  // y-face partner at the previous column (lane 0, row 0)
+
+        // ---- step 0: only lane 0 works (local column 0); it holds the cross point
+        {
+            const int x = -lane;
+            if (lane == 0 && nr > 0 && lx > 0) {
+                T up = T(0), upx = T(0);
 #pragma unroll
-            for (int k = 0; k < D; ++k) {
-                const int s = s0 + k;
-                if (s < nsteps) {
-                    const T up_in = shfl_up1(last);
-                    const T upx_in = shfl_up1(xplast);
-                    const int x = s - lane;
-                    if (nr > 0 && x >= 0 && x < lx) {
-                        T up = (lane > 0) ? up_in : T(0);
-                        T upx = (lane > 0) ? upx_in : T(0);
-                        const int cidx = col0 + cstep * x;
-                        T v = T(0), vq = T(0);
+                for (int r = 0; r < R; ++r) {
+                    if (r < nr) {
+                        const int y = r;
+                        const int a = rowbase + rstep * r + col0;
+                        const T iv = sc ? T(1) : elem<T>(ri[0], r);
+                        const T ax = elem<T>(ra[0], r), ay = elem<T>(rb[0], r);
+                        const T rhs = sc ? vt[a] : iv * vt[a];
+                        T v, vq = T(0);
+                        if (cx && y == 0 && cy) {
+                            // cross point: A=(0,0), B=(-1,0), C=(0,-1), D=(-1,-1)
+                            const int aq = a - cstep, ac = a - rstep, ad = a - rstep - cstep;
+                            const T ivq = fx[0], aqp = fx[1], aqy = fx[2];
+                            const T ivc = fy[0], acp = fy[1], acd = fy[2];
+                            const T ivd = fk[0], adb = fk[1], adc = fk[2];
+                            const T rq = sc ? vt[aq] : ivq * vt[aq];
+                            const T rc = sc ? vt[ac] : ivc * vt[ac];
+                            const T rd = sc ? vt[ad] : ivd * vt[ad];
+                            T M[4][4] = {{T(1), -ax, -ay, T(0)},
+                                         {-aqp, T(1), T(0), -aqy},
+                                         {-acp, T(0), T(1), -acd},
+                                         {T(0), -adb, -adc, T(1)}};
+                            T b[4] = {rhs, rq, rc, rd};
 #pragma unroll
-                        for (int r = 0; r < R; ++r) {
-                            if (r < nr) {
-                                const int y = R * lane + r;
-                                const int a = rowbase + rstep * r + cidx;
-                                const T iv = sc ? T(1) : elem<T>(ri[k], r);
-                                const T ax = elem<T>(ra[k], r), ay = elem<T>(rb[k], r);
-                                const T rhs = sc ? vt[a] : iv * vt[a];
-                                if (x == 0 && cx) {
-                                    // x-face partner Q = (-1, y)
-                                    const int aq = a - cstep;
-                                    const T ivq = fx[y], aqp = fx[ly + y], aqy = fx[2 * ly + y];
-                                    const T rq = sc ? vt[aq] : ivq * vt[aq];
-                                    if (y == 0 && cy) {
-                                        // cross point: A=(0,0), B=(-1,0), C=(0,-1), D=(-1,-1)
-                                        const T ivc = fy[0], acp = fy[lx], acd = fy[2 * lx];
-                                        const T ivd = fk[0], adb = fk[1], adc = fk[2];
-                                        const int ac = a - rstep, ad = a - rstep - cstep;
-                                        const T rc = sc ? vt[ac] : ivc * vt[ac];
-                                        const T rd = sc ? vt[ad] : ivd * vt[ad];
-                                        // rows: A: yA - ax yB - ay yC = rhs ; B: yB - aqp yA - aqy yD = rq
-                                        //       C: yC - acp yA - acd yD = rc ; D: yD - adb yB - adc yC = rd
-                                        T M[4][4] = {{T(1), -ax, -ay, T(0)},
-                                                     {-aqp, T(1), T(0), -aqy},
-                                                     {-acp, T(0), T(1), -acd},
-                                                     {T(0), -adb, -adc, T(1)}};
-                                        T b[4] = {rhs, rq, rc, rd};
+                            for (int p = 0; p < 4; ++p) {
+                                const T ip = T(1) / M[p][p];
 #pragma unroll
-                                        for (int p = 0; p < 4; ++p) {
-                                            const T ip = T(1) / M[p][p];
+                                for (int i = p + 1; i < 4; ++i) {
+                                    const T l = M[i][p] * ip;
 #pragma unroll
-                                            for (int i = p + 1; i < 4; ++i) {
-                                                const T l = M[i][p] * ip;
-#pragma unroll
-                                                for (int jj = p + 1; jj < 4; ++jj) M[i][jj] -= l * M[p][jj];
-                                                b[i] -= l * b[p];
-                                            }
-                                        }
-#pragma unroll
-                                        for (int i = 3; i >= 0; --i) {
-                                            T acc = b[i];
-#pragma unroll
-                                            for (int jj = i + 1; jj < 4; ++jj) acc -= M[i][jj] * b[jj];
-                                            b[i] = acc / M[i][i];
-                                        }
-                                        v = b[0];
-                                        vq = b[1];
-                                        yprev = b[2];
-                                    } else {
-                                        const T bp = rhs + ay * up;
-                                        const T bq = rq + aqy * upx;
-                                        const T det = T(1) - ax * aqp;
-                                        v = (bp + ax * bq) / det;
-                                        vq = (bq + aqp * bp) / det;
-                                    }
-                                } else if (y == 0 && cy) {
-                                    // y-face partner Q = (x, -1), chained along x
-                                    const int aq = a - rstep;
-                                    const T ivq = fy[x], aqp = fy[lx + x], aqx = fy[2 * lx + x];
-                                    const T rq = sc ? vt[aq] : ivq * vt[aq];
-                                    const T bp = rhs + ax * left[r];
-                                    const T bq = rq + aqx * yprev;
-                                    const T det = T(1) - ay * aqp;
-                                    v = (bp + ay * bq) / det;
-                                    vq = (bq + aqp * bp) / det;
-                                    yprev = vq;
-                                } else {
-                                    v = rhs + ax * left[r] + ay * up;
+                                    for (int jj = p + 1; jj < 4; ++jj) M[i][jj] -= l * M[p][jj];
+                                    b[i] -= l * b[p];
                                 }
-                                vt[a] = v;
-                                left[r] = v;
-                                up = v;
-                                upx = vq;
                             }
+#pragma unroll
+                            for (int i = 3; i >= 0; --i) {
+                                T acc = b[i];
+#pragma unroll
+                                for (int jj = i + 1; jj < 4; ++jj) acc -= M[i][jj] * b[jj];
+                                b[i] = acc / M[i][i];
+                            }
+                            v = b[0];
+                            vq = b[1];
+                            yprev = b[2];
+                        } else if (cx) {
+                            const int aq = a - cstep;
+                            const T ivq = fx[4 * y], aqp = fx[4 * y + 1], aqy = fx[4 * y + 2], idt = fx[4 * y + 3];
+                            const T rq = sc ? vt[aq] : ivq * vt[aq];
+                            const T bq = rq + aqy * upx;
+                            v = idt * (rhs + ax * bq + ay * up);
+                            vq = bq + aqp * v;
+                        } else if (y == 0 && cy) {
+                            const int aq = a - rstep;
+                            const T ivq = fy[0], aqp = fy[1], idt = fy[3];
+                            const T rq = sc ? vt[aq] : ivq * vt[aq];
+                            v = idt * (rhs + ay * rq);
+                            vq = rq + aqp * v;
+                            yprev = vq;
+                        } else {
+                            v = rhs + ay * up;
                         }
-                        last = up;
-                        if (x == 0) xplast = upx;
-                    }
-                    // refill this ring slot with step s + D
-                    const int xn = s + D - lane;
-                    if (nr > 0 && xn >= 0 && xn < lx) {
-                        const int64_t o = (int64_t)(s + D) * 64 + lane;
-                        if (!sc) ri[k] = pinv[o];
-                        ra[k] = pax[o];
-                        rb[k] = pay[o];
+                        vt[a] = v;
+                        left[r] = v;
+                        up = v;
+                        upx = vq;
                     }
                 }
+                last = up;
+                xplast = upx;
+            }
+            (void)x;
+            const int o = boff(D);
+            if (!sc) ri[0] = ldbuf<V>(rinv, o);
+            ra[0] = ldbuf<V>(rax, o);
+            rb[0] = ldbuf<V>(ray, o);
+        }
+
+        // ---- prologue, steps 1..Ps-1 (lane j meets the x face at step j):
+        // straight-line, face pairs formed with selects, idle lanes write to a
+        // scratch slot, so the coefficient loads stay D steps ahead.
+        const int Ps = 1 + D * ((L - 1 + D - 1) / D);
+        for (int s0 = 1; s0 < Ps; s0 += D) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const int slot = (1 + k) % D;
+                const int s = s0 + k;
+                T up = lane_up(last);
+                T upx = lane_up(xplast);
+                const int x = s - lane;
+                const bool act = nr > 0 && x >= 0 && x < lx;
+                const int xc = min(max(x, 0), lx - 1);
+                const int cidx = col0 + cstep * xc;
+                const bool isx0 = cx && x == 0;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int rr = min(r, rlast);
+                    const bool valid = act && r < nr;
+                    const int y = R * lane_c + rr;
+                    const int a = rowbase + rstep * rr + cidx;
+                    const T iv = sc ? T(1) : elem<T>(ri[slot], r);
+                    const T ax = elem<T>(ra[slot], r), ay = elem<T>(rb[slot], r);
+                    const T rhs = sc ? vt[a] : iv * vt[a];
+                    const bool isx = isx0;
+                    const bool isy = cy && y == 0 && !isx;
+                    // partner record of this point's face (x face: row y, y face: column x)
+                    const T *fp = isx ? fx + 4 * y : fy + 4 * xc;
+                    const T ivq = fp[0], aqp = fp[1], aqu = fp[2], idt = fp[3];
+                    const int aq = a - (isx ? cstep : rstep);
+                    const T vq_in = vt[aq];
+                    const T rq = sc ? vq_in : ivq * vq_in;
+                    const T bq = rq + aqu * (isx ? upx : yprev);
+                    const bool face = isx || isy;
+                    const T L0 = isx ? bq : left[r];
+                    const T U0 = isy ? bq : up;
+                    const T c0 = face ? idt : T(1);
+                    const T v = c0 * (rhs + ax * L0 + ay * U0);
+                    const T vq = bq + aqp * v;
+                    yprev = (valid && isy) ? vq : yprev;
+                    vt[valid ? a : sink] = v;
+                    left[r] = valid ? v : left[r];
+                    up = valid ? v : up;
+                    upx = valid ? vq : upx;
+                }
+                last = act ? up : last;
+                xplast = (act && x == 0) ? upx : xplast;
+                // refill this ring slot with step s + D
+                const int o = boff(s + D);
+                if (!sc) ri[slot] = ldbuf<V>(rinv, o);
+                ra[slot] = ldbuf<V>(rax, o);
+                rb[slot] = ldbuf<V>(ray, o);
+            }
+        }
+
+        // ---- main phase, steps Ps..nsteps-1: every active point has x >= 1, so
+        // only lane 0 (row 0) carries a face, the y-face chain; its partner
+        // record is read at lane 0's column by all lanes (an LDS broadcast).
+        const bool l0cy = (lane == 0) && cy;
+        const int rowq = row0 - rstep; // LDS row of the y-face partners
+        // right-hand sides of the next step, read before this step's writes
+        T rn[R];
+        {
+            const int a0 = rowbase + col0 + cstep * min(max(Ps - lane, 0), lx - 1);
+#pragma unroll
+            for (int r = 0; r < R; ++r) rn[r] = vt[a0 + rstep * min(r, rlast)];
+        }
+        for (int s0 = Ps; s0 < nsteps; s0 += D) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const int slot = (1 + k) % D;
+                const int s = s0 + k;
+                const T up_in = lane_up(last);
+                const int x = s - lane;
+                const bool act = nr > 0 && x < lx;
+                const int a0 = rowbase + col0 + cstep * min(x, lx - 1);
+                T rc[R];
+                {
+                    const int an = rowbase + col0 + cstep * min(x + 1, lx - 1);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        rc[r] = rn[r];
+                        rn[r] = vt[an + rstep * min(r, rlast)];
+                    }
+                }
+                const int x0 = min(s, lx - 1);
+                const T *fp = fy + 4 * x0;
+                const T ivq = fp[0], aqp = fp[1], aqu = fp[2], idt = fp[3];
+                const T vq_in = vt[rowq + col0 + cstep * x0];
+                const T bq = (sc ? vq_in : ivq * vq_in) + aqu * yprev;
+                T up = l0cy ? bq : up_in;
+                const T c0 = l0cy ? idt : T(1);
+                T v0 = T(0);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const bool valid = act && r < nr;
+                    const int a = a0 + rstep * min(r, rlast);
+                    const T iv = sc ? T(1) : elem<T>(ri[slot], r);
+                    const T ax = elem<T>(ra[slot], r), ay = elem<T>(rb[slot], r);
+                    const T rhs = sc ? rc[r] : iv * rc[r];
+                    T v = rhs + ax * left[r] + ay * up;
+                    if (r == 0) {
+                        v = c0 * v;
+                        v0 = v;
+                    }
+                    vt[valid ? a : sink] = v;
+                    left[r] = v;
+                    up = (r < nr) ? v : up;
+                }
+                last = up;
+                yprev = bq + aqp * v0;
+                const int o = boff(s + D);
+                if (!sc) ri[slot] = ldbuf<V>(rinv, o);
+                ra[slot] = ldbuf<V>(rax, o);
+                rb[slot] = ldbuf<V>(ray, o);
             }
         }
     }
     __syncthreads();
 
-    // ---- write the tile back, coalesced along rows
+    // ---- write the tile back, same row-chunk order
     const T cs = (T)A.cscale;
-    for (int idx = tid; idx < lx * ly; idx += nth) {
-        const int row = idx / lx, col = idx - row * lx;
-        A.out[lin2(n0, F.lox + col, F.loy + row)] = (TOUT)(cs * vt[(row + 1) * pitch + col + 1]);
+    for (int it0 = wid; it0 < nitems; it0 += nw * kStageBatch) {
+        T v[kStageBatch];
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int it = it0 + u * nw;
+            const int row = it / cpr, col = (it - row * cpr) * 64 + ln;
+            v[u] = (it < nitems && col < lx) ? vt[(row + 1) * pitch + col + 1] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int it = it0 + u * nw;
+            const int row = it / cpr, col = (it - row * cpr) * 64 + ln;
+            if (it < nitems && col < lx) A.out[lin2(n0, F.lox + col, F.loy + row)] = (TOUT)(cs * v[u]);
+        }
     }
 }
 
@@ -473,7 +646,7 @@ __global__ void __launch_bounds__(256) k_end_faces2d_fast(EndFaceArgs<T, S, TIN,
 size_t fast2d_lds_bytes(int lx, int ly, int R, size_t elem) {
     int pitch = lx + 2;
     if ((R * pitch) & 1) ++pitch;
-    return elem * ((size_t)(ly + 2) * pitch + 3 * (size_t)(lx + ly) + 3);
+    return elem * ((size_t)(ly + 2) * pitch + 4 * (size_t)(lx + ly) + 8);
 }
 
 hipError_t launch_pack2d(const PassGeom &g, Store s, int R, bool transposed, const double *const *diag,
@@ -494,7 +667,7 @@ hipError_t launch_pack2d(const PassGeom &g, Store s, int R, bool transposed, con
     return hipGetLastError();
 }
 
-template <int R, typename T, typename S, typename TIN, typename TOUT>
+template <int R, typename T, typename S, typename TIN, typename TOUT, bool SC, bool CPL>
 static hipError_t fast_impl(const Fast2dPass &p, const void *in, bool scale_by_piv, void *out, double cscale,
                             hipStream_t st) {
     Fast2dArgs<S, TIN, TOUT> A{};
@@ -511,14 +684,24 @@ static hipError_t fast_impl(const Fast2dPass &p, const void *in, bool scale_by_p
     A.coupled = p.coupled ? 1 : 0;
     A.cscale = cscale;
     size_t sm = fast2d_lds_bytes(p.lxmax, p.lymax, R, sizeof(T));
-    hipLaunchKernelGGL((k_fast2d<R, T, S, TIN, TOUT>), dim3(p.g.ntiles), dim3(256), sm, st, A);
+    hipLaunchKernelGGL((k_fast2d<R, T, S, TIN, TOUT, SC, CPL>), dim3(p.g.ntiles), dim3(256), sm, st, A);
     return hipGetLastError();
+}
+
+template <int R, typename T, typename S, typename TIN, typename TOUT>
+static hipError_t fast_flags(const Fast2dPass &p, const void *in, bool scale, void *out, double cs, hipStream_t st) {
+    if (scale) {
+        if (p.coupled) return fast_impl<R, T, S, TIN, TOUT, true, true>(p, in, scale, out, cs, st);
+        return fast_impl<R, T, S, TIN, TOUT, true, false>(p, in, scale, out, cs, st);
+    }
+    if (p.coupled) return fast_impl<R, T, S, TIN, TOUT, false, true>(p, in, scale, out, cs, st);
+    return fast_impl<R, T, S, TIN, TOUT, false, false>(p, in, scale, out, cs, st);
 }
 
 template <typename T, typename S, typename TIN, typename TOUT>
 static hipError_t fast_r(const Fast2dPass &p, const void *in, bool scale, void *out, double cs, hipStream_t st) {
-    if (p.R == 1) return fast_impl<1, T, S, TIN, TOUT>(p, in, scale, out, cs, st);
-    return fast_impl<2, T, S, TIN, TOUT>(p, in, scale, out, cs, st);
+    if (p.R == 1) return fast_flags<1, T, S, TIN, TOUT>(p, in, scale, out, cs, st);
+    return fast_flags<2, T, S, TIN, TOUT>(p, in, scale, out, cs, st);
 }
 
 hipError_t launch_fast2d(const Fast2dPass &p, Store s, const void *in, bool in_f64, bool scale_by_piv, void *out,

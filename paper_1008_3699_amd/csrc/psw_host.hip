@@ -213,7 +213,7 @@ psw_status fast_setup(psw_problem *P, PrecState &S, hipStream_t st) {
             toff.push_back(t);
             foff.push_back(f);
             t += (int64_t)(lx + L - 1 + kFast2dDepth) * 64 * R;
-            f += 3 * (int64_t)(lx + ly) + 3;
+            f += 4 * (int64_t)(lx + ly) + 3;
             f = (f + 7) & ~(int64_t)7;
         }
     Store s = store_of(P->prec);
