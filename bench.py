@@ -113,7 +113,7 @@ def main():
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_sweep_start (forward half-sweep)", "kernel_ms": round(k_ms, 4),
+                "kernel": "k_fast2d<2,double,...,SC=false,CPL=true> (forward start-coupled half-sweep)", "kernel_ms": round(k_ms, 4),
                 "bytes_per_point": bpp}
 
     cpu = None
