@@ -95,19 +95,22 @@ def main():
     half_sweeps = sum(4 * (it + 1) for it in iters)
     value = N * half_sweeps / elapsed / 1e9
 
-    # dominant kernel: forward start-coupled half-sweep, timed with HIP events on its stream
+    # dominant kernel: forward start-coupled half-sweep, timed with HIP events on its stream.
+    # The four half-sweeps run in turn, as inside CG, so the timed pass finds the
+    # Infinity Cache holding the other passes' data (their coefficients exceed it).
     r = torch.randn(N, dtype=torch.float64, device=dev)
     y = torch.empty_like(r)
-    for _ in range(3):
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.kernel_reps)]
+    for k in range(args.kernel_reps + 2):
+        if k >= 2:
+            evs[k - 2][0].record(stream)
         g.precond_half(args.precond, 0, r, y)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.kernel_reps):
-        g.precond_half(args.precond, 0, r, y)
-    e1.record(stream)
+        if k >= 2:
+            evs[k - 2][1].record(stream)
+        for which in (1, 2, 3):
+            g.precond_half(args.precond, which, r, y)
     torch.cuda.synchronize()
-    k_ms = e0.elapsed_time(e1) / args.kernel_reps
+    k_ms = sum(a.elapsed_time(b) for a, b in evs) / args.kernel_reps
     bpp = {"f64": 40, "f32": 28, "bf16": 20}[args.prec]  # r(8) + Piv + 2 upstream couplings + y
     alg_bytes = bpp * N
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9

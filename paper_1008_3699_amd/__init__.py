@@ -197,3 +197,17 @@ class Problem:
         d = info.as_dict()
         d["status"] = st
         return d
+
+
+def batch_solve(problems, fs, us, precond="ssor", rtol=1e-8, maxit=100000, method="cg", stream=None):
+    """Solve several problems together (psw_batch_solve); returns a list of info dicts."""
+    n = len(problems)
+    hp = (ctypes.c_void_p * n)(*[p.handle.value for p in problems])
+    fp = (ctypes.c_void_p * n)(*[_ptr(f, p.N, "f").value for f, p in zip(fs, problems)])
+    up = (ctypes.c_void_p * n)(*[_ptr(u, p.N, "u").value for u, p in zip(us, problems)])
+    infos = (Info * n)()
+    st = lib().psw_batch_solve(n, hp, fp, up, _METHOD[method], _KIND[precond], float(rtol), int(maxit), infos,
+                               _stream(stream))
+    if st not in (0, -4):
+        raise PswError(st, "psw_batch_solve")
+    return [i.as_dict() for i in infos]

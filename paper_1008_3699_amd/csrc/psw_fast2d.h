@@ -44,3 +44,48 @@ hipError_t launch_end_interior(const PassGeom &g, Store s, const void *const *di
                                bool in_f64, bool scale_by_piv, void *out, bool out_f64, hipStream_t st);
 
 } // namespace psw
+
+namespace psw {
+
+// ---------------------------------------------------------------- batches
+// A batch refers to problems that each own their buffers; device tables of
+// pointers let one launch cover the tiles (or vector chunks) of all of them.
+enum BSlot { kSlotR = 0, kSlotZ = 1, kSlotZ1 = 2, kSlotY1 = 3, kSlotY2 = 4, kSlotP = 5, kSlotQ = 6, kSlotX = 7,
+             kSlotF = 8 };
+
+struct BProb {
+    int n0, n1;
+    int64_t N;
+    const void *s_inv[4], *s_ax[4], *s_ay[4], *face[4]; // packed passes (storage precision)
+    const int64_t *toff, *foff;                         // per tile of this problem
+    const void *diagS[5];                               // storage-precision couplings (end faces)
+    const void *pivS;                                   // storage-precision pivots
+    const double *diag64[5];                            // FP64 operator
+    void *vec[9];                                       // r, z, z1, y1, y2, p, q, x, f
+    double *scal;                                       // 0,1: r.z by parity; 2: p.q; 3: r.r; 4: f.f
+    int *flags;                                         // 0: active, 1: iterations, 2: status
+    double c;                                           // preconditioner scale
+    int chunk0, nchunk;                                 // this problem's vector chunks
+};
+
+struct BTile {
+    TileDesc td;
+    int prob; // index into the problem table
+    int tix;  // tile index within the problem
+};
+
+struct BChunk {
+    int prob;
+    int len;
+    int64_t start;
+};
+
+// one pass of the preconditioner over all tiles in `tiles` (same R)
+hipError_t launch_b_fast2d(const BTile *tiles, int ntiles, const BProb *probs, const int sig[2], int pass, int R,
+                           Store s, int in_slot, bool in_f64, int out_slot, bool out_f64, bool scale_by_piv,
+                           bool coupled, bool cs_from_prob, size_t lds, hipStream_t st);
+// end faces and cross points of an end-coupled pass over all tiles
+hipError_t launch_b_end2d(const BTile *tiles, int ntiles, const BProb *probs, const int sig[2], Store s, int in_slot,
+                          bool in_f64, int out_slot, bool out_f64, bool scale_by_piv, int facemax, hipStream_t st);
+
+} // namespace psw

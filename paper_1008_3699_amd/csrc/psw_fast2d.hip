@@ -26,6 +26,9 @@
 
 namespace psw {
 
+// global-memory (address space 1) object type
+template <typename T> using GP = __attribute__((address_space(1))) T;
+
 namespace {
 
 __device__ __forceinline__ float bf16f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
@@ -91,6 +94,19 @@ __device__ __forceinline__ Frame2 frame2(const PassGeom &g, const TileDesc &td) 
     return f;
 }
 
+__device__ __forceinline__ Frame2 frame2n(const int sig[2], int n0, int n1, const TileDesc &td) {
+    Frame2 f;
+    f.d0 = sig[0] * (td.par[0] ? -1 : 1);
+    f.d1 = sig[1] * (td.par[1] ? -1 : 1);
+    f.lx = td.len[0];
+    f.ly = td.len[1];
+    f.lox = td.lo[0];
+    f.loy = td.lo[1];
+    f.cx = f.d0 > 0 ? td.lo[0] > 0 : td.lo[0] + td.len[0] < n0;
+    f.cy = f.d1 > 0 ? td.lo[1] > 0 : td.lo[1] + td.len[1] < n1;
+    return f;
+}
+
 // global coordinate of local coordinate l (l = -1 is the partner across the start face)
 __device__ __forceinline__ int gx_of(const Frame2 &f, int x) { return f.d0 > 0 ? f.lox + x : f.lox + f.lx - 1 - x; }
 __device__ __forceinline__ int gy_of(const Frame2 &f, int y) { return f.d1 > 0 ? f.loy + y : f.loy + f.ly - 1 - y; }
@@ -102,16 +118,12 @@ __device__ __forceinline__ int gy_of(const Frame2 &f, int y) { return f.d1 > 0 ?
 // coupled start faces.  transposed: the couplings are those of the upstream
 // neighbour towards the point (a_{R->P}) and no face is coupled.
 template <typename S>
-__global__ void k_pack2d(PassGeom g, int R, int transposed, Fast2dDiag dg, const double *__restrict__ piv,
-                         const int64_t *__restrict__ toff, const int64_t *__restrict__ foff, S *s_inv, S *s_ax,
-                         S *s_ay, S *face) {
-    const TileDesc td = g.tiles[blockIdx.x];
-    const Frame2 F = frame2(g, td);
+__device__ void pack2d_body(const Frame2 &F, int n0, int R, int transposed, const Fast2dDiag &dg,
+                            const double *__restrict__ piv, S *s_inv, S *s_ax, S *s_ay, S *fc) {
     const bool cx = !transposed && F.cx, cy = !transposed && F.cy;
     const int L = (F.ly + R - 1) / R;
     const int64_t nslots = (int64_t)(F.lx + L - 1 + kFast2dDepth) * 64 * R;
-    const int64_t base = toff[blockIdx.x];
-    const int n0 = g.n[0];
+    const int64_t base = 0;
     for (int64_t sl = threadIdx.x; sl < nslots; sl += blockDim.x) {
         const int r = (int)(sl % R), j = (int)((sl / R) % 64);
         const int s = (int)(sl / (64 * R));
@@ -136,7 +148,6 @@ __global__ void k_pack2d(PassGeom g, int R, int transposed, Fast2dDiag dg, const
     }
     // partner data of the coupled start faces, per row (x face) / column (y face):
     // [1/Piv_Q, a'_{Q->P}, a'_{Q->upstream along the face}, 1/(1 - a'_{P->Q} a'_{Q->P})]
-    S *fc = face + foff[blockIdx.x];
     for (int y = threadIdx.x; y < F.ly; y += blockDim.x) {
         double v0 = 0, v1 = 0, v2 = 0, v3 = 1;
         if (cx) {
@@ -183,6 +194,16 @@ __global__ void k_pack2d(PassGeom g, int R, int transposed, Fast2dDiag dg, const
         fk[1] = from_f64<S>(v1);
         fk[2] = from_f64<S>(v2);
     }
+}
+
+template <typename S>
+__global__ void k_pack2d(PassGeom g, int R, int transposed, Fast2dDiag dg, const double *__restrict__ piv,
+                         const int64_t *__restrict__ toff, const int64_t *__restrict__ foff, S *s_inv, S *s_ax,
+                         S *s_ay, S *face) {
+    const TileDesc td = g.tiles[blockIdx.x];
+    const Frame2 F = frame2(g, td);
+    const int64_t t = toff[blockIdx.x];
+    pack2d_body<S>(F, g.n[0], R, transposed, dg, piv, s_inv + t, s_ax + t, s_ay + t, face + foff[blockIdx.x]);
 }
 
 // ------------------------------------------------------------------ the pipelined half-sweep
@@ -236,14 +257,14 @@ template <> __device__ __forceinline__ uint16_t ldbuf<uint16_t>(__amdgpu_buffer_
     return __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
 }
 
+// One tile of a pass.  in / out point at the problem's vectors (indexed by
+// x + n0*y), s_* and fsrc at the tile's packed coefficients and face records.
 template <int R, typename T, typename S, typename TIN, typename TOUT, bool SC, bool CPL>
-__global__ void __launch_bounds__(256) k_fast2d(Fast2dArgs<S, TIN, TOUT> A) {
+__device__ __forceinline__ void fast2d_body(const Frame2 &F, int n0, const GP<TIN> *__restrict__ in,
+                                            GP<TOUT> *__restrict__ out, const S *s_inv_t, const S *s_ax_t,
+                                            const S *s_ay_t, const GP<S> *fsrc, double cscale, unsigned char *smem) {
     using V = typename Pack<S, R>::V;
     constexpr int D = kFast2dDepth;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const PassGeom &g = A.g;
-    const TileDesc td = g.tiles[blockIdx.x];
-    const Frame2 F = frame2(g, td);
     const bool cx = CPL && F.cx, cy = CPL && F.cy;
     const int lx = F.lx, ly = F.ly;
     // LDS: vector tile in global orientation with a one-point ring, pitch chosen
@@ -255,7 +276,6 @@ __global__ void __launch_bounds__(256) k_fast2d(Fast2dArgs<S, TIN, TOUT> A) {
     T *fy = fx + 4 * ly;                   // y-face partner records (4 values per column)
     T *fk = fy + 4 * lx;                   // cross point partner (3)
     const int sink = (int)((fk + 4) - vt);  // scratch slot for writes of idle lanes
-    const int n0 = g.n[0];
     const int tid = threadIdx.x, nth = blockDim.x;
 
     // ---- stage the input tile (+ partners) into LDS: each wave takes whole
@@ -270,7 +290,7 @@ __global__ void __launch_bounds__(256) k_fast2d(Fast2dArgs<S, TIN, TOUT> A) {
             const int it = it0 + u * nw;
             const int row = it / cpr, col = (it - row * cpr) * 64 + ln;
             const bool ok = it < nitems && col < lx;
-            v[u] = ok ? cvt<T>(A.in[lin2(n0, F.lox + col, F.loy + row)]) : T(0);
+            v[u] = ok ? cvt<T>(in[lin2(n0, F.lox + col, F.loy + row)]) : T(0);
         }
 #pragma unroll
         for (int u = 0; u < kStageBatch; ++u) {
@@ -281,17 +301,16 @@ __global__ void __launch_bounds__(256) k_fast2d(Fast2dArgs<S, TIN, TOUT> A) {
     }
     if (cx) {
         const int gx = gx_of(F, -1), col = F.d0 > 0 ? 0 : lx + 1;
-        for (int row = tid; row < ly; row += nth) vt[(row + 1) * pitch + col] = cvt<T>(A.in[lin2(n0, gx, F.loy + row)]);
+        for (int row = tid; row < ly; row += nth) vt[(row + 1) * pitch + col] = cvt<T>(in[lin2(n0, gx, F.loy + row)]);
     }
     if (cy) {
         const int gy = gy_of(F, -1), row = F.d1 > 0 ? 0 : ly + 1;
-        for (int col = tid; col < lx; col += nth) vt[row * pitch + col + 1] = cvt<T>(A.in[lin2(n0, F.lox + col, gy)]);
+        for (int col = tid; col < lx; col += nth) vt[row * pitch + col + 1] = cvt<T>(in[lin2(n0, F.lox + col, gy)]);
     }
     if (cx && cy && tid == 0) {
         const int col = F.d0 > 0 ? 0 : lx + 1, row = F.d1 > 0 ? 0 : ly + 1;
-        vt[row * pitch + col] = cvt<T>(A.in[lin2(n0, gx_of(F, -1), gy_of(F, -1))]);
+        vt[row * pitch + col] = cvt<T>(in[lin2(n0, gx_of(F, -1), gy_of(F, -1))]);
     }
-    const S *fsrc = A.face + A.foff[blockIdx.x];
     for (int i = tid; i < 4 * (lx + ly) + 3; i += nth) fx[i] = cvt<T>(fsrc[i]);
     __syncthreads();
 
@@ -302,11 +321,10 @@ __global__ void __launch_bounds__(256) k_fast2d(Fast2dArgs<S, TIN, TOUT> A) {
         const int nr = lane < L ? min(R, ly - R * lane) : 0;
         const int rlast = nr > 0 ? nr - 1 : 0;
         const int nsteps = lx + L - 1;
-        const int64_t sbase = A.toff[blockIdx.x];
         const int nbytes = (lx + L - 1 + D) * 64 * R * (int)sizeof(S);
-        const __amdgpu_buffer_rsrc_t rinv = __builtin_amdgcn_make_buffer_rsrc((void *)(A.s_inv + sbase), 0, nbytes, kBufCfg);
-        const __amdgpu_buffer_rsrc_t rax = __builtin_amdgcn_make_buffer_rsrc((void *)(A.s_ax + sbase), 0, nbytes, kBufCfg);
-        const __amdgpu_buffer_rsrc_t ray = __builtin_amdgcn_make_buffer_rsrc((void *)(A.s_ay + sbase), 0, nbytes, kBufCfg);
+        const __amdgpu_buffer_rsrc_t rinv = __builtin_amdgcn_make_buffer_rsrc((void *)s_inv_t, 0, nbytes, kBufCfg);
+        const __amdgpu_buffer_rsrc_t rax = __builtin_amdgcn_make_buffer_rsrc((void *)s_ax_t, 0, nbytes, kBufCfg);
+        const __amdgpu_buffer_rsrc_t ray = __builtin_amdgcn_make_buffer_rsrc((void *)s_ay_t, 0, nbytes, kBufCfg);
         constexpr bool sc = SC;
         const int vbytes = R * (int)sizeof(S);
         auto boff = [&](int s) -> int {
@@ -537,7 +555,7 @@ __global__ void __launch_bounds__(256) k_fast2d(Fast2dArgs<S, TIN, TOUT> A) {
     __syncthreads();
 
     // ---- write the tile back, same row-chunk order
-    const T cs = (T)A.cscale;
+    const T cs = (T)cscale;
     for (int it0 = wid; it0 < nitems; it0 += nw * kStageBatch) {
         T v[kStageBatch];
 #pragma unroll
@@ -550,45 +568,59 @@ __global__ void __launch_bounds__(256) k_fast2d(Fast2dArgs<S, TIN, TOUT> A) {
         for (int u = 0; u < kStageBatch; ++u) {
             const int it = it0 + u * nw;
             const int row = it / cpr, col = (it - row * cpr) * 64 + ln;
-            if (it < nitems && col < lx) A.out[lin2(n0, F.lox + col, F.loy + row)] = (TOUT)(cs * v[u]);
+            if (it < nitems && col < lx) out[lin2(n0, F.lox + col, F.loy + row)] = (TOUT)(cs * v[u]);
         }
     }
+}
+
+template <int R, typename T, typename S, typename TIN, typename TOUT, bool SC, bool CPL>
+__global__ void __launch_bounds__(256) k_fast2d(Fast2dArgs<S, TIN, TOUT> A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const TileDesc td = A.g.tiles[blockIdx.x];
+    const Frame2 F = frame2(A.g, td);
+    const int64_t t = A.toff[blockIdx.x];
+    fast2d_body<R, T, S, TIN, TOUT, SC, CPL>(F, A.g.n[0], (const GP<TIN> *)A.in, (GP<TOUT> *)A.out, A.s_inv + t,
+                                              A.s_ax + t, A.s_ay + t, (const GP<S> *)(A.face + A.foff[blockIdx.x]),
+                                              A.cscale, smem);
 }
 
 // ------------------------------------------------------------------ end-face chains (2D), prefetched
 // The coupled end face owned by a tile (see k_end_faces in psw_kernels.hip):
 // all data of the chain that does not depend on the chain itself is gathered
 // into LDS by the workgroup; one thread then runs the 2x2 recurrence.
-template <typename T, typename S, typename TIN, typename TOUT> struct EndFaceArgs {
-    PassGeom g;
-    const S *diag[5];
-    const S *piv;
-    const TIN *in;
-    int scale_by_piv;
-    TOUT *out;
-};
 
-template <typename T, typename S> __device__ __forceinline__ T ldS(const S *p, int64_t i) { return cvt<T>(p[i]); }
+template <typename T, typename S> __device__ __forceinline__ T ldS(const GP<S> *p, int64_t i) { return cvt<T>(p[i]); }
 
-template <typename T, typename S, typename TIN, typename TOUT>
-__global__ void __launch_bounds__(256) k_end_faces2d_fast(EndFaceArgs<T, S, TIN, TOUT> A) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const PassGeom &g = A.g;
-    const int tile = blockIdx.x >> 1, a = blockIdx.x & 1, b = 1 - a;
-    const TileDesc td = g.tiles[tile];
+// Tile frame of an end-coupled pass on axis pair (a, b).
+struct EndFrame2 {
     int d[2], len[2], lo[2];
     bool endc[2];
+};
+
+__device__ __forceinline__ EndFrame2 end_frame2(const int sig[2], int n0, int n1, const TileDesc &td) {
+    EndFrame2 f;
+    const int n[2] = {n0, n1};
     for (int q = 0; q < 2; ++q) {
-        d[q] = g.sig[q] * (td.par[q] ? -1 : 1);
-        len[q] = td.len[q];
-        lo[q] = td.lo[q];
-        endc[q] = d[q] > 0 ? lo[q] + len[q] < g.n[q] : lo[q] > 0;
+        f.d[q] = sig[q] * (td.par[q] ? -1 : 1);
+        f.len[q] = td.len[q];
+        f.lo[q] = td.lo[q];
+        f.endc[q] = f.d[q] > 0 ? f.lo[q] + f.len[q] < n[q] : f.lo[q] > 0;
     }
-    if (!(d[a] > 0 && endc[a])) return;
-    const int nb = endc[b] ? len[b] - 1 : len[b];
+    return f;
+}
+
+// The coupled end face on axis a owned by this tile (the tile sweeps towards
+// it): all data of the 2x2 chain that does not depend on the chain itself is
+// gathered into LDS by the workgroup; one thread then runs the recurrence.
+template <typename T, typename S, typename TIN, typename TOUT>
+__device__ void end_face2d_body(const EndFrame2 &E, int a, int n0, const GP<S> *const *diag, const GP<S> *piv,
+                                const GP<TIN> *in, bool scale_by_piv, GP<TOUT> *out, unsigned char *smem) {
+    const int b = 1 - a;
+    if (!(E.d[a] > 0 && E.endc[a])) return;
+    const int *d = E.d, *len = E.len, *lo = E.lo;
+    const int nb = E.endc[b] ? len[b] - 1 : len[b];
     T *mPQ = reinterpret_cast<T *>(smem);
     T *mQP = mPQ + nb, *cP = mQP + nb, *cQ = cP + nb, *bP = cQ + nb, *bQ = bP + nb;
-    const int n0 = g.n[0];
     auto gidx = [&](int la, int lb) -> int64_t {
         int c[2];
         c[a] = d[a] > 0 ? lo[a] + la : lo[a] + len[a] - 1 - la;
@@ -599,47 +631,141 @@ __global__ void __launch_bounds__(256) k_end_faces2d_fast(EndFaceArgs<T, S, TIN,
     for (int k = threadIdx.x; k < nb; k += blockDim.x) {
         const int64_t P = gidx(len[a] - 1, k), Q = gidx(len[a], k);
         const int64_t Pin = gidx(len[a] - 2, k), Qin = gidx(len[a] + 1, k);
-        const T DP = ldS<T>(A.piv, P), DQ = ldS<T>(A.piv, Q);
-        T rp = cvt<T>(A.in[P]), rq = cvt<T>(A.in[Q]);
-        if (A.scale_by_piv) {
+        const T DP = ldS<T>(piv, P), DQ = ldS<T>(piv, Q);
+        T rp = cvt<T>(in[P]), rq = cvt<T>(in[Q]);
+        if (scale_by_piv) {
             rp *= DP;
             rq *= DQ;
         }
         // couplings of the neighbours towards P / Q (transposed rows)
         const int sa = d[a], sb = d[b];
-        rp += ldS<T>(A.diag[dkk(a, +sa)], Pin) * cvt<T>(A.out[Pin]);
-        rq += ldS<T>(A.diag[dkk(a, -sa)], Qin) * cvt<T>(A.out[Qin]);
-        mPQ[k] = ldS<T>(A.diag[dkk(a, -sa)], Q) / DP; // Q's coupling towards P
-        mQP[k] = ldS<T>(A.diag[dkk(a, +sa)], P) / DQ; // P's coupling towards Q
+        rp += ldS<T>(diag[dkk(a, +sa)], Pin) * cvt<T>(out[Pin]);
+        rq += ldS<T>(diag[dkk(a, -sa)], Qin) * cvt<T>(out[Qin]);
+        const T iP = T(1) / DP, iQ = T(1) / DQ;
+        const T m1 = ldS<T>(diag[dkk(a, -sa)], Q) * iP; // Q's coupling towards P
+        const T m2 = ldS<T>(diag[dkk(a, +sa)], P) * iQ; // P's coupling towards Q
+        mPQ[k] = m1 / (T(1) - m1 * m2);                  // pre-divided by the 2x2 determinant
+        mQP[k] = m2;
         if (k > 0) {
             const int64_t Pp = gidx(len[a] - 1, k - 1), Qp = gidx(len[a], k - 1);
-            cP[k] = ldS<T>(A.diag[dkk(b, +sb)], Pp) / DP;
-            cQ[k] = ldS<T>(A.diag[dkk(b, +sb)], Qp) / DQ;
+            cP[k] = ldS<T>(diag[dkk(b, +sb)], Pp) * iP;
+            cQ[k] = ldS<T>(diag[dkk(b, +sb)], Qp) * iQ;
         } else {
             cP[k] = T(0);
             cQ[k] = T(0);
         }
-        bP[k] = rp / DP;
-        bQ[k] = rq / DQ;
+        bP[k] = rp * iP;
+        bQ[k] = rq * iQ;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
+        // x_P = e_P + m1 x_Q, x_Q = e_Q + m2 x_P  =>  x_P = (e_P + m1 e_Q) / (1 - m1 m2)
         T xp = T(0), xq = T(0);
         for (int k = 0; k < nb; ++k) {
             const T ep = bP[k] + cP[k] * xp, eq = bQ[k] + cQ[k] * xq;
-            const T m1 = mPQ[k], m2 = mQP[k];
-            const T det = T(1) - m1 * m2;
-            xp = (ep + m1 * eq) / det;
-            xq = (eq + m2 * ep) / det;
+            const T m1d = mPQ[k], m2 = mQP[k];
+            const T idet = T(1) + m1d * m2; // 1/(1 - m1 m2) = 1 + m1 m2 / (1 - m1 m2)
+            xp = ep * idet + m1d * eq;
+            xq = eq + m2 * xp;
             bP[k] = xp;
             bQ[k] = xq;
         }
     }
     __syncthreads();
     for (int k = threadIdx.x; k < nb; k += blockDim.x) {
-        A.out[gidx(len[a] - 1, k)] = (TOUT)bP[k];
-        A.out[gidx(len[a], k)] = (TOUT)bQ[k];
+        out[gidx(len[a] - 1, k)] = (TOUT)bP[k];
+        out[gidx(len[a], k)] = (TOUT)bQ[k];
     }
+}
+
+// Cross point of two coupled end faces, owned by the tile sweeping towards
+// +x and +y: the 4x4 block of the corner points of the four tiles.
+template <typename T, typename S, typename TIN, typename TOUT>
+__device__ void end_corner2d_body(const EndFrame2 &E, int n0, const GP<S> *const *diag, const GP<S> *piv,
+                                  const GP<TIN> *in, bool scale_by_piv, GP<TOUT> *out) {
+    if (!(E.d[0] > 0 && E.endc[0] && E.d[1] > 0 && E.endc[1])) return;
+    const int gx = E.lo[0] + E.len[0] - 1, gy = E.lo[1] + E.len[1] - 1;
+    // block points B = bit0 (x shifted by +1), bit1 (y shifted by +1)
+    T M[4][4], R[4];
+    int64_t idx[4];
+    for (int B = 0; B < 4; ++B) {
+        const int qx = gx + (B & 1), qy = gy + ((B >> 1) & 1);
+        idx[B] = (int64_t)qx + (int64_t)n0 * qy;
+    }
+    for (int B = 0; B < 4; ++B) {
+        const int fx = B & 1, fy = (B >> 1) & 1;
+        const int dqx = fx ? -1 : 1, dqy = fy ? -1 : 1; // direction of the point's own tile
+        const int qx = gx + fx, qy = gy + fy;
+        const int64_t Q = idx[B];
+        const T D = ldS<T>(piv, Q), iD = T(1) / D;
+        T acc = cvt<T>(in[Q]);
+        if (scale_by_piv) acc *= D;
+        for (int j = 0; j < 4; ++j) M[B][j] = (j == B) ? T(1) : T(0);
+        // block mates across x and y: their couplings towards Q
+        {
+            const int s = fx ? -1 : 1; // Q + s e_x is the mate
+            M[B][B ^ 1] -= ldS<T>(diag[dkk(0, -s)], idx[B ^ 1]) * iD;
+        }
+        {
+            const int s = fy ? -1 : 1;
+            M[B][B ^ 2] -= ldS<T>(diag[dkk(1, -s)], idx[B ^ 2]) * iD;
+        }
+        // upstream points inside the point's own tile (chain values of the faces)
+        {
+            const int64_t Rx = (int64_t)(qx - dqx) + (int64_t)n0 * qy;
+            acc += ldS<T>(diag[dkk(0, dqx)], Rx) * cvt<T>(out[Rx]);
+        }
+        {
+            const int64_t Ry = (int64_t)qx + (int64_t)n0 * (qy - dqy);
+            acc += ldS<T>(diag[dkk(1, dqy)], Ry) * cvt<T>(out[Ry]);
+        }
+        R[B] = acc * iD;
+    }
+    for (int k = 0; k < 4; ++k) {
+        const T ip = T(1) / M[k][k];
+        for (int i = k + 1; i < 4; ++i) {
+            const T l = M[i][k] * ip;
+            for (int j = k + 1; j < 4; ++j) M[i][j] -= l * M[k][j];
+            R[i] -= l * R[k];
+        }
+    }
+    for (int i = 3; i >= 0; --i) {
+        T acc = R[i];
+        for (int j = i + 1; j < 4; ++j) acc -= M[i][j] * R[j];
+        R[i] = acc / M[i][i];
+    }
+    for (int B = 0; B < 4; ++B) out[idx[B]] = (TOUT)R[B];
+}
+
+template <typename T, typename S, typename TIN, typename TOUT> struct EndFaceArgs {
+    PassGeom g;
+    const S *diag[5];
+    const S *piv;
+    const TIN *in;
+    int scale_by_piv;
+    TOUT *out;
+};
+
+template <typename T, typename S, typename TIN, typename TOUT>
+__global__ void __launch_bounds__(64) k_end_faces2d_fast(EndFaceArgs<T, S, TIN, TOUT> A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const TileDesc td = A.g.tiles[blockIdx.x >> 1];
+    const EndFrame2 E = end_frame2(A.g.sig, A.g.n[0], A.g.n[1], td);
+    const GP<S> *dg[5] = {(const GP<S> *)A.diag[0], (const GP<S> *)A.diag[1], (const GP<S> *)A.diag[2],
+                          (const GP<S> *)A.diag[3], (const GP<S> *)A.diag[4]};
+    end_face2d_body<T, S, TIN, TOUT>(E, blockIdx.x & 1, A.g.n[0], dg, (const GP<S> *)A.piv, (const GP<TIN> *)A.in,
+                                     A.scale_by_piv != 0, (GP<TOUT> *)A.out, smem);
+}
+
+template <typename T, typename S, typename TIN, typename TOUT>
+__global__ void k_end_corners2d(EndFaceArgs<T, S, TIN, TOUT> A) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= A.g.ntiles) return;
+    const EndFrame2 E = end_frame2(A.g.sig, A.g.n[0], A.g.n[1], A.g.tiles[t]);
+    const GP<S> *dg[5] = {(const GP<S> *)A.diag[0], (const GP<S> *)A.diag[1], (const GP<S> *)A.diag[2],
+                          (const GP<S> *)A.diag[3], (const GP<S> *)A.diag[4]};
+    end_corner2d_body<T, S, TIN, TOUT>(E, A.g.n[0], dg, (const GP<S> *)A.piv, (const GP<TIN> *)A.in,
+                                       A.scale_by_piv != 0, (GP<TOUT> *)A.out);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -734,6 +860,7 @@ static hipError_t endf_impl(const PassGeom &g, const void *const *diag, const vo
     A.out = (TOUT *)out;
     size_t sm = sizeof(T) * 6 * (size_t)facemax;
     hipLaunchKernelGGL((k_end_faces2d_fast<T, S, TIN, TOUT>), dim3(g.ntiles * 2), dim3(64), sm, st, A);
+    hipLaunchKernelGGL((k_end_corners2d<T, S, TIN, TOUT>), dim3((g.ntiles + 63) / 64), dim3(64), 0, st, A);
     return hipGetLastError();
 }
 
@@ -751,6 +878,139 @@ hipError_t launch_end_faces2d_fast(const PassGeom &g, Store s, const void *const
     if (!in_f64 && !out_f64) return endf_impl<float, uint16_t, float, float>(g, diag, piv, in, scale_by_piv, out, facemax, st);
     if (in_f64 && out_f64) return endf_impl<float, uint16_t, double, double>(g, diag, piv, in, scale_by_piv, out, facemax, st);
     return endf_impl<float, uint16_t, float, double>(g, diag, piv, in, scale_by_piv, out, facemax, st);
+}
+
+// ------------------------------------------------------------------ batched 2D passes
+// Pointers read from the problem table are generic; casting them through the
+// global address space lets the compiler emit global (not flat) memory
+// instructions, which do not hold up the LDS counters.
+template <typename T> __device__ __forceinline__ GP<T> *as_global(const void *p) {
+    return (GP<T> *)p;
+}
+
+__device__ __forceinline__ void *bslot(const BProb &P, int k) { return P.vec[k]; }
+
+template <int R, typename T, typename S, typename TIN, typename TOUT, bool SC, bool CPL>
+__global__ void __launch_bounds__(256) k_b_fast2d(const BTile *__restrict__ tiles, const BProb *__restrict__ probs, int sig0, int sig1,
+                                                  int pass, int in_slot, int out_slot, int cs_from_prob) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const BTile tb = tiles[blockIdx.x];
+    const BProb &P = probs[tb.prob];
+    if (P.flags[0] == 0) return;
+    const int sig[2] = {sig0, sig1};
+    const Frame2 F = frame2n(sig, P.n0, P.n1, tb.td);
+    const int64_t t = P.toff[tb.tix];
+    fast2d_body<R, T, S, TIN, TOUT, SC, CPL>(
+        F, P.n0, as_global<const TIN>(bslot(P, in_slot)), as_global<TOUT>(bslot(P, out_slot)),
+        (const S *)P.s_inv[pass] + t, (const S *)P.s_ax[pass] + t, (const S *)P.s_ay[pass] + t,
+        as_global<const S>(P.face[pass]) + P.foff[tb.tix],
+        cs_from_prob ? P.c : 1.0, smem);
+}
+
+template <typename T, typename S, typename TIN, typename TOUT>
+__global__ void __launch_bounds__(64) k_b_end_faces2d(const BTile *__restrict__ tiles, const BProb *__restrict__ probs, int sig0, int sig1,
+                                                      int in_slot, int out_slot, int scale_by_piv) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const BTile tb = tiles[blockIdx.x >> 1];
+    const BProb &P = probs[tb.prob];
+    if (P.flags[0] == 0) return;
+    const int sig[2] = {sig0, sig1};
+    const EndFrame2 E = end_frame2(sig, P.n0, P.n1, tb.td);
+    const GP<S> *dg[5] = {as_global<const S>(P.diagS[0]), as_global<const S>(P.diagS[1]),
+                          as_global<const S>(P.diagS[2]), as_global<const S>(P.diagS[3]),
+                          as_global<const S>(P.diagS[4])};
+    end_face2d_body<T, S, TIN, TOUT>(E, blockIdx.x & 1, P.n0, dg, as_global<const S>(P.pivS),
+                                     as_global<const TIN>(bslot(P, in_slot)), scale_by_piv != 0,
+                                     as_global<TOUT>(bslot(P, out_slot)), smem);
+}
+
+template <typename T, typename S, typename TIN, typename TOUT>
+__global__ void k_b_end_corners2d(const BTile *__restrict__ tiles, int ntiles, const BProb *__restrict__ probs, int sig0, int sig1,
+                                  int in_slot, int out_slot, int scale_by_piv) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ntiles) return;
+    const BTile tb = tiles[i];
+    const BProb &P = probs[tb.prob];
+    if (P.flags[0] == 0) return;
+    const int sig[2] = {sig0, sig1};
+    const EndFrame2 E = end_frame2(sig, P.n0, P.n1, tb.td);
+    const GP<S> *dg[5] = {as_global<const S>(P.diagS[0]), as_global<const S>(P.diagS[1]),
+                          as_global<const S>(P.diagS[2]), as_global<const S>(P.diagS[3]),
+                          as_global<const S>(P.diagS[4])};
+    end_corner2d_body<T, S, TIN, TOUT>(E, P.n0, dg, as_global<const S>(P.pivS), as_global<const TIN>(bslot(P, in_slot)),
+                                       scale_by_piv != 0, as_global<TOUT>(bslot(P, out_slot)));
+}
+
+template <int R, typename T, typename S, typename TIN, typename TOUT>
+static hipError_t b_fast_flags(const BTile *tiles, int ntiles, const BProb *probs, const int sig[2], int pass,
+                               int in_slot, int out_slot, bool scale, bool coupled, bool csp, size_t lds,
+                               hipStream_t st) {
+    dim3 g(ntiles), b(256);
+    const int c = csp ? 1 : 0;
+    if (scale && coupled)
+        hipLaunchKernelGGL((k_b_fast2d<R, T, S, TIN, TOUT, true, true>), g, b, lds, st, tiles, probs, sig[0], sig[1], pass, in_slot, out_slot, c);
+    else if (scale)
+        hipLaunchKernelGGL((k_b_fast2d<R, T, S, TIN, TOUT, true, false>), g, b, lds, st, tiles, probs, sig[0], sig[1], pass, in_slot, out_slot, c);
+    else if (coupled)
+        hipLaunchKernelGGL((k_b_fast2d<R, T, S, TIN, TOUT, false, true>), g, b, lds, st, tiles, probs, sig[0], sig[1], pass, in_slot, out_slot, c);
+    else
+        hipLaunchKernelGGL((k_b_fast2d<R, T, S, TIN, TOUT, false, false>), g, b, lds, st, tiles, probs, sig[0], sig[1], pass, in_slot, out_slot, c);
+    return hipGetLastError();
+}
+
+template <typename T, typename S, typename TIN, typename TOUT>
+static hipError_t b_fast_r(const BTile *tiles, int ntiles, const BProb *probs, const int sig[2], int pass, int R,
+                           int in_slot, int out_slot, bool scale, bool coupled, bool csp, size_t lds, hipStream_t st) {
+    if (R == 1) return b_fast_flags<1, T, S, TIN, TOUT>(tiles, ntiles, probs, sig, pass, in_slot, out_slot, scale, coupled, csp, lds, st);
+    return b_fast_flags<2, T, S, TIN, TOUT>(tiles, ntiles, probs, sig, pass, in_slot, out_slot, scale, coupled, csp, lds, st);
+}
+
+hipError_t launch_b_fast2d(const BTile *tiles, int ntiles, const BProb *probs, const int sig[2], int pass, int R,
+                           Store s, int in_slot, bool in_f64, int out_slot, bool out_f64, bool scale, bool coupled,
+                           bool csp, size_t lds, hipStream_t st) {
+    if (ntiles <= 0) return hipSuccess;
+#define PSW_B_ARGS tiles, ntiles, probs, sig, pass, R, in_slot, out_slot, scale, coupled, csp, lds, st
+    if (s == Store::F64) return b_fast_r<double, double, double, double>(PSW_B_ARGS);
+    if (s == Store::F32) {
+        if (in_f64 && !out_f64) return b_fast_r<float, float, double, float>(PSW_B_ARGS);
+        if (!in_f64 && out_f64) return b_fast_r<float, float, float, double>(PSW_B_ARGS);
+        if (in_f64 && out_f64) return b_fast_r<float, float, double, double>(PSW_B_ARGS);
+        return b_fast_r<float, float, float, float>(PSW_B_ARGS);
+    }
+    if (in_f64 && !out_f64) return b_fast_r<float, uint16_t, double, float>(PSW_B_ARGS);
+    if (!in_f64 && out_f64) return b_fast_r<float, uint16_t, float, double>(PSW_B_ARGS);
+    if (in_f64 && out_f64) return b_fast_r<float, uint16_t, double, double>(PSW_B_ARGS);
+    return b_fast_r<float, uint16_t, float, float>(PSW_B_ARGS);
+#undef PSW_B_ARGS
+}
+
+template <typename T, typename S, typename TIN, typename TOUT>
+static hipError_t b_end_impl(const BTile *tiles, int ntiles, const BProb *probs, const int sig[2], int in_slot,
+                             int out_slot, bool scale, int facemax, hipStream_t st) {
+    size_t sm = sizeof(T) * 6 * (size_t)facemax;
+    hipLaunchKernelGGL((k_b_end_faces2d<T, S, TIN, TOUT>), dim3(ntiles * 2), dim3(64), sm, st, tiles, probs, sig[0],
+                       sig[1], in_slot, out_slot, scale ? 1 : 0);
+    hipLaunchKernelGGL((k_b_end_corners2d<T, S, TIN, TOUT>), dim3((ntiles + 63) / 64), dim3(64), 0, st, tiles, ntiles,
+                       probs, sig[0], sig[1], in_slot, out_slot, scale ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_end2d(const BTile *tiles, int ntiles, const BProb *probs, const int sig[2], Store s, int in_slot,
+                          bool in_f64, int out_slot, bool out_f64, bool scale, int facemax, hipStream_t st) {
+    if (ntiles <= 0) return hipSuccess;
+#define PSW_E_ARGS tiles, ntiles, probs, sig, in_slot, out_slot, scale, facemax, st
+    if (s == Store::F64) return b_end_impl<double, double, double, double>(PSW_E_ARGS);
+    if (s == Store::F32) {
+        if (in_f64 && !out_f64) return b_end_impl<float, float, double, float>(PSW_E_ARGS);
+        if (!in_f64 && !out_f64) return b_end_impl<float, float, float, float>(PSW_E_ARGS);
+        if (in_f64 && out_f64) return b_end_impl<float, float, double, double>(PSW_E_ARGS);
+        return b_end_impl<float, float, float, double>(PSW_E_ARGS);
+    }
+    if (in_f64 && !out_f64) return b_end_impl<float, uint16_t, double, float>(PSW_E_ARGS);
+    if (!in_f64 && !out_f64) return b_end_impl<float, uint16_t, float, float>(PSW_E_ARGS);
+    if (in_f64 && out_f64) return b_end_impl<float, uint16_t, double, double>(PSW_E_ARGS);
+    return b_end_impl<float, uint16_t, float, double>(PSW_E_ARGS);
+#undef PSW_E_ARGS
 }
 
 } // namespace psw

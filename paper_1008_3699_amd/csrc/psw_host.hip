@@ -7,6 +7,7 @@
 // residual norm crosses to the host for the stopping test.
 #include "psw_internal.h"
 #include "psw_fast2d.h"
+#include "psw_batch.h"
 #include "../../include/psweep.h"
 
 #include <hip/hip_runtime.h>
@@ -310,7 +311,6 @@ psw_status half(psw_problem *P, psw_precond kind, int which, const void *in, boo
             HIPCHK(launch_fast2d(fp, s, in, in_f64, scale_by_piv, out, out_f64, 1.0, st));
             HIPCHK(launch_end_faces2d_fast(g, s, d, S.piv.p, in, in_f64, scale_by_piv, out, out_f64,
                                            std::max(S.lxmax, S.lymax), st));
-            HIPCHK(launch_end_corners(g, s, d, S.piv.p, in, in_f64, scale_by_piv, out, out_f64, st));
         }
         return PSW_OK;
     }
@@ -554,6 +554,279 @@ psw_status solve_fgmres(psw_problem *P, psw_precond kind, double rtol, int64_t m
         info->converged = conv && nr / nf <= rtol * 10;
     }
     return conv ? PSW_OK : PSW_ENOCONV;
+}
+
+
+// ---------------------------------------------------------------- batched CG
+// CG with the symmetric preconditioner over a batch of 2D problems whose
+// preconditioner runs on the pipelined path.  Each problem keeps its own
+// buffers; the batch is a device table of pointers.  Two iterations (one per
+// parity of the r.z slot) are captured in a hipGraph and replayed; the host
+// reads the number of active problems once per replay group.
+struct BatchRun {
+    std::vector<BProb> hp;
+    std::vector<BTile> tiles[2]; // by rows per lane (R = 1, 2)
+    std::vector<BChunk> chunks;
+    DevBuf dprobs, dtiles[2], dchunks, partials, count;
+    size_t lds[2] = {0, 0};
+    int facemax = 1;
+    Store store = Store::F64;
+    bool f64 = true;
+    int sig[2] = {1, 1};
+    int np = 0, nc = 0;
+};
+
+bool batch_eligible(psw_problem *P, psw_precond kind) {
+    if (P->dim != 2 || !P->has_diag || !P->has_decomp) return false;
+    if (kind != PSW_SSOR && kind != PSW_ILU0) return false;
+    int R, lx, ly;
+    return fast_eligible(P, R, lx, ly);
+}
+
+psw_status batch_build(BatchRun &B, int count, psw_problem *const *probs, const double *const *f, double *const *u,
+                       psw_precond kind, hipStream_t st) {
+    B.np = count;
+    B.store = store_of(probs[0]->prec);
+    B.f64 = probs[0]->prec == PSW_F64;
+    int sig3[3];
+    sched_sig(probs[0], 0, sig3);
+    B.sig[0] = sig3[0];
+    B.sig[1] = sig3[1];
+    int chunk = 0;
+    for (int i = 0; i < count; ++i) {
+        psw_problem *P = probs[i];
+        if (P->prec != probs[0]->prec || P->phase != probs[0]->phase) return PSW_ENOTSUP;
+        psw_status ps = precond_setup(P, kind, st);
+        if (ps) return ps;
+        if ((ps = ensure_work(P))) return ps;
+        PrecState &S = P->pc[kind];
+        if (!S.fast) return PSW_ENOTSUP;
+        BProb b{};
+        b.n0 = P->n[0];
+        b.n1 = P->n[1];
+        b.N = P->N;
+        for (int w = 0; w < 4; ++w) {
+            b.s_inv[w] = S.fp[w].inv.p;
+            b.s_ax[w] = S.fp[w].ax.p;
+            b.s_ay[w] = S.fp[w].ay.p;
+            b.face[w] = S.fp[w].face.p;
+        }
+        b.toff = S.toff.as<int64_t>();
+        b.foff = S.foff.as<int64_t>();
+        for (int k = 0; k < 5; ++k) {
+            b.diagS[k] = S.diag[k].p;
+            b.diag64[k] = P->diag[k].as<double>();
+        }
+        b.pivS = S.piv.p;
+        b.vec[kSlotR] = P->w_r.p;
+        b.vec[kSlotZ] = P->w_z.p;
+        b.vec[kSlotZ1] = P->w_z1.p;
+        b.vec[kSlotY1] = P->w_y.p;
+        b.vec[kSlotY2] = P->w_y2.p;
+        b.vec[kSlotP] = P->w_p.p;
+        b.vec[kSlotQ] = P->w_q.p;
+        b.vec[kSlotX] = u[i];
+        b.vec[kSlotF] = const_cast<double *>(f[i]);
+        b.scal = P->scal.as<double>();
+        b.flags = reinterpret_cast<int *>(P->scal.as<double>() + 40);
+        b.c = S.c;
+        b.chunk0 = chunk;
+        for (int64_t s0 = 0; s0 < P->N; s0 += kBatchChunk) {
+            BChunk c{};
+            c.prob = i;
+            c.start = s0;
+            c.len = (int)std::min<int64_t>(kBatchChunk, P->N - s0);
+            B.chunks.push_back(c);
+            ++chunk;
+        }
+        b.nchunk = chunk - b.chunk0;
+        B.hp.push_back(b);
+        // tiles in the order of the problem's packed offsets
+        std::vector<int> lo0, len0, lo1, len1;
+        partition(P->n[0], P->p[0], lo0, len0);
+        partition(P->n[1], P->p[1], lo1, len1);
+        const int g = S.R - 1;
+        int tix = 0;
+        for (int s1 = 0; s1 < P->p[1]; ++s1)
+            for (int s0 = 0; s0 < P->p[0]; ++s0) {
+                BTile t{};
+                t.td.lo[0] = lo0[s0];
+                t.td.len[0] = len0[s0];
+                t.td.par[0] = s0 & 1;
+                t.td.lo[1] = lo1[s1];
+                t.td.len[1] = len1[s1];
+                t.td.par[1] = s1 & 1;
+                t.td.lo[2] = 0;
+                t.td.len[2] = 1;
+                t.td.par[2] = 0;
+                t.prob = i;
+                t.tix = tix++;
+                B.tiles[g].push_back(t);
+            }
+        size_t elem = B.f64 ? 8 : 4;
+        B.lds[g] = std::max(B.lds[g], fast2d_lds_bytes(S.lxmax, S.lymax, S.R, elem));
+        B.facemax = std::max(B.facemax, std::max(S.lxmax, S.lymax));
+    }
+    B.nc = (int)B.chunks.size();
+    if (!B.dprobs.ensure(sizeof(BProb) * B.hp.size()) || !B.dchunks.ensure(sizeof(BChunk) * B.chunks.size()) ||
+        !B.partials.ensure(sizeof(double) * B.chunks.size()) || !B.count.ensure(sizeof(int) * 4))
+        return PSW_ENOMEM;
+    HIPCHK(hipMemcpyAsync(B.dprobs.p, B.hp.data(), sizeof(BProb) * B.hp.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(B.dchunks.p, B.chunks.data(), sizeof(BChunk) * B.chunks.size(), hipMemcpyHostToDevice, st));
+    for (int g = 0; g < 2; ++g)
+        if (!B.tiles[g].empty()) {
+            if (!B.dtiles[g].ensure(sizeof(BTile) * B.tiles[g].size())) return PSW_ENOMEM;
+            HIPCHK(hipMemcpyAsync(B.dtiles[g].p, B.tiles[g].data(), sizeof(BTile) * B.tiles[g].size(),
+                                  hipMemcpyHostToDevice, st));
+        }
+    HIPCHK(hipStreamSynchronize(st)); // host tables must outlive the copies
+    return PSW_OK;
+}
+
+// z = (M^-1 + M^-T) r / 2 for every active problem of the batch
+psw_status batch_precond(BatchRun &B, hipStream_t st) {
+    const BProb *dp = B.dprobs.as<BProb>();
+    const int sf[2] = {B.sig[0], B.sig[1]}, sb[2] = {-B.sig[0], -B.sig[1]};
+    const bool f64 = B.f64;
+    for (int g = 0; g < 2; ++g) {
+        const int nt = (int)B.tiles[g].size();
+        if (!nt) continue;
+        const BTile *t = B.dtiles[g].as<BTile>();
+        HIPCHK(launch_b_fast2d(t, nt, dp, sf, 0, g + 1, B.store, kSlotR, true, kSlotY1, f64, false, true, false, B.lds[g], st));
+        HIPCHK(launch_b_fast2d(t, nt, dp, sf, 2, g + 1, B.store, kSlotR, true, kSlotY2, f64, false, false, false, B.lds[g], st));
+    }
+    for (int g = 0; g < 2; ++g) {
+        const int nt = (int)B.tiles[g].size();
+        if (!nt) continue;
+        HIPCHK(launch_b_end2d(B.dtiles[g].as<BTile>(), nt, dp, sf, B.store, kSlotR, true, kSlotY2, f64, false, B.facemax, st));
+    }
+    for (int g = 0; g < 2; ++g) {
+        const int nt = (int)B.tiles[g].size();
+        if (!nt) continue;
+        const BTile *t = B.dtiles[g].as<BTile>();
+        HIPCHK(launch_b_fast2d(t, nt, dp, sb, 1, g + 1, B.store, kSlotY1, f64, kSlotZ1, true, true, true, true, B.lds[g], st));
+        HIPCHK(launch_b_fast2d(t, nt, dp, sb, 3, g + 1, B.store, kSlotY2, f64, kSlotY1, f64, true, false, false, B.lds[g], st));
+    }
+    for (int g = 0; g < 2; ++g) {
+        const int nt = (int)B.tiles[g].size();
+        if (!nt) continue;
+        HIPCHK(launch_b_end2d(B.dtiles[g].as<BTile>(), nt, dp, sb, B.store, kSlotY2, f64, kSlotY1, f64, true, B.facemax, st));
+    }
+    HIPCHK(launch_b_combine(B.dchunks.as<BChunk>(), B.nc, dp, f64, st));
+    return PSW_OK;
+}
+
+psw_status batch_iteration(BatchRun &B, int par, double rtol2, int64_t maxit, hipStream_t st) {
+    const BProb *dp = B.dprobs.as<BProb>();
+    const BChunk *dc = B.dchunks.as<BChunk>();
+    double *part = B.partials.as<double>();
+    HIPCHK(launch_b_spmv(dc, B.nc, dp, kSlotP, kSlotQ, false, st));
+    HIPCHK(launch_b_dot(dc, B.nc, dp, B.np, kSlotP, kSlotQ, part, 2, false, st));
+    HIPCHK(launch_b_cg_xr(dc, B.nc, dp, B.np, par, part, st));
+    HIPCHK(launch_b_check(dp, B.np, rtol2, maxit, st));
+    psw_status ps = batch_precond(B, st);
+    if (ps) return ps;
+    HIPCHK(launch_b_dot(dc, B.nc, dp, B.np, kSlotR, kSlotZ, part, 1 - par, false, st));
+    HIPCHK(launch_b_cg_p(dc, B.nc, dp, 1 - par, par, st));
+    return PSW_OK;
+}
+
+struct StreamHolder {
+    hipStream_t s = nullptr;
+    ~StreamHolder() {
+        if (s) (void)hipStreamDestroy(s);
+    }
+};
+
+psw_status batch_cg(int count, psw_problem *const *probs, const double *const *f, double *const *u, psw_precond kind,
+                    double rtol, int64_t maxit, psw_info *infos, hipStream_t user) {
+    const double t0 = now_ms();
+    BatchRun B;
+    // work on an internal stream (graph capture needs a capturable stream), ordered after the caller's
+    StreamHolder sh;
+    HIPCHK(hipStreamCreateWithFlags(&sh.s, hipStreamNonBlocking));
+    hipStream_t st = sh.s;
+    HIPCHK(hipStreamSynchronize(user));
+    psw_status ps = batch_build(B, count, probs, f, u, kind, st);
+    if (ps) return ps;
+    const BProb *dp = B.dprobs.as<BProb>();
+    const BChunk *dc = B.dchunks.as<BChunk>();
+    double *part = B.partials.as<double>();
+    const double rtol2 = rtol * rtol;
+    // start: r = f - A x, f.f, r.r, z = M r, r.z, p = z
+    HIPCHK(launch_b_activate(dp, B.np, st));
+    HIPCHK(launch_b_spmv(dc, B.nc, dp, kSlotX, kSlotR, true, st));
+    HIPCHK(launch_b_dot(dc, B.nc, dp, B.np, kSlotF, kSlotF, part, 4, true, st));
+    HIPCHK(launch_b_dot(dc, B.nc, dp, B.np, kSlotR, kSlotR, part, 3, true, st));
+    HIPCHK(launch_b_init(dp, B.np, rtol2, st));
+    if ((ps = batch_precond(B, st))) return ps;
+    HIPCHK(launch_b_dot(dc, B.nc, dp, B.np, kSlotR, kSlotZ, part, 0, false, st));
+    HIPCHK(launch_b_copy(dc, B.nc, dp, kSlotZ, kSlotP, st));
+    // two iterations in one graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    psw_status cap = batch_iteration(B, 0, rtol2, maxit, st);
+    if (cap == PSW_OK) cap = batch_iteration(B, 1, rtol2, maxit, st);
+    hipError_t ec = hipStreamEndCapture(st, &graph);
+    if (cap != PSW_OK || ec != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return cap != PSW_OK ? cap : PSW_EDEVICE;
+    }
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return PSW_EDEVICE;
+    }
+    int *hcount = nullptr;
+    if (hipHostMalloc((void **)&hcount, sizeof(int)) != hipSuccess) {
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        return PSW_ENOMEM;
+    }
+    psw_status run = PSW_OK;
+    const int per_poll = 8; // graph replays (2 iterations each) between polls
+    for (int64_t done = 0; done < maxit + 2; done += 2 * per_poll) {
+        for (int k = 0; k < per_poll; ++k)
+            if (hipGraphLaunch(exec, st) != hipSuccess) run = PSW_EDEVICE;
+        if (run) break;
+        if (launch_b_count(dp, B.np, B.count.as<int>(), st) != hipSuccess ||
+            hipMemcpyAsync(hcount, B.count.p, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            run = PSW_EDEVICE;
+            break;
+        }
+        if (*hcount == 0) break;
+    }
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    (void)hipHostFree(hcount);
+    if (run) return run;
+    // true residuals at exit
+    std::vector<int> st_it(2 * count);
+    HIPCHK(hipStreamSynchronize(st));
+    for (int i = 0; i < count; ++i)
+        HIPCHK(hipMemcpyAsync(&st_it[2 * i], B.hp[i].flags + 1, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(launch_b_activate(dp, B.np, st));
+    HIPCHK(launch_b_spmv(dc, B.nc, dp, kSlotX, kSlotR, true, st));
+    HIPCHK(launch_b_dot(dc, B.nc, dp, B.np, kSlotR, kSlotR, part, 3, true, st));
+    std::vector<double> sc(5 * count);
+    for (int i = 0; i < count; ++i)
+        HIPCHK(hipMemcpyAsync(&sc[5 * i], B.hp[i].scal, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const double t1 = now_ms();
+    psw_status worst = PSW_OK;
+    for (int i = 0; i < count; ++i) {
+        const double ff = sc[5 * i + 4] > 0 ? sc[5 * i + 4] : 1.0;
+        psw_info inf{};
+        inf.iters = st_it[2 * i];
+        inf.relres = std::sqrt(sc[5 * i + 3] / ff);
+        inf.status = st_it[2 * i + 1];
+        inf.converged = inf.status == PSW_OK;
+        inf.t_total_ms = t1 - t0;
+        if (infos) infos[i] = inf;
+        if (inf.status != PSW_OK && worst == PSW_OK) worst = (psw_status)inf.status;
+    }
+    return worst;
 }
 
 } // namespace
@@ -813,7 +1086,18 @@ psw_status psw_solve(psw_problem *P, psw_method method, psw_precond precond, dou
     psw_status ps;
     switch (method) {
     case PSW_SOR_STATIONARY: ps = solve_stationary(P, rtol, maxit, f, u, &loc, st); break;
-    case PSW_CG: ps = solve_cg(P, precond, rtol, maxit, f, u, &loc, st); break;
+    case PSW_CG:
+        // a single large problem runs faster on the host-driven loop; the
+        // graph-replayed batch path can be forced for testing
+        if (batch_eligible(P, precond) && std::getenv("PSW_BATCH_CG") && std::getenv("PSW_BATCH_CG")[0] == '1') {
+            psw_problem *pp[1] = {P};
+            const double *ff[1] = {f};
+            double *uu[1] = {u};
+            ps = batch_cg(1, pp, ff, uu, precond, rtol, maxit, &loc, st);
+            if (ps != PSW_ENOTSUP) break;
+        }
+        ps = solve_cg(P, precond, rtol, maxit, f, u, &loc, st);
+        break;
     case PSW_FGMRES: ps = solve_fgmres(P, precond, rtol, maxit, restart, f, u, &loc, st); break;
     default: return PSW_EINVAL;
     }
@@ -827,7 +1111,18 @@ psw_status psw_solve(psw_problem *P, psw_method method, psw_precond precond, dou
 psw_status psw_batch_solve(int count, psw_problem *const *probs, const double *const *f, double *const *u,
                            psw_method method, psw_precond precond, double rtol, int64_t maxit, psw_info *infos,
                            void *stream) {
-    if (count < 0 || (count > 0 && (!probs || !f || !u))) return PSW_EINVAL;
+    if (count < 0 || (count > 0 && (!probs || !f || !u)) || !(rtol > 0.0) || maxit < 1) return PSW_EINVAL;
+    if (count == 0) return PSW_OK;
+    for (int i = 0; i < count; ++i)
+        if (!probs[i] || !f[i] || !u[i] || f[i] == u[i]) return PSW_EINVAL;
+    DeviceGuard dg(probs[0]->device);
+    bool batched = method == PSW_CG;
+    for (int i = 0; i < count && batched; ++i)
+        batched = probs[i]->device == probs[0]->device && batch_eligible(probs[i], precond);
+    if (batched) {
+        psw_status s = batch_cg(count, probs, f, u, precond, rtol, maxit, infos, (hipStream_t)stream);
+        if (s != PSW_ENOTSUP) return s;
+    }
     psw_status worst = PSW_OK;
     for (int i = 0; i < count; ++i) {
         psw_info inf{};
