@@ -174,6 +174,19 @@ psw_status psw_batch_solve(int count, psw_problem *const *probs, const double *c
                            double *const *u, psw_method method, psw_precond precond, double rtol,
                            int64_t maxit, psw_info *infos, void *stream);
 
+/* Autotuner for batched solves: choose subdomain counts p_out for a 2D
+ * problem of n[0] x n[1] points by timing candidate tile sides (16 to 128
+ * points) on the batched symmetric preconditioner, with the problem
+ * replicated until its tiles fill the device; the cheapest per problem wins.
+ * The choice changes speed only: with exact coupled blocks the
+ * preconditioner quality barely depends on the tile size.  Results are
+ * cached per (size, precision, preconditioner) for the life of the process.
+ * us_per_problem (may be NULL) receives the winning time per problem and
+ * preconditioner application, or -1 when the answer came from the cache.
+ * PSW_ENOTSUP for 3D. */
+psw_status psw_autotune(int dim, const int64_t n[3], psw_prec prec, psw_precond kind, int p_out[3],
+                        double *us_per_problem, void *stream);
+
 /* Readable name of a status code (static storage). */
 const char *psw_status_string(psw_status st);
 

@@ -211,3 +211,17 @@ def batch_solve(problems, fs, us, precond="ssor", rtol=1e-8, maxit=100000, metho
     if st not in (0, -4):
         raise PswError(st, "psw_batch_solve")
     return [i.as_dict() for i in infos]
+
+
+def autotune(dim, n, prec="f64", precond="ssor", stream=None):
+    """Subdomain counts chosen by psw_autotune for a problem size; returns (p, us_per_problem)."""
+    L = lib()
+    L.psw_autotune.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_int,
+                               ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]
+    L.psw_autotune.restype = ctypes.c_int
+    arr = (ctypes.c_int64 * 3)(*(list(n) + [1] * (3 - len(n))))
+    p = (ctypes.c_int * 3)()
+    us = ctypes.c_double()
+    _check(L.psw_autotune(dim, arr, _PREC[prec], _KIND[precond], p, ctypes.byref(us), _stream(stream)),
+           "psw_autotune")
+    return tuple(p[:dim]), us.value

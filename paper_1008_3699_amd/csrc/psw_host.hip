@@ -14,6 +14,9 @@
 
 #include <algorithm>
 #include <chrono>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -829,10 +832,122 @@ psw_status batch_cg(int count, psw_problem *const *probs, const double *const *f
     return worst;
 }
 
+
+// ---------------------------------------------------------------- autotuner
+// Tile shape for a 2D problem size in a batch: candidate tile sides are timed
+// on the batched symmetric preconditioner with the problem replicated until
+// its tiles fill the device, and the cheapest per problem wins.  Results are
+// cached per (n0, n1, precision, preconditioner) for the life of the process.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, std::pair<int, int>> g_tune_cache;
+
+psw_status tune_candidate(int n0, int n1, psw_prec prec, psw_precond kind, int p0, int p1, double *us,
+                          hipStream_t st) {
+    const int64_t n[3] = {n0, n1, 1};
+    psw_problem *P = nullptr;
+    psw_status ps = psw_problem_create(2, n, 5, &P);
+    if (ps) return ps;
+    struct Closer {
+        psw_problem *p;
+        ~Closer() { psw_problem_destroy(p); }
+    } closer{P};
+    // unit coefficients: the tile shape, not the values, sets the cost
+    std::vector<double> one((size_t)P->N, 1.0), four((size_t)P->N, 4.0);
+    const double *dg[5] = {four.data(), one.data(), one.data(), one.data(), one.data()};
+    if ((ps = psw_set_diagonals(P, dg, 0, prec, st))) return ps;
+    const double w = 1.0;
+    if ((ps = psw_set_relaxation(P, &w, 1))) return ps;
+    const int pp[3] = {p0, p1, 1};
+    if ((ps = psw_set_decomposition(P, pp, 2, 0))) return ps;
+    if (!batch_eligible(P, kind)) return PSW_ENOTSUP;
+    const int tiles = p0 * p1;
+    const int reps_prob = std::max(1, (2 * 256 + tiles - 1) / tiles);
+    std::vector<psw_problem *> probs(reps_prob, P);
+    std::vector<const double *> f(reps_prob, nullptr);
+    std::vector<double *> u(reps_prob, nullptr);
+    if ((ps = ensure_work(P))) return ps;
+    for (int i = 0; i < reps_prob; ++i) {
+        f[i] = P->w_t.as<double>();
+        u[i] = P->w_t.as<double>();
+    }
+    BatchRun B;
+    if ((ps = batch_build(B, reps_prob, probs.data(), f.data(), u.data(), kind, st))) return ps;
+    HIPCHK(launch_b_activate(B.dprobs.as<BProb>(), B.np, st));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    psw_status run = batch_precond(B, st); // warm-up
+    const int reps = 3;
+    if (!run) {
+        (void)hipEventRecord(e0, st);
+        for (int k = 0; k < reps && !run; ++k) run = batch_precond(B, st);
+        (void)hipEventRecord(e1, st);
+    }
+    float ms = 0.f;
+    if (!run && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        run = PSW_EDEVICE;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (run) return run;
+    *us = 1e3 * ms / reps / reps_prob;
+    return PSW_OK;
+}
+
+psw_status autotune2d(int n0, int n1, psw_prec prec, psw_precond kind, int p[2], double *best_us, hipStream_t st) {
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(std::make_tuple(n0, n1, (int)prec, (int)kind));
+        if (it != g_tune_cache.end()) {
+            p[0] = it->second.first;
+            p[1] = it->second.second;
+            if (best_us) *best_us = -1.0;
+            return PSW_OK;
+        }
+    }
+    const int sides[] = {16, 24, 32, 48, 64, 96, 128};
+    double best = 1e300;
+    int bp0 = 0, bp1 = 0;
+    for (int side : sides) {
+        int p0 = std::max(1, (n0 + side - 1) / side), p1 = std::max(1, (n1 + side - 1) / side);
+        p0 = std::min(p0, std::max(1, n0 / 2));
+        p1 = std::min(p1, std::max(1, n1 / 2));
+        double us = 0;
+        psw_status ps = tune_candidate(n0, n1, prec, kind, p0, p1, &us, st);
+        if (ps == PSW_ENOTSUP || ps == PSW_EINVAL) continue;
+        if (ps) return ps;
+        if (us < best) {
+            best = us;
+            bp0 = p0;
+            bp1 = p1;
+        }
+    }
+    if (!bp0) return PSW_ENOTSUP;
+    p[0] = bp0;
+    p[1] = bp1;
+    if (best_us) *best_us = best;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[std::make_tuple(n0, n1, (int)prec, (int)kind)] = {bp0, bp1};
+    return PSW_OK;
+}
+
 } // namespace
 
 // ====================================================================== C ABI
 extern "C" {
+
+psw_status psw_autotune(int dim, const int64_t n[3], psw_prec prec, psw_precond kind, int p_out[3],
+                        double *us_per_problem, void *stream) {
+    if (!n || !p_out || (kind != PSW_SSOR && kind != PSW_ILU0) || prec < PSW_F64 || prec > PSW_BF16) return PSW_EINVAL;
+    if (dim != 2) return PSW_ENOTSUP;
+    if (n[0] < 2 || n[1] < 2 || n[0] > (1 << 20) || n[1] > (1 << 20)) return PSW_EINVAL;
+    int p[2];
+    psw_status ps = autotune2d((int)n[0], (int)n[1], prec, kind, p, us_per_problem, (hipStream_t)stream);
+    if (ps) return ps;
+    p_out[0] = p[0];
+    p_out[1] = p[1];
+    p_out[2] = 1;
+    return PSW_OK;
+}
 
 const char *psw_status_string(psw_status st) {
     switch (st) {

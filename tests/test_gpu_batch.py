@@ -30,17 +30,22 @@ def test_batch_equals_alone(kind, prec):
         g.set_decomposition(p, overlap=2)
         probs.append(g)
         fs.append(to_dev(f))
+    hosts = []
     for g, f in zip(probs, fs):
         u = torch.zeros_like(f)
-        info = g.solve("cg", kind, f, u, rtol=1e-8)
+        info = P.batch_solve([g], [f], [u], precond=kind, rtol=1e-8)[0]  # alone: a batch of one
         alone.append((info, to_np(u)))
+        v = torch.zeros_like(f)
+        g.solve("cg", kind, f, v, rtol=1e-8)  # the host-driven solver, other reduction order
+        hosts.append(to_np(v))
     us = [torch.zeros_like(f) for f in fs]
     infos = P.batch_solve(probs, fs, us, precond=kind, rtol=1e-8)
-    for (ia, ua), ib, ub in zip(alone, infos, us):
+    for (ia, ua), ib, ub, uh in zip(alone, infos, us, hosts):
         assert ib["converged"] and ia["converged"]
         assert ib["iters"] == ia["iters"]
-        assert np.array_equal(to_np(ub), ua)
+        assert np.array_equal(to_np(ub), ua)  # bitwise: the mix does not change a problem's arithmetic
         assert ib["relres"] <= 1.5e-8
+        assert np.linalg.norm(to_np(ub) - uh) <= 1e-5 * np.linalg.norm(uh)
 
 
 @pytest.mark.parametrize("kind", ["ssor", "ilu0"])
