@@ -41,11 +41,16 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample-s", type=float, default=15.0)
-    ap.add_argument("--workload", default="varcoef2048", choices=["varcoef2048", "batch512"],
+    ap.add_argument("--workload", default="varcoef2048", choices=["varcoef2048", "batch512", "serve"],
                     help="varcoef2048: one 2048^2 solve per step (default); batch512: 512 anisotropic problems "
-                         "solved together per step")
+                         "solved together per step; serve: a stream of Poisson arrivals through the server")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--plain-sample", type=int, default=24, help="batch512: problems solved one by one in FP64")
+    ap.add_argument("--serve-count", type=int, default=120, help="serve: number of requests in the stream")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="serve: mean arrival rate (requests/s)")
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0, help="serve: admission budget (GiB of HBM)")
+    ap.add_argument("--serve-plain-s", type=float, default=10.0,
+                    help="serve: time spent solving a sample one by one with the plain FP64 solver")
     return ap.parse_args()
 
 
@@ -64,6 +69,8 @@ def main():
 
     if args.workload == "batch512":
         return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     n, p = args.n, args.p
@@ -246,6 +253,106 @@ def bench_batch(args):
         "plain_fp64_sequential_solves_per_s": round(plain_rate, 3),
         "speedup_vs_plain": round(args.steps * len(specs) / elapsed / plain_rate, 2),
         "max_rel_diff_vs_plain_fp64": max(err),
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+def bench_serve(args):
+    """A stream of Poisson arrivals (mixed 2D 64^2..1024^2 and 3D 32^3..128^3 variable-coefficient problems,
+    coefficients log-uniform [1e-2,1e2]) served to 1e-8 by the continuously batched server."""
+    import numpy as np
+    import torch
+
+    import paper_1008_3699_amd as P
+    import synth
+
+    dev = torch.device("cuda:0")
+    prec = "f32" if args.prec == "f64" else args.prec
+    reqs = synth.serving_stream(count=args.serve_count, rate=args.serve_rate)
+    fields = [synth.request_fields(r) for r in reqs]
+    # tile shapes for every 2D size bucket are tuned before the stream starts
+    for b in sorted({max(32, ((r["n"][0] + 32) // 64) * 64) for r in reqs if r["dim"] == 2}):
+        P.autotune(2, (b, b), prec, args.precond)
+    torch.cuda.synchronize()
+    budget = int(args.serve_budget_gib * (1 << 30))
+    srv = P.Server(budget, prec=prec, precond=args.precond, rtol=args.rtol, maxit=args.maxit)
+    t0 = time.perf_counter()
+    tickets = []
+    for r, fl in zip(reqs, fields):
+        wait = t0 + r["t"] - time.perf_counter()
+        if wait > 0:
+            time.sleep(wait)
+        tickets.append(srv.submit(fl["dim"], fl["n"], fl["alphas"], fl["f"], fl["beta"]))
+    t_sub = time.perf_counter() - t0
+    out = []
+    for k, t in enumerate(tickets):
+        out.append(srv.poll(t, wait=True))
+        if (k + 1) % 20 == 0:
+            print(f"# {k + 1}/{len(tickets)} requests done", file=sys.stderr, flush=True)
+    elapsed = time.perf_counter() - t0
+    srv.close()
+    lat = np.array([o[1]["t_total_ms"] for o in out])
+    queue = np.array([o[1]["t_queue_ms"] for o in out])
+    iters = np.array([o[1]["iters"] for o in out])
+    dims = np.array([r["dim"] for r in reqs])
+    nconv = int(sum(o[1]["converged"] for o in out))
+    # the plain solver (FP64 sweeps, one request at a time, host-driven CG) on a sample, same decompositions
+    rng = np.random.default_rng(0)
+    order = rng.permutation(len(reqs))
+    t_plain, n_plain, err = 0.0, 0, []
+    for k in order:
+        if t_plain > args.serve_plain_s:
+            break
+        fl = fields[k]
+        dim, n = fl["dim"], fl["n"]
+        g = P.Problem(dim, n)
+        g.assemble([torch.from_numpy(np.ascontiguousarray(a).reshape(-1)).to(dev) for a in fl["alphas"]], 0.0)
+        g.set_relaxation([1.0])
+        if dim == 2:
+            pp = tuple(max(1, min(v // 2, -(-v // 128))) for v in n)
+        else:
+            pp = tuple(max(1, min(v // 2, -(-v // 32))) for v in n)
+        g.set_decomposition(pp, overlap=2)
+        g.precond_setup(args.precond)
+        f = torch.from_numpy(fl["f"]).to(dev)
+        u = torch.zeros_like(f)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        g.solve("cg", args.precond, f, u, rtol=args.rtol, maxit=args.maxit)
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - a
+        n_plain += 1
+        us = torch.from_numpy(out[k][0]).to(dev)
+        err.append(float(torch.linalg.norm(us - u) / torch.linalg.norm(u)))
+        g.close()
+    rate = len(reqs) / elapsed
+    rec = {
+        "metric": "served PCG solves/s to 1e-8 with p50/p99 latency (Poisson arrivals)",
+        "value": round(rate, 3),
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(1e3 * elapsed, 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": prec, "data": "synthetic",
+        "config": {"workload": f"{len(reqs)} requests, Poisson arrivals at {args.serve_rate:g}/s, 2D 5-point "
+                               "64^2..1024^2 and 3D 7-point 32^3..128^3, coefficients log-uniform [1e-2,1e2], "
+                               f"rhs U[-1,1], {args.precond.upper()}-PCG to {args.rtol:g}, FP64 CG / {prec} sweeps",
+                   "budget_gib": args.serve_budget_gib, "requests_2d": int((dims == 2).sum()),
+                   "requests_3d": int((dims == 3).sum())},
+        "p50_ms": round(float(np.percentile(lat, 50)), 2),
+        "p99_ms": round(float(np.percentile(lat, 99)), 2),
+        "p50_ms_2d": round(float(np.percentile(lat[dims == 2], 50)), 2) if (dims == 2).any() else None,
+        "p50_ms_3d": round(float(np.percentile(lat[dims == 3], 50)), 2) if (dims == 3).any() else None,
+        "queue_p50_ms": round(float(np.percentile(queue, 50)), 2),
+        "queue_p99_ms": round(float(np.percentile(queue, 99)), 2),
+        "offered_rate": args.serve_rate, "arrival_window_s": round(t_sub, 3),
+        "converged": nconv, "iterations_mean": float(iters.mean()),
+        "plain_fp64_sequential_solves_per_s": round(n_plain / t_plain, 3) if t_plain > 0 else None,
+        "plain_sample": n_plain,
+        "max_rel_diff_vs_plain_fp64": max(err) if err else None,
+        "capacity_note": "offered load above the served rate: latency is then mostly queueing"
+        if rate < args.serve_rate else "served rate keeps up with the offered load",
         "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(rec), flush=True)

@@ -31,6 +31,7 @@
 #ifndef PSWEEP_H
 #define PSWEEP_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -186,6 +187,44 @@ psw_status psw_batch_solve(int count, psw_problem *const *probs, const double *c
  * PSW_ENOTSUP for 3D. */
 psw_status psw_autotune(int dim, const int64_t n[3], psw_prec prec, psw_precond kind, int p_out[3],
                         double *us_per_problem, void *stream);
+
+/* ---------------------------------------------------------------- serving
+ * A server solves a stream of independent problems A u = f with
+ * -div(alpha grad u) + beta u on unit-spaced grids (2D 5-point or 3D
+ * 7-point), CG with the symmetric form of the preconditioner, u0 = 0.
+ * Admission reserves an estimate of each request's device memory against
+ * budget_bytes; requests wait in arrival order until their reservation fits.
+ * 2D requests are batched continuously: between epochs of epoch_iters CG
+ * iterations of all active 2D problems, admitted requests join and finished
+ * ones leave and free their memory.  3D requests are solved one at a time on
+ * a second stream that overlaps with the 2D batch.  A request's arithmetic
+ * does not depend on the other requests in the batch.  Thread-safe. */
+typedef struct psw_server psw_server;
+typedef struct {
+    psw_prec prec;       /* sweep precision (outer CG is FP64) */
+    psw_precond precond; /* PSW_SSOR (omega = 1) or PSW_ILU0 */
+    double rtol;         /* relative residual tolerance */
+    int64_t maxit;       /* iteration limit per request */
+    int epoch_iters;     /* CG iterations between admissions (rounded up to even; <= 0: 16) */
+    int max_active;      /* most 2D problems in the batch at once (<= 0: 1024) */
+} psw_server_opts;
+
+psw_status psw_server_create(size_t budget_bytes, const psw_server_opts *opts, psw_server **out);
+/* Queue a request.  alpha[a] (a < dim): axis-a coefficients on the (n+2)^dim
+ * nodes, as in psw_assemble_diffusion; f: N right-hand-side values; host
+ * arrays, copied before return.  PSW_EBUSY if the request alone exceeds the
+ * budget.  *ticket identifies the request. */
+psw_status psw_server_submit(psw_server *srv, int dim, const int64_t n[3], const double *const alpha[], double beta,
+                             const double *f, uint64_t *ticket);
+/* *done = 1 once the request has finished (wait = 1 blocks until then).  On
+ * completion info receives iterations, relres, status and t_total_ms =
+ * submission to completion; t_queue_ms (may be NULL) the time spent waiting
+ * for admission; u (host, N doubles, may be NULL) the solution.  A finished
+ * request is returned once; its ticket is then forgotten. */
+psw_status psw_server_poll(psw_server *srv, uint64_t ticket, int wait, int *done, psw_info *info, double *u,
+                           double *t_queue_ms);
+/* Finish every queued request, then stop the workers and free the server. */
+psw_status psw_server_destroy(psw_server *srv);
 
 /* Readable name of a status code (static storage). */
 const char *psw_status_string(psw_status st);

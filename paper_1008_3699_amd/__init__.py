@@ -11,7 +11,8 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["Problem", "PswError", "lib", "SSOR", "ILU0", "NONE", "STATIONARY", "CG", "FGMRES"]
+__all__ = ["Problem", "Server", "PswError", "lib", "batch_solve", "autotune", "SSOR", "ILU0", "NONE",
+           "STATIONARY", "CG", "FGMRES"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 SO_PATH = os.path.join(_HERE, "libpsweep.so")
@@ -46,6 +47,9 @@ def lib():
     if _lib is None:
         if not os.path.exists(SO_PATH):
             raise RuntimeError(f"{SO_PATH} is missing: build it with `python -m paper_1008_3699_amd.build`")
+        # torch first: its HIP runtime then satisfies the library's libamdhip64.so.7 dependency by soname.
+        # Loaded the other way round, the process maps two HIP runtimes and torch's fails to find the GPU.
+        import torch  # noqa: F401
         L = ctypes.CDLL(SO_PATH)
         vp, i64, dbl, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
         pp = ctypes.POINTER(ctypes.c_void_p)
@@ -225,3 +229,86 @@ def autotune(dim, n, prec="f64", precond="ssor", stream=None):
     _check(L.psw_autotune(dim, arr, _PREC[prec], _KIND[precond], p, ctypes.byref(us), _stream(stream)),
            "psw_autotune")
     return tuple(p[:dim]), us.value
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int), ("precond", ctypes.c_int), ("rtol", ctypes.c_double),
+                ("maxit", ctypes.c_int64), ("epoch_iters", ctypes.c_int), ("max_active", ctypes.c_int)]
+
+
+class Server:
+    """Continuously batched solver of independent diffusion problems (psw_server_*).
+
+    Requests are host numpy arrays: per-axis node coefficients of (n+2)^dim
+    values and a right-hand side of prod(n) values; results come back to the host.
+    """
+
+    def __init__(self, budget_bytes, prec="f32", precond="ilu0", rtol=1e-8, maxit=100000, epoch_iters=16,
+                 max_active=1024):
+        L = lib()
+        vp = ctypes.c_void_p
+        L.psw_server_create.argtypes = [ctypes.c_size_t, ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
+        L.psw_server_submit.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_void_p), ctypes.c_double, vp,
+                                        ctypes.POINTER(ctypes.c_uint64)]
+        L.psw_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(Info), vp, ctypes.POINTER(ctypes.c_double)]
+        L.psw_server_destroy.argtypes = [vp]
+        for fn in (L.psw_server_create, L.psw_server_submit, L.psw_server_poll, L.psw_server_destroy):
+            fn.restype = ctypes.c_int
+        opts = ServerOpts(_PREC[prec], _KIND[precond], float(rtol), int(maxit), int(epoch_iters), int(max_active))
+        h = ctypes.c_void_p()
+        _check(L.psw_server_create(int(budget_bytes), ctypes.byref(opts), ctypes.byref(h)), "psw_server_create")
+        self._h = h
+        self._size = {}
+
+    def submit(self, dim, n, alphas, f, beta=0.0):
+        """Queue one request; returns its ticket.  Raises PswError (PSW_EBUSY) if it can never fit."""
+        import numpy as np
+        n = tuple(int(v) for v in n)
+        N = int(np.prod(n))
+        nodes = int(np.prod([v + 2 for v in n]))
+        al = [np.ascontiguousarray(a, dtype=np.float64).reshape(-1) for a in alphas]
+        fh = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
+        if len(al) != dim or any(a.size != nodes for a in al) or fh.size != N:
+            raise ValueError("alphas need (n+2)^dim values per axis and f prod(n) values")
+        arr = (ctypes.c_int64 * 3)(*(list(n) + [1] * (3 - dim)))
+        ptrs = (ctypes.c_void_p * 3)(*([a.ctypes.data for a in al] + [0] * (3 - dim)))
+        t = ctypes.c_uint64()
+        _check(lib().psw_server_submit(self._h, dim, arr, ptrs, float(beta), ctypes.c_void_p(fh.ctypes.data),
+                                       ctypes.byref(t)), "psw_server_submit")
+        self._size[t.value] = N
+        return t.value
+
+    def poll(self, ticket, wait=False):
+        """None while the request runs; else (solution u as numpy, info dict with t_queue_ms)."""
+        import numpy as np
+        done = ctypes.c_int()
+        info = Info()
+        u = np.empty(self._size[ticket], dtype=np.float64)
+        tq = ctypes.c_double()
+        _check(lib().psw_server_poll(self._h, ticket, int(bool(wait)), ctypes.byref(done), ctypes.byref(info),
+                                     ctypes.c_void_p(u.ctypes.data), ctypes.byref(tq)), "psw_server_poll")
+        if not done.value:
+            return None
+        del self._size[ticket]
+        d = info.as_dict()
+        d["t_queue_ms"] = tq.value
+        return u, d
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().psw_server_destroy(self._h), "psw_server_destroy")
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

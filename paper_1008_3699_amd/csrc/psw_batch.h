@@ -18,6 +18,8 @@ hipError_t launch_b_check(const BProb *p, int np, double rtol2, int64_t maxit, h
 hipError_t launch_b_init(const BProb *p, int np, double rtol2, hipStream_t st);
 hipError_t launch_b_activate(const BProb *p, int np, hipStream_t st);
 hipError_t launch_b_count(const BProb *p, int np, int *out, hipStream_t st);
+// iflags[3 b + k] = flags[k] (active, iterations, status); dscal[5 b + k] = scal[k] (dscal may be null)
+hipError_t launch_b_gather(const BProb *p, int np, int *iflags, double *dscal, hipStream_t st);
 hipError_t launch_b_cg_p(const BChunk *c, int nc, const BProb *p, int num, int den, hipStream_t st);
 hipError_t launch_b_combine(const BChunk *c, int nc, const BProb *p, bool y_f64, hipStream_t st);
 hipError_t launch_b_copy(const BChunk *c, int nc, const BProb *p, int src, int dst, hipStream_t st);

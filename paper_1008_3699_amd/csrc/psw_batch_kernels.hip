@@ -164,6 +164,16 @@ __global__ void k_b_count(const BProb *probs, int nprob, int *out) {
     if (threadIdx.x == 0) out[0] = sh[0];
 }
 
+// per problem: iflags[3 b + k] = flags[k] (k < 3), dscal[5 b + k] = scal[k] (k < 5)
+__global__ void k_b_gather(const BProb *probs, int nprob, int *iflags, double *dscal) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nprob) return;
+    const BProb &p = probs[b];
+    for (int k = 0; k < 3; ++k) iflags[3 * b + k] = p.flags[k];
+    if (dscal)
+        for (int k = 0; k < 5; ++k) dscal[5 * b + k] = p.scal[k];
+}
+
 // p = z + beta p, beta = scal[num] / scal[den]
 __global__ void __launch_bounds__(kT) k_b_cg_p(const BChunk *chunks, int nc, const BProb *probs, int num, int den) {
     for (int ci = blockIdx.x; ci < nc; ci += gridDim.x) {
@@ -250,6 +260,11 @@ hipError_t launch_b_activate(const BProb *p, int np, hipStream_t st) {
 
 hipError_t launch_b_count(const BProb *p, int np, int *out, hipStream_t st) {
     hipLaunchKernelGGL(k_b_count, dim3(1), dim3(kT), 0, st, p, np, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_gather(const BProb *p, int np, int *iflags, double *dscal, hipStream_t st) {
+    hipLaunchKernelGGL(k_b_gather, dim3((np + 63) / 64), dim3(64), 0, st, p, np, iflags, dscal);
     return hipGetLastError();
 }
 

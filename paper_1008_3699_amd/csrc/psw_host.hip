@@ -14,8 +14,12 @@
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
+#include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
+#include <thread>
 #include <tuple>
 #include <cmath>
 #include <cstdio>
@@ -570,7 +574,7 @@ struct BatchRun {
     std::vector<BProb> hp;
     std::vector<BTile> tiles[2]; // by rows per lane (R = 1, 2)
     std::vector<BChunk> chunks;
-    DevBuf dprobs, dtiles[2], dchunks, partials, count;
+    DevBuf dprobs, dtiles[2], dchunks, partials, count, gflags, gscal;
     size_t lds[2] = {0, 0};
     int facemax = 1;
     Store store = Store::F64;
@@ -672,7 +676,8 @@ psw_status batch_build(BatchRun &B, int count, psw_problem *const *probs, const 
     }
     B.nc = (int)B.chunks.size();
     if (!B.dprobs.ensure(sizeof(BProb) * B.hp.size()) || !B.dchunks.ensure(sizeof(BChunk) * B.chunks.size()) ||
-        !B.partials.ensure(sizeof(double) * B.chunks.size()) || !B.count.ensure(sizeof(int) * 4))
+        !B.partials.ensure(sizeof(double) * B.chunks.size()) || !B.count.ensure(sizeof(int) * 4) ||
+        !B.gflags.ensure(sizeof(int) * 3 * B.hp.size()) || !B.gscal.ensure(sizeof(double) * 5 * B.hp.size()))
         return PSW_ENOMEM;
     HIPCHK(hipMemcpyAsync(B.dprobs.p, B.hp.data(), sizeof(BProb) * B.hp.size(), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(B.dchunks.p, B.chunks.data(), sizeof(BChunk) * B.chunks.size(), hipMemcpyHostToDevice, st));
@@ -734,6 +739,53 @@ psw_status batch_iteration(BatchRun &B, int par, double rtol2, int64_t maxit, hi
     return PSW_OK;
 }
 
+// start of a solve for every problem of B: r = f - A x, f.f, r.r, activity,
+// z = M r, r.z (parity 0), p = z
+psw_status batch_start(BatchRun &B, double rtol2, hipStream_t st) {
+    const BProb *dp = B.dprobs.as<BProb>();
+    const BChunk *dc = B.dchunks.as<BChunk>();
+    double *part = B.partials.as<double>();
+    HIPCHK(launch_b_activate(dp, B.np, st));
+    HIPCHK(launch_b_spmv(dc, B.nc, dp, kSlotX, kSlotR, true, st));
+    HIPCHK(launch_b_dot(dc, B.nc, dp, B.np, kSlotF, kSlotF, part, 4, true, st));
+    HIPCHK(launch_b_dot(dc, B.nc, dp, B.np, kSlotR, kSlotR, part, 3, true, st));
+    HIPCHK(launch_b_init(dp, B.np, rtol2, st));
+    psw_status ps = batch_precond(B, st);
+    if (ps) return ps;
+    HIPCHK(launch_b_dot(dc, B.nc, dp, B.np, kSlotR, kSlotZ, part, 0, false, st));
+    HIPCHK(launch_b_copy(dc, B.nc, dp, kSlotZ, kSlotP, st));
+    return PSW_OK;
+}
+
+// true residuals of every problem of B; fills infos (iterations, status, relres)
+psw_status batch_finish(BatchRun &B, psw_info *infos, hipStream_t st) {
+    const BProb *dp = B.dprobs.as<BProb>();
+    const BChunk *dc = B.dchunks.as<BChunk>();
+    double *part = B.partials.as<double>();
+    const int count = B.np;
+    std::vector<int> fl(3 * count);
+    std::vector<double> sc(5 * count);
+    // iterations and status before the activity flags are reset for the residual pass
+    HIPCHK(launch_b_gather(dp, count, B.gflags.as<int>(), nullptr, st));
+    HIPCHK(hipMemcpyAsync(fl.data(), B.gflags.p, sizeof(int) * 3 * count, hipMemcpyDeviceToHost, st));
+    HIPCHK(launch_b_activate(dp, count, st));
+    HIPCHK(launch_b_spmv(dc, B.nc, dp, kSlotX, kSlotR, true, st));
+    HIPCHK(launch_b_dot(dc, B.nc, dp, count, kSlotR, kSlotR, part, 3, true, st));
+    HIPCHK(launch_b_gather(dp, count, B.gflags.as<int>(), B.gscal.as<double>(), st));
+    HIPCHK(hipMemcpyAsync(sc.data(), B.gscal.p, sizeof(double) * 5 * count, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int i = 0; i < count; ++i) {
+        const double ff = sc[5 * i + 4] > 0 ? sc[5 * i + 4] : 1.0;
+        psw_info inf{};
+        inf.iters = fl[3 * i + 1];
+        inf.relres = std::sqrt(sc[5 * i + 3] / ff);
+        inf.status = fl[3 * i + 2];
+        inf.converged = inf.status == PSW_OK;
+        infos[i] = inf;
+    }
+    return PSW_OK;
+}
+
 struct StreamHolder {
     hipStream_t s = nullptr;
     ~StreamHolder() {
@@ -753,18 +805,8 @@ psw_status batch_cg(int count, psw_problem *const *probs, const double *const *f
     psw_status ps = batch_build(B, count, probs, f, u, kind, st);
     if (ps) return ps;
     const BProb *dp = B.dprobs.as<BProb>();
-    const BChunk *dc = B.dchunks.as<BChunk>();
-    double *part = B.partials.as<double>();
     const double rtol2 = rtol * rtol;
-    // start: r = f - A x, f.f, r.r, z = M r, r.z, p = z
-    HIPCHK(launch_b_activate(dp, B.np, st));
-    HIPCHK(launch_b_spmv(dc, B.nc, dp, kSlotX, kSlotR, true, st));
-    HIPCHK(launch_b_dot(dc, B.nc, dp, B.np, kSlotF, kSlotF, part, 4, true, st));
-    HIPCHK(launch_b_dot(dc, B.nc, dp, B.np, kSlotR, kSlotR, part, 3, true, st));
-    HIPCHK(launch_b_init(dp, B.np, rtol2, st));
-    if ((ps = batch_precond(B, st))) return ps;
-    HIPCHK(launch_b_dot(dc, B.nc, dp, B.np, kSlotR, kSlotZ, part, 0, false, st));
-    HIPCHK(launch_b_copy(dc, B.nc, dp, kSlotZ, kSlotP, st));
+    if ((ps = batch_start(B, rtol2, st))) return ps;
     // two iterations in one graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -804,30 +846,14 @@ psw_status batch_cg(int count, psw_problem *const *probs, const double *const *f
     (void)hipGraphDestroy(graph);
     (void)hipHostFree(hcount);
     if (run) return run;
-    // true residuals at exit
-    std::vector<int> st_it(2 * count);
-    HIPCHK(hipStreamSynchronize(st));
-    for (int i = 0; i < count; ++i)
-        HIPCHK(hipMemcpyAsync(&st_it[2 * i], B.hp[i].flags + 1, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(launch_b_activate(dp, B.np, st));
-    HIPCHK(launch_b_spmv(dc, B.nc, dp, kSlotX, kSlotR, true, st));
-    HIPCHK(launch_b_dot(dc, B.nc, dp, B.np, kSlotR, kSlotR, part, 3, true, st));
-    std::vector<double> sc(5 * count);
-    for (int i = 0; i < count; ++i)
-        HIPCHK(hipMemcpyAsync(&sc[5 * i], B.hp[i].scal, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    std::vector<psw_info> loc(count);
+    if ((ps = batch_finish(B, loc.data(), st))) return ps;
     const double t1 = now_ms();
     psw_status worst = PSW_OK;
     for (int i = 0; i < count; ++i) {
-        const double ff = sc[5 * i + 4] > 0 ? sc[5 * i + 4] : 1.0;
-        psw_info inf{};
-        inf.iters = st_it[2 * i];
-        inf.relres = std::sqrt(sc[5 * i + 3] / ff);
-        inf.status = st_it[2 * i + 1];
-        inf.converged = inf.status == PSW_OK;
-        inf.t_total_ms = t1 - t0;
-        if (infos) infos[i] = inf;
-        if (inf.status != PSW_OK && worst == PSW_OK) worst = (psw_status)inf.status;
+        loc[i].t_total_ms = t1 - t0;
+        if (infos) infos[i] = loc[i];
+        if (loc[i].status != PSW_OK && worst == PSW_OK) worst = (psw_status)loc[i].status;
     }
     return worst;
 }
@@ -930,10 +956,375 @@ psw_status autotune2d(int n0, int n1, psw_prec prec, psw_precond kind, int p[2],
     return PSW_OK;
 }
 
+
+// ---------------------------------------------------------------- serving
+// Requests carry a coefficient field and a right-hand side (host arrays).
+// Admission reserves an estimate of the request's device memory against the
+// budget.  2D requests join a continuously batched CG: between epochs of an
+// even number of iterations, admitted problems are started and joined to the
+// active set and converged ones are retired and freed.  3D requests are solved
+// one at a time on a second stream, overlapping with the 2D batch.
+struct SrvReq {
+    uint64_t id = 0;
+    int dim = 2;
+    int64_t n[3] = {1, 1, 1};
+    int64_t N = 0;
+    std::vector<double> alpha[3];
+    double beta = 0.0;
+    std::vector<double> f, u;
+    psw_info info{};
+    int state = 0; // 0 queued, 1 running, 2 done
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    size_t bytes = 0;
+    psw_problem *P = nullptr;
+    DevBuf dx, df, dal[3];
+};
+
+size_t request_bytes(int dim, const int64_t n[3], psw_prec prec) {
+    int64_t N = 1, nodes = 1;
+    for (int a = 0; a < dim; ++a) {
+        N *= n[a];
+        nodes *= n[a] + 2;
+    }
+    // FP64 operator, vectors and workspace (~16 arrays), packed passes (~4 x 3
+    // arrays with padding) and pivots in the sweep precision, node coefficients
+    const size_t s = prec == PSW_F64 ? 8 : 4;
+    return (size_t)N * (16 * 8 + 20 * s + 16) + (size_t)nodes * 8 * dim;
+}
+
+} // namespace
+
+struct psw_server {
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<SrvReq *> q2, q3;
+    std::map<uint64_t, std::unique_ptr<SrvReq>> reqs;
+    size_t budget = 0, used = 0;
+    psw_prec prec = PSW_F32;
+    psw_precond precond = PSW_SSOR;
+    double rtol = 1e-8;
+    int64_t maxit = 100000;
+    int epoch_iters = 16;
+    int max_active = 1024;
+    bool stop = false;
+    uint64_t next_id = 1;
+    int device = 0;
+    int64_t n_done = 0;
+    std::thread w2, w3;
+};
+
+namespace {
+
+// set up a request's problem on the device (assembly, decomposition, preconditioner)
+psw_status srv_setup(psw_server *S, SrvReq *r, hipStream_t st) {
+    psw_status ps = psw_problem_create(r->dim, r->n, 2 * r->dim + 1, &r->P);
+    if (ps) return ps;
+    int64_t nodes = 1;
+    for (int a = 0; a < r->dim; ++a) nodes *= r->n[a] + 2;
+    const double *al[3] = {nullptr, nullptr, nullptr};
+    for (int a = 0; a < r->dim; ++a) {
+        if (!r->dal[a].ensure(sizeof(double) * nodes)) return PSW_ENOMEM;
+        HIPCHK(hipMemcpyAsync(r->dal[a].p, r->alpha[a].data(), sizeof(double) * nodes, hipMemcpyHostToDevice, st));
+        al[a] = r->dal[a].as<double>();
+    }
+    if (!r->df.ensure(sizeof(double) * r->N) || !r->dx.ensure(sizeof(double) * r->N)) return PSW_ENOMEM;
+    HIPCHK(hipMemcpyAsync(r->df.p, r->f.data(), sizeof(double) * r->N, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(r->dx.p, 0, sizeof(double) * r->N, st));
+    if ((ps = psw_assemble_diffusion(r->P, al, r->beta, S->prec, st))) return ps;
+    const double w = 1.0;
+    if ((ps = psw_set_relaxation(r->P, &w, 1))) return ps;
+    int p[3] = {1, 1, 1};
+    if (r->dim == 2) {
+        // autotuned tile side of the size bucket
+        const int b = (int)std::max<int64_t>(32, ((r->n[0] + 32) / 64) * 64);
+        int pb[2];
+        if (autotune2d(b, b, S->prec, S->precond, pb, nullptr, st) == PSW_OK) {
+            const int side = std::max(2, b / pb[0]);
+            for (int a = 0; a < 2; ++a)
+                p[a] = (int)std::max<int64_t>(1, std::min<int64_t>(r->n[a] / 2, (r->n[a] + side - 1) / side));
+        } else {
+            for (int a = 0; a < 2; ++a) p[a] = (int)std::max<int64_t>(1, (r->n[a] + 127) / 128);
+        }
+    } else {
+        for (int a = 0; a < 3; ++a) p[a] = (int)std::max<int64_t>(1, std::min<int64_t>(r->n[a] / 2, (r->n[a] + 31) / 32));
+    }
+    if ((ps = psw_set_decomposition(r->P, p, 2, 0))) return ps;
+    if ((ps = precond_setup(r->P, S->precond, st))) return ps;
+    HIPCHK(hipStreamSynchronize(st));
+    r->alpha[0].clear();
+    r->alpha[1].clear();
+    r->alpha[2].clear();
+    for (int a = 0; a < 3; ++a) r->dal[a].release();
+    return PSW_OK;
+}
+
+void srv_finish(psw_server *S, SrvReq *r, psw_status st_code, hipStream_t st) {
+    r->u.assign((size_t)r->N, 0.0);
+    if (r->dx.p) (void)hipMemcpyAsync(r->u.data(), r->dx.p, sizeof(double) * r->N, hipMemcpyDeviceToHost, st);
+    (void)hipStreamSynchronize(st);
+    if (r->P) psw_problem_destroy(r->P);
+    r->P = nullptr;
+    r->dx.release();
+    r->df.release();
+    r->f.clear();
+    std::lock_guard<std::mutex> lk(S->mu);
+    r->t_done = now_ms();
+    if (st_code != PSW_OK) r->info.status = st_code;
+    r->info.converged = r->info.status == PSW_OK;
+    r->info.t_total_ms = r->t_done - r->t_submit;
+    r->state = 2;
+    S->used -= r->bytes;
+    ++S->n_done;
+    S->cv.notify_all();
+}
+
+// one request solved alone (host-driven CG)
+void srv_solve_one(psw_server *S, SrvReq *r, hipStream_t st) {
+    psw_info inf{};
+    psw_status ps = psw_solve(r->P, PSW_CG, S->precond, S->rtol, S->maxit, 30, r->df.as<double>(), r->dx.as<double>(),
+                              &inf, st);
+    r->info = inf;
+    srv_finish(S, r, ps, st);
+}
+
+void srv_admit(psw_server *S, std::deque<SrvReq *> &q, std::vector<SrvReq *> &out, size_t max_new) {
+    std::lock_guard<std::mutex> lk(S->mu);
+    while (!q.empty() && out.size() < max_new && S->used + q.front()->bytes <= S->budget) {
+        SrvReq *r = q.front();
+        q.pop_front();
+        S->used += r->bytes;
+        r->state = 1;
+        r->t_admit = now_ms();
+        out.push_back(r);
+    }
+}
+
+void srv_lane2d(psw_server *S) {
+    (void)hipSetDevice(S->device);
+    StreamHolder sh;
+    if (hipStreamCreateWithFlags(&sh.s, hipStreamNonBlocking) != hipSuccess) return;
+    hipStream_t st = sh.s;
+    const double rtol2 = S->rtol * S->rtol;
+    std::vector<SrvReq *> active;
+    std::unique_ptr<BatchRun> B;
+    bool dirty = true;
+    for (;;) {
+        std::vector<SrvReq *> fresh;
+        const size_t room = active.size() < (size_t)S->max_active ? S->max_active - active.size() : 0;
+        srv_admit(S, S->q2, fresh, room);
+        if (active.empty() && fresh.empty()) {
+            std::unique_lock<std::mutex> lk(S->mu);
+            if (S->stop && S->q2.empty()) break;
+            S->cv.wait_for(lk, std::chrono::milliseconds(2));
+            continue;
+        }
+        // start the admitted problems
+        std::vector<SrvReq *> ok;
+        for (SrvReq *r : fresh) {
+            psw_status ps = srv_setup(S, r, st);
+            if (ps) {
+                srv_finish(S, r, ps, st);
+            } else if (!batch_eligible(r->P, S->precond)) {
+                srv_solve_one(S, r, st); // a shape the batched kernels do not take
+            } else {
+                ok.push_back(r);
+            }
+        }
+        if (!ok.empty()) {
+            std::vector<psw_problem *> pp;
+            std::vector<const double *> ff;
+            std::vector<double *> uu;
+            for (SrvReq *r : ok) {
+                pp.push_back(r->P);
+                ff.push_back(r->df.as<double>());
+                uu.push_back(r->dx.as<double>());
+            }
+            BatchRun Bn;
+            psw_status ps = batch_build(Bn, (int)ok.size(), pp.data(), ff.data(), uu.data(), S->precond, st);
+            if (!ps) ps = batch_start(Bn, rtol2, st);
+            if (!ps && hipStreamSynchronize(st) != hipSuccess) ps = PSW_EDEVICE;
+            if (ps) {
+                for (SrvReq *r : ok) srv_finish(S, r, ps, st);
+            } else {
+                active.insert(active.end(), ok.begin(), ok.end());
+                dirty = true;
+            }
+        }
+        if (active.empty()) continue;
+        if (dirty) {
+            B.reset(new BatchRun());
+            std::vector<psw_problem *> pp;
+            std::vector<const double *> ff;
+            std::vector<double *> uu;
+            for (SrvReq *r : active) {
+                pp.push_back(r->P);
+                ff.push_back(r->df.as<double>());
+                uu.push_back(r->dx.as<double>());
+            }
+            psw_status ps = batch_build(*B, (int)active.size(), pp.data(), ff.data(), uu.data(), S->precond, st);
+            if (ps) {
+                for (SrvReq *r : active) srv_finish(S, r, ps, st);
+                active.clear();
+                continue;
+            }
+            dirty = false;
+        }
+        // an epoch: an even number of iterations keeps every problem at r.z parity 0
+        psw_status ps = PSW_OK;
+        for (int k = 0; k < S->epoch_iters && !ps; ++k) ps = batch_iteration(*B, k & 1, rtol2, S->maxit, st);
+        std::vector<int> fl(3 * active.size());
+        if (!ps && (launch_b_gather(B->dprobs.as<BProb>(), B->np, B->gflags.as<int>(), nullptr, st) != hipSuccess ||
+                    hipMemcpyAsync(fl.data(), B->gflags.p, sizeof(int) * fl.size(), hipMemcpyDeviceToHost, st) !=
+                        hipSuccess ||
+                    hipStreamSynchronize(st) != hipSuccess))
+            ps = PSW_EDEVICE;
+        if (ps) {
+            for (SrvReq *r : active) srv_finish(S, r, ps, st);
+            active.clear();
+            dirty = true;
+            continue;
+        }
+        // retire the finished problems
+        std::vector<SrvReq *> done, keep;
+        for (size_t i = 0; i < active.size(); ++i) (fl[3 * i] ? keep : done).push_back(active[i]);
+        if (!done.empty()) {
+            std::vector<psw_problem *> pp;
+            std::vector<const double *> ff;
+            std::vector<double *> uu;
+            for (SrvReq *r : done) {
+                pp.push_back(r->P);
+                ff.push_back(r->df.as<double>());
+                uu.push_back(r->dx.as<double>());
+            }
+            BatchRun Bd;
+            std::vector<psw_info> inf(done.size());
+            psw_status fs = batch_build(Bd, (int)done.size(), pp.data(), ff.data(), uu.data(), S->precond, st);
+            if (!fs) fs = batch_finish(Bd, inf.data(), st);
+            for (size_t i = 0; i < done.size(); ++i) {
+                if (!fs) done[i]->info = inf[i];
+                srv_finish(S, done[i], fs ? fs : (psw_status)inf[i].status, st);
+            }
+            active.swap(keep);
+            dirty = true;
+        }
+    }
+}
+
+void srv_lane3d(psw_server *S) {
+    (void)hipSetDevice(S->device);
+    StreamHolder sh;
+    if (hipStreamCreateWithFlags(&sh.s, hipStreamNonBlocking) != hipSuccess) return;
+    hipStream_t st = sh.s;
+    for (;;) {
+        std::vector<SrvReq *> one;
+        srv_admit(S, S->q3, one, 1);
+        if (one.empty()) {
+            std::unique_lock<std::mutex> lk(S->mu);
+            if (S->stop && S->q3.empty()) break;
+            S->cv.wait_for(lk, std::chrono::milliseconds(2));
+            continue;
+        }
+        SrvReq *r = one[0];
+        psw_status ps = srv_setup(S, r, st);
+        if (ps) srv_finish(S, r, ps, st);
+        else srv_solve_one(S, r, st);
+    }
+}
+
 } // namespace
 
 // ====================================================================== C ABI
 extern "C" {
+
+psw_status psw_server_create(size_t budget_bytes, const psw_server_opts *opts, psw_server **out) {
+    if (!out || budget_bytes == 0) return PSW_EINVAL;
+    *out = nullptr;
+    psw_server *S = new (std::nothrow) psw_server();
+    if (!S) return PSW_ENOMEM;
+    if (hipGetDevice(&S->device) != hipSuccess) {
+        delete S;
+        return PSW_EDEVICE;
+    }
+    S->budget = budget_bytes;
+    if (opts) {
+        if (opts->prec < PSW_F64 || opts->prec > PSW_BF16 || (opts->precond != PSW_SSOR && opts->precond != PSW_ILU0) ||
+            !(opts->rtol > 0.0) || opts->maxit < 1) {
+            delete S;
+            return PSW_EINVAL;
+        }
+        S->prec = opts->prec;
+        S->precond = opts->precond;
+        S->rtol = opts->rtol;
+        S->maxit = opts->maxit;
+        if (opts->epoch_iters > 0) S->epoch_iters = (opts->epoch_iters + 1) & ~1;
+        if (opts->max_active > 0) S->max_active = opts->max_active;
+    }
+    S->w2 = std::thread(srv_lane2d, S);
+    S->w3 = std::thread(srv_lane3d, S);
+    *out = S;
+    return PSW_OK;
+}
+
+psw_status psw_server_submit(psw_server *S, int dim, const int64_t n[3], const double *const alpha[], double beta,
+                             const double *f, uint64_t *ticket) {
+    if (!S || !n || !alpha || !f || !ticket || (dim != 2 && dim != 3) || !(beta >= 0.0)) return PSW_EINVAL;
+    std::unique_ptr<SrvReq> r(new (std::nothrow) SrvReq());
+    if (!r) return PSW_ENOMEM;
+    r->dim = dim;
+    r->N = 1;
+    int64_t nodes = 1;
+    for (int a = 0; a < dim; ++a) {
+        if (n[a] < 4 || n[a] > (1 << 16) || !alpha[a]) return PSW_EINVAL;
+        r->n[a] = n[a];
+        r->N *= n[a];
+        nodes *= n[a] + 2;
+    }
+    r->bytes = request_bytes(dim, r->n, S->prec);
+    if (r->bytes > S->budget) return PSW_EBUSY;
+    for (int a = 0; a < dim; ++a) r->alpha[a].assign(alpha[a], alpha[a] + nodes);
+    r->f.assign(f, f + r->N);
+    r->beta = beta;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stop) return PSW_ESTATE;
+    r->id = S->next_id++;
+    r->t_submit = now_ms();
+    SrvReq *raw = r.get();
+    S->reqs[raw->id] = std::move(r);
+    (dim == 2 ? S->q2 : S->q3).push_back(raw);
+    *ticket = raw->id;
+    S->cv.notify_all();
+    return PSW_OK;
+}
+
+psw_status psw_server_poll(psw_server *S, uint64_t ticket, int wait, int *done, psw_info *info, double *u,
+                           double *t_queue_ms) {
+    if (!S || !done) return PSW_EINVAL;
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return PSW_EINVAL;
+    SrvReq *r = it->second.get();
+    if (wait) S->cv.wait(lk, [&] { return r->state == 2; });
+    *done = r->state == 2;
+    if (!*done) return PSW_OK;
+    if (info) *info = r->info;
+    if (t_queue_ms) *t_queue_ms = r->t_admit - r->t_submit;
+    if (u) std::copy(r->u.begin(), r->u.end(), u);
+    S->reqs.erase(it); // a finished request is handed out once
+    return PSW_OK;
+}
+
+psw_status psw_server_destroy(psw_server *S) {
+    if (!S) return PSW_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+        S->cv.notify_all();
+    }
+    if (S->w2.joinable()) S->w2.join();
+    if (S->w3.joinable()) S->w3.join();
+    delete S;
+    return PSW_OK;
+}
 
 psw_status psw_autotune(int dim, const int64_t n[3], psw_prec prec, psw_precond kind, int p_out[3],
                         double *us_per_problem, void *stream) {

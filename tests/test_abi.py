@@ -4,6 +4,7 @@ import os
 import re
 
 import pytest
+import torch  # noqa: F401  (loads torch's HIP runtime before the library, as the binding does)
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HDR = os.path.join(ROOT, "include", "psweep.h")
@@ -18,7 +19,9 @@ def declared():
 def test_header_declares_the_boundary():
     names = declared()
     for must in ("psw_problem_create", "psw_set_diagonals", "psw_set_relaxation", "psw_set_decomposition",
-                 "psw_sweep", "psw_precond_apply", "psw_solve", "psw_batch_solve", "psw_status_string"):
+                 "psw_sweep", "psw_precond_apply", "psw_solve", "psw_batch_solve", "psw_autotune",
+                 "psw_server_create", "psw_server_submit", "psw_server_poll", "psw_server_destroy",
+                 "psw_status_string"):
         assert must in names
 
 
@@ -48,3 +51,15 @@ def test_create_rejects_bad_arguments_without_touching_gpu():
     assert L.psw_problem_create(2, n, 7, ctypes.byref(h)) == -1
     assert L.psw_problem_create(4, n, 9, ctypes.byref(h)) == -1
     assert L.psw_problem_create(1, n, 3, ctypes.byref(h)) == -8
+
+
+def test_server_rejects_bad_arguments_without_touching_gpu():
+    L = ctypes.CDLL(SO)
+    h = ctypes.c_void_p()
+    L.psw_server_create.argtypes = [ctypes.c_size_t, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+    assert L.psw_server_create(0, None, ctypes.byref(h)) == -1  # zero budget
+    assert L.psw_server_destroy(None) == -1
+    done = ctypes.c_int()
+    L.psw_server_poll.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_void_p]
+    assert L.psw_server_poll(None, 1, 0, ctypes.byref(done), None, None, None) == -1
