@@ -6,7 +6,7 @@
  * fully parallel SOR/ILU preconditioners for structured n-diagonal matrices".
  * The kernels are HIP for gfx950 (MI355X).
  *
- * Problem statement (Sec. 6): solve or precondition A u = f where A is an
+ * Problem statement (Sec. 7): solve or precondition A u = f where A is an
  * irreducibly diagonally dominant structured n-diagonal matrix on a
  * structured grid.
  *
@@ -83,7 +83,7 @@ psw_status psw_set_diagonals(psw_problem *prob, const double *const diag[], int 
                              psw_prec sweep_prec, void *stream);
 
 /* Assemble the diagonals of -div(alpha grad u) + beta u on a unit-spaced
- * grid (eq. d2d; Sec. 2 harmonic face means) on the device.  alpha[a],
+ * grid (eq. d2d; Sec. 3 harmonic face means) on the device.  alpha[a],
  * a < dim, is the axis-a coefficient on all (n0+2)*(n1+2)[*(n2+2)] nodes,
  * boundary ring included, node (i,j,k) at i + (n0+2)*(j + (n1+2)*k) and
  * interior point x at node x+1.  Face coupling = harmonic mean of the two
@@ -95,7 +95,7 @@ psw_status psw_assemble_diffusion(psw_problem *prob, const double *const alpha[]
 /* Copy diagonal k (0 = P ... 2*dim) into the device array out (N doubles). */
 psw_status psw_get_diagonal(psw_problem *prob, int k, double *out, void *stream);
 
-/* Relaxation factors per start corner (Sec. 2: w_SW, w_NE, ...): count = 1
+/* Relaxation factors per start corner (Sec. 3: omega_SW, omega_NE, ...): count = 1
  * (same factor everywhere) or 2^dim, indexed by the start corner of the
  * sweep: bit a set when the sweep along axis a starts at the high end (so in
  * 2D: 0 = SW, 1 = SE, 2 = NW, 3 = NE).  Each factor must lie in (0,2).
@@ -103,11 +103,11 @@ psw_status psw_get_diagonal(psw_problem *prob, int k, double *out, void *stream)
 psw_status psw_set_relaxation(psw_problem *prob, const double *omega, int count);
 
 /* Decomposition into p[0] x p[1] (x p[2]) subdomains: contiguous ranges per
- * axis, the first n mod p ranges one point longer (Sec. 2.1).  Every
+ * axis, the first n mod p ranges one point longer (Sec. 3).  Every
  * subdomain must be at least 2 points long on every axis.  overlap is the
  * halo depth staged per subdomain (>= 2; a 5/7-point sweep reads 2 layers,
- * Sec. 2.3) and does not change any result.  phase swaps the two members
- * of every direction pair of the schedule (Sec. 2.2). */
+ * Sec. 3, Data structure) and does not change any result.  phase swaps the two members
+ * of every direction pair of the schedule (Sec. 3, Sweeping directions). */
 psw_status psw_set_decomposition(psw_problem *prob, const int p[3], int overlap, int phase);
 
 /* One decomposed SOR sweep, FP64 (Secs. 2-4).  Subdomain (r,s,t) sweeps at

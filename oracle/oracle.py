@@ -13,11 +13,11 @@ sequential sweeping on structured grids"):
   values from the other side; points on a start face whose neighbour subdomain
   also starts there are solved jointly (eqs. 1d:sorc, 2d:sor2b2, 2d:sor4b4,
   and the 3D 2x2 / 4x4 / 8x8 systems of Sec. 4).
-* Direction schedule (Sec. 2.2 rules): base cycle for subdomain (0,0,0) --
+* Direction schedule (Sec. 3, Sweeping directions; Sec. 4): base cycle for subdomain (0,0,0) --
   1D: +, -; 2D: (-,-), (+,+), (+,-), (-,+); 3D: the pairs (s,-s) for
   s = (-,-,-), (+,-,-), (-,+,-), (+,+,-); the sign on axis a flips for odd
   subdomain coordinate a.  ``phase`` swaps the two members of every pair.
-* Relaxation factors are per start corner (Sec. 2, w_SW, w_NE, ...): corner
+* Relaxation factors are per start corner (Sec. 3, omega_SW, omega_NE, ...): corner
   index = sum of 2**a over axes a whose sweep starts at the high end.
 * Preconditioners (Sec. 5; the paper never writes them out):
   SSOR:  z = (2-w) (D/w - N2)^-1 (D/w) (D/w - N1)^-1 r
@@ -359,7 +359,7 @@ def fgmres(apply_a, apply_m, f, rtol=1e-8, maxit=10000, restart=50):
 
 # ---------------------------------------------------------------- paper model problem
 def model_problem(dim, N):
-    """Laplace model problem of Sec. 7: u = prod x_i on the boundary of [0,1]^d.
+    """Laplace model problem of Sec. 8: u = prod x_i on the boundary of [0,1]^d.
 
     N points per axis including both boundary points, h = 1/(N-1); unit-spaced
     coefficients (a^X = 1, a^P = 2d); Dirichlet data folded into f.
@@ -396,7 +396,7 @@ L1_NORM = {1: lambda N: N, 2: lambda N: 3.0 * N * N, 3: lambda N: float(N) ** 3}
 
 
 def l1_error(dim, N, u, u_exact):
-    """L1 error as tabulated in Sec. 7 (normalisation decoded: N, 3N^2, N^3 in 1D/2D/3D)."""
+    """L1 error as tabulated in Sec. 8 (normalisation decoded: N, 3N^2, N^3 in 1D/2D/3D)."""
     return np.abs(u - u_exact).sum() / L1_NORM[dim](N)
 
 

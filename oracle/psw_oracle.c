@@ -17,7 +17,7 @@
  *      diag0[P] u_P - sum_{k>0} diag_k[P] u_{P+e_k} = f_P      (eq. d2d)
  *    and couplings that point outside the grid are ignored.
  *  - Subdomains: p[a] contiguous ranges per axis; the first n mod p ranges get
- *    ceil(n/p) points (Sec. 2.1 "almost equal" sub-domains).  Subdomain id
+ *    ceil(n/p) points (Sec. 3: sub-domains of nearly equal size).  Subdomain id
  *    s = r + p0*(q + p1*t).
  *  - A direction is a sign per axis: +1 sweeps towards increasing index.
  *    Neighbour X of P is "upstream" when it lies on the side where the sweep
@@ -121,7 +121,7 @@ static inline int sub_of(const grid_t *g, const int64_t c[3])
 static inline int dk(int a, int s) { return s < 0 ? 1 + 2 * a : 2 + 2 * a; }
 
 /* ------------------------------------------------------------------ */
-/* Direction schedule (Sec. 2.2 "Sweeping directions" rules, Sec. 4).
+/* Direction schedule (Sec. 3, Sweeping directions; Sec. 4).
  * The base cycle sigma_k is used by subdomain (0,0,0); along each axis the
  * sign is flipped for odd subdomain coordinates, so neighbours always sweep
  * in opposite directions.  Consecutive pairs (sigma_{2i}, sigma_{2i+1}) are
@@ -189,7 +189,7 @@ int or_spmv(int dim, const int64_t n[3], const double *const *diag, const double
 }
 
 /* Diagonals of the variable-coefficient operator -div(alpha grad u) + beta u
- * on a unit-spaced grid (eq. d2d with delta = 1; 1D eq. d1d; Sec. 6 general
+ * on a unit-spaced grid (eq. d2d with delta = 1; 1D eq. d1d; Sec. 7 general
  * molecule).  alpha[a] holds the axis-a coefficient on all (n+2)^dim nodes,
  * boundary ring included, node (i,j,k) at i + (n0+2)*(j + (n1+2)*k) with
  * interior point x at node x+1.  Face values are harmonic means of the two

@@ -3,7 +3,7 @@
 // One workgroup per tile.  The tile is swept in its local orientation
 // (towards +x, +y).  One 64-lane wave carries the recurrence: lane j owns R
 // consecutive rows and handles column x = s - j at step s, so each step is a
-// whole anti-diagonal of the tile (the frontal sweep of Sec. 2) and lane j
+// whole anti-diagonal of the tile (the frontal sweep of Sec. 3) and lane j
 // receives the new value of the row above it from lane j-1 by a cross-lane
 // shuffle.  The input vector tile (plus the partner column / row across the
 // coupled start faces) is staged in LDS by the whole workgroup with

@@ -32,7 +32,7 @@ using namespace psw;
 
 namespace {
 
-// Base direction cycle of tile (0,0,0) (Sec. 2.2 rules; Sec. 4 for 3D):
+// Base direction cycle of tile (0,0,0) (Sec. 3, Sweeping directions; Sec. 4 for 3D):
 // consecutive pairs are mutually reversed and each pair uses a new diagonal.
 const int kCycle2[4][3] = {{-1, -1, 1}, {+1, +1, 1}, {+1, -1, 1}, {-1, +1, 1}};
 const int kCycle3[8][3] = {{-1, -1, -1}, {+1, +1, +1}, {+1, -1, -1}, {-1, +1, +1},

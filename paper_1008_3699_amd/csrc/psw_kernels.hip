@@ -2,7 +2,7 @@
 //
 // Decomposed sweeps (Tavakoli, Secs. 2-5).  One workgroup owns one subdomain
 // ("tile").  Inside a tile the sweep advances one hyperplane level
-// t = l0 + l1 + l2 at a time (the frontal strategy of Sec. 2, fig. swp2d),
+// t = l0 + l1 + l2 at a time (the frontal strategy of Sec. 3, fig. swp2d),
 // in tile-local coordinates l in which the tile's sweep runs towards +l.
 // Threads own cross-section positions (l1, l2); the new value of a point is
 // published in LDS where the points of the next level read it.

@@ -59,6 +59,25 @@ def test_stationary_sweep(dim, n, p):
 PRECOND_CASES = SWEEP_CASES + [(2, (300, 250), (3, 2)), (2, (130, 128), (1, 1)), (2, (256, 190), (4, 3))]
 
 
+@pytest.mark.parametrize("dim,n,p", [(2, (37, 29), (5, 3)), (3, (12, 9, 10), (3, 2, 4))])
+def test_overlap_changes_no_result(dim, n, p):
+    """The overlap (halo depth >= 2) is a staging parameter: every value is the same for any overlap."""
+    pr, diags = _prob(dim, n)
+    g = make_problem(dim, n, pr["alphas"])
+    g.set_relaxation([1.4])
+    import torch
+    u = to_dev(pr["u"]); f = to_dev(pr["f"])
+    outs = []
+    for o in (2, 3, 5):
+        g.set_decomposition(p, overlap=o, phase=0)
+        out = torch.empty_like(u)
+        g.sweep(1, u, f, out)
+        outs.append(to_np(out))
+    assert all(np.array_equal(outs[0], x) for x in outs[1:])
+    ref = O.dsweep(dim, n, p, O.schedule(dim, p, 1, 0), diags, pr["f"], uold=pr["u"], omega=[1.4] * (1 << dim))
+    assert relmax(outs[0], ref) <= 1e-12
+
+
 @pytest.fixture(params=["pipelined", "generic"])
 def path(request, monkeypatch):
     """2D problems run the wavefront-pipelined kernels unless PSW_FORCE_GENERIC=1."""

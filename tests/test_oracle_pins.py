@@ -24,7 +24,7 @@ def _rows():
     return [pytest.param(r, id=f"{r['table']}-{r['method']}-{r['N']}") for r in rows]
 
 
-# ---------------------------------------------------------------- paper tables (Sec. 7)
+# ---------------------------------------------------------------- paper tables (Sec. 8)
 @pytest.mark.parametrize("row", _rows())
 def test_paper_sequential_rows(row):
     if row["dim"] == 2 and row["N"] > 101:
@@ -110,7 +110,7 @@ def test_assemble_harmonic_means():
     assert d[0][P] == pytest.approx(d[1][P] + d[2][P] + d[3][P] + d[4][P] + 0.25, rel=1e-15)
 
 
-# ---------------------------------------------------------------- schedule (Sec. 2.2, Sec. 4)
+# ---------------------------------------------------------------- schedule (Sec. 3 Sweeping directions, Sec. 4)
 def test_schedule_paper_2x2_example():
     """Fig. split2d text: sub-domains 1..4 (SW, SE, NW, NE boxes) start at NE, NW, SE, SW; then reversed."""
     d0 = O.schedule(2, (2, 2), 0)[:, :2].tolist()
@@ -352,7 +352,7 @@ def test_cg_and_fgmres_reach_direct_solution():
 
 
 def test_stationary_decomposed_converges_to_exact_model_solution():
-    """Model problem of Sec. 7: the parallel sweep converges to the d-linear exact solution."""
+    """Model problem of Sec. 8: the parallel sweep converges to the d-linear exact solution."""
     n, diags, f, ue = O.model_problem(2, 21)
     u, it, rel = O.stationary_solve(2, (n, n), (3, 2), diags, 1.5, f, rtol=1e-12)
     assert rel <= 1e-12 and np.max(np.abs(u - ue)) < 1e-10
