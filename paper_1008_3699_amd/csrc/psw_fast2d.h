@@ -5,8 +5,21 @@
 
 namespace psw {
 
-// steps of coefficient loads each lane keeps in flight
-constexpr int kFast2dDepth = 12;
+// Pipelined 2D passes.  The recurrence wave advances kFast2dBlk anti-diagonal
+// steps between workgroup barriers; the other waves stage / write back one
+// column block of kFast2dBlk columns per barrier interval.
+constexpr int kFast2dBlk = 16;
+// entries of a tile's step-offset table: [0] = bytes of the tile's packed
+// region, [1 + t] = byte offset of step t's first lane slot minus the lane
+// index times the slot size (so lane j reads at table value + j * slot).
+inline int fast2d_tab_len(int lx, int ly, int R) { return 1 + lx + (ly + R - 1) / R - 1 + 3 * kFast2dBlk + 16; }
+// packed elements of one tile: lx * L lane slots of R values, 64 zero slots, rounded to 256 bytes
+inline int64_t fast2d_tile_elems(int lx, int ly, int R, size_t elem) {
+    const int64_t L = (ly + R - 1) / R;
+    const int64_t e = (int64_t)(lx * L + 64) * R;
+    const int64_t a = (int64_t)(256 / elem);
+    return (e + a - 1) / a * a;
+}
 
 struct Fast2dDiag {
     const double *d[5];
@@ -21,6 +34,8 @@ struct Fast2dPass {
     int lxmax, lymax;
     const void *s_inv, *s_ax, *s_ay, *face;
     const int64_t *toff, *foff;
+    const int *otab;       // step-offset tables of all tiles
+    const int64_t *ooff;   // per tile: start of its table in otab
 };
 
 size_t fast2d_lds_bytes(int lx, int ly, int R, size_t elem);
@@ -28,6 +43,8 @@ size_t fast2d_lds_bytes(int lx, int ly, int R, size_t elem);
 hipError_t launch_pack2d(const PassGeom &g, Store s, int R, bool transposed, const double *const *diag,
                          const double *piv, const int64_t *toff, const int64_t *foff, void *s_inv, void *s_ax,
                          void *s_ay, void *face, hipStream_t st);
+// step-offset table of a tile (host); tab must hold fast2d_tab_len(lx, ly, R) entries
+void fast2d_fill_tab(int lx, int ly, int R, size_t elem, int *tab);
 
 hipError_t launch_fast2d(const Fast2dPass &p, Store s, const void *in, bool in_f64, bool scale_by_piv, void *out,
                          bool out_f64, double cscale, hipStream_t st);
@@ -58,6 +75,8 @@ struct BProb {
     int64_t N;
     const void *s_inv[4], *s_ax[4], *s_ay[4], *face[4]; // packed passes (storage precision)
     const int64_t *toff, *foff;                         // per tile of this problem
+    const int *otab;                                    // step-offset tables of this problem's tiles
+    const int64_t *ooff;
     const void *diagS[5];                               // storage-precision couplings (end faces)
     const void *pivS;                                   // storage-precision pivots
     const double *diag64[5];                            // FP64 operator

@@ -24,6 +24,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 namespace psw {
 
 // global-memory (address space 1) object type
@@ -114,37 +116,57 @@ __device__ __forceinline__ int gy_of(const Frame2 &f, int y) { return f.d1 > 0 ?
 } // namespace
 
 // ------------------------------------------------------------------ packing
-// Coefficients of one pass in sweep-major order plus the partner data of the
-// coupled start faces.  transposed: the couplings are those of the upstream
-// neighbour towards the point (a_{R->P}) and no face is coupled.
+// Coefficients of one pass in compact sweep-major order: step t = x + j of
+// lane j (rows R*j .. R*j+R-1) holds the lanes jlo(t)..jhi(t) that have a
+// point at that step, R values per lane, followed by 64 zero lane slots.
+// Also the partner data of the coupled start faces.  transposed: the
+// couplings are those of the upstream neighbour towards the point (a_{R->P})
+// and no face is coupled.
+
+// first lane slot of step t: the number of (column, lane) pairs at earlier steps
+__host__ __device__ __forceinline__ int64_t fast2d_step_base(int t, int lx, int L) {
+    const int64_t a = t <= L ? (int64_t)t * (t + 1) / 2 : (int64_t)L * (L + 1) / 2 + (int64_t)(t - L) * L;
+    const int64_t b = t <= lx ? 0 : (int64_t)(t - lx) * (t - lx + 1) / 2;
+    return a - b;
+}
+
 template <typename S>
 __device__ void pack2d_body(const Frame2 &F, int n0, int R, int transposed, const Fast2dDiag &dg,
                             const double *__restrict__ piv, S *s_inv, S *s_ax, S *s_ay, S *fc) {
     const bool cx = !transposed && F.cx, cy = !transposed && F.cy;
     const int L = (F.ly + R - 1) / R;
-    const int64_t nslots = (int64_t)(F.lx + L - 1 + kFast2dDepth) * 64 * R;
-    const int64_t base = 0;
-    for (int64_t sl = threadIdx.x; sl < nslots; sl += blockDim.x) {
-        const int r = (int)(sl % R), j = (int)((sl / R) % 64);
-        const int s = (int)(sl / (64 * R));
-        const int x = s - j, y = R * j + r;
-        double inv = 0, ax = 0, ay = 0;
-        if (j < L && x >= 0 && x < F.lx && y < F.ly) {
-            const int gx = gx_of(F, x), gy = gy_of(F, y);
-            const int64_t P = lin2(n0, gx, gy);
-            inv = 1.0 / piv[P];
-            if (x > 0 || cx) {
-                const int64_t Q = lin2(n0, gx - F.d0, gy);
-                ax = (transposed ? dg.d[dkk(0, +F.d0)][Q] : dg.d[dkk(0, -F.d0)][P]) * inv;
-            }
-            if (y > 0 || cy) {
-                const int64_t Q = lin2(n0, gx, gy - F.d1);
-                ay = (transposed ? dg.d[dkk(1, +F.d1)][Q] : dg.d[dkk(1, -F.d1)][P]) * inv;
-            }
+    const int64_t npairs = (int64_t)F.lx * L;
+    for (int64_t q = threadIdx.x; q < npairs + 64; q += blockDim.x) {
+        int64_t slot;
+        int x = 0, j = 0;
+        if (q < npairs) {
+            j = (int)(q / F.lx);
+            x = (int)(q - (int64_t)j * F.lx);
+            const int t = x + j;
+            slot = fast2d_step_base(t, F.lx, L) + (j - max(0, t - F.lx + 1));
+        } else {
+            slot = q; // the zero slots after the last step
         }
-        s_inv[base + sl] = from_f64<S>(inv);
-        s_ax[base + sl] = from_f64<S>(ax);
-        s_ay[base + sl] = from_f64<S>(ay);
+        for (int r = 0; r < R; ++r) {
+            double inv = 0, ax = 0, ay = 0;
+            const int y = R * j + r;
+            if (q < npairs && y < F.ly) {
+                const int gx = gx_of(F, x), gy = gy_of(F, y);
+                const int64_t P = lin2(n0, gx, gy);
+                inv = 1.0 / piv[P];
+                if (x > 0 || cx) {
+                    const int64_t Q = lin2(n0, gx - F.d0, gy);
+                    ax = (transposed ? dg.d[dkk(0, +F.d0)][Q] : dg.d[dkk(0, -F.d0)][P]) * inv;
+                }
+                if (y > 0 || cy) {
+                    const int64_t Q = lin2(n0, gx, gy - F.d1);
+                    ay = (transposed ? dg.d[dkk(1, +F.d1)][Q] : dg.d[dkk(1, -F.d1)][P]) * inv;
+                }
+            }
+            s_inv[slot * R + r] = from_f64<S>(inv);
+            s_ax[slot * R + r] = from_f64<S>(ax);
+            s_ay[slot * R + r] = from_f64<S>(ay);
+        }
     }
     // partner data of the coupled start faces, per row (x face) / column (y face):
     // [1/Piv_Q, a'_{Q->P}, a'_{Q->upstream along the face}, 1/(1 - a'_{P->Q} a'_{Q->P})]
@@ -211,366 +233,360 @@ template <typename S, typename TIN, typename TOUT> struct Fast2dArgs {
     PassGeom g;
     const S *s_inv, *s_ax, *s_ay, *face;
     const int64_t *toff, *foff;
+    const int *otab;
+    const int64_t *ooff;
     const TIN *in;
     TOUT *out;
-    int scale_by_piv; // rhs' = in (backward passes) instead of in / Piv
-    int coupled;      // start faces coupled (0 for the transposed passes)
     double cscale;
-    int pitch_max;
 };
 
-// value of lane j-1 in lane j (0 in lane 0): one DPP wave shift per 32 bits
+// value of lane j-1 in lane j and 0 in lane 0: one DPP wave shift per 32 bits
+// (bound_ctrl writes 0 where there is no source lane)
 __device__ __forceinline__ float lane_up(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 __device__ __forceinline__ double lane_up(double v) {
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), 0x138, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffff), 0x138, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x138, 0xf, 0xf, true);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Raw buffer loads of one lane's R coefficients: lanes with nothing to do
-// pass an offset beyond the buffer's range and read zero without a memory
-// access, so every ring refill is an unconditional instruction.
 constexpr int kBufCfg = 0x00020000; // gfx9 buffer resource word 3
-constexpr int kOutOfRange = 0x7ffffff0;
-constexpr int kStageBatch = 16; // global loads in flight per thread while staging
+constexpr int kPf = 4;              // steps by which right-hand sides and face records are read ahead
 
-template <typename V> __device__ __forceinline__ V ldbuf(__amdgpu_buffer_rsrc_t r, int off);
-template <> __device__ __forceinline__ double2 ldbuf<double2>(__amdgpu_buffer_rsrc_t r, int off) {
-    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+// raw buffer load of one lane slot (R values of type S): vector offset voff, scalar offset soff
+template <typename V> __device__ __forceinline__ V ldbuf(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <> __device__ __forceinline__ double2 ldbuf<double2>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
-template <> __device__ __forceinline__ double ldbuf<double>(__amdgpu_buffer_rsrc_t r, int off) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+template <> __device__ __forceinline__ double ldbuf<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
-template <> __device__ __forceinline__ float2 ldbuf<float2>(__amdgpu_buffer_rsrc_t r, int off) {
-    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+template <> __device__ __forceinline__ float2 ldbuf<float2>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
-template <> __device__ __forceinline__ float ldbuf<float>(__amdgpu_buffer_rsrc_t r, int off) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+template <> __device__ __forceinline__ float ldbuf<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
-template <> __device__ __forceinline__ uint32_t ldbuf<uint32_t>(__amdgpu_buffer_rsrc_t r, int off) {
-    return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+template <> __device__ __forceinline__ uint32_t ldbuf<uint32_t>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
 }
-template <> __device__ __forceinline__ uint16_t ldbuf<uint16_t>(__amdgpu_buffer_rsrc_t r, int off) {
-    return __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+template <> __device__ __forceinline__ uint16_t ldbuf<uint16_t>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
 }
 
-// One tile of a pass.  in / out point at the problem's vectors (indexed by
-// x + n0*y), s_* and fsrc at the tile's packed coefficients and face records.
+// LDS pitch (elements) of the tile: at least lx + 2, and such that the
+// anti-diagonal accesses of the wave (stride R * pitch - 1) hit distinct banks
+__host__ __device__ __forceinline__ int fast2d_pitch(int lx, int R) {
+    int p = lx + 2;
+    if (((R * p - 1) & 1) == 0) ++p;
+    return p;
+}
+
+// One tile of a pass.  The tile is swept in local orientation (towards +x,
+// +y); the LDS copy of the input tile uses local coordinates too, with the
+// partners across the coupled start faces in column / row -1.
+//   wave 0     : the recurrence, kFast2dBlk anti-diagonal steps per barrier
+//                interval; lane j owns rows R*j .. R*j+R-1 and handles column
+//                x = s - j at step s; the row above arrives by a DPP shift.
+//   waves 1..3 : stage column block i + 2 and write back column block i - lag
+//                (all of whose points are final) during interval i.
+// Coefficients stream from the compact sweep-major packing through a
+// register ring of RING steps; the right-hand sides and face records come
+// from LDS kPf steps ahead.  Lanes without a point at a step compute with
+// another slot's coefficients and finite LDS values; their results reach
+// no lane that has a point and are written to a per-lane sink.
 template <int R, typename T, typename S, typename TIN, typename TOUT, bool SC, bool CPL>
 __device__ __forceinline__ void fast2d_body(const Frame2 &F, int n0, const GP<TIN> *__restrict__ in,
                                             GP<TOUT> *__restrict__ out, const S *s_inv_t, const S *s_ax_t,
-                                            const S *s_ay_t, const GP<S> *fsrc, double cscale, unsigned char *smem) {
+                                            const S *s_ay_t, const GP<int> *__restrict__ tab, const GP<S> *fsrc,
+                                            double cscale, unsigned char *smem) {
     using V = typename Pack<S, R>::V;
-    constexpr int D = kFast2dDepth;
+    constexpr int RING = SC ? 16 : 8;
+    constexpr int KB = kFast2dBlk;
     const bool cx = CPL && F.cx, cy = CPL && F.cy;
     const int lx = F.lx, ly = F.ly;
-    // LDS: vector tile in global orientation with a one-point ring, pitch chosen
-    // so that the wave's anti-diagonal reads hit distinct banks
-    int pitch = lx + 2;
-    if ((R * pitch) & 1) ++pitch;
+    const int L = (ly + R - 1) / R;
+    const int nsteps = lx + L - 1;
+    const int niter = (nsteps + KB - 1) / KB;
+    const int nblk = (lx + KB - 1) / KB;
+    const int lag = (L + KB - 2) / KB + 1; // block c is final after interval c + lag - 1
+    const int pitch = fast2d_pitch(lx, R);
     T *vt = reinterpret_cast<T *>(smem);
-    T *fx = vt + (size_t)(ly + 2) * pitch; // x-face partner records (4 values per row)
-    T *fy = fx + 4 * ly;                   // y-face partner records (4 values per column)
-    T *fk = fy + 4 * lx;                   // cross point partner (3)
-    const int sink = (int)((fk + 4) - vt);  // scratch slot for writes of idle lanes
-    const int tid = threadIdx.x, nth = blockDim.x;
+    const int sink = (ly + 2) * pitch;             // 64 + (R - 1) * pitch sink slots
+    T *fx = vt + ((sink + 64 + pitch + 3) & ~3);   // x-face partner records (4 per row)
+    T *fy = fx + 4 * ly;                           // y-face partner records (4 per column)
+    T *fk = fy + 4 * lx;                           // cross-point partner (3)
+    const int tid = threadIdx.x;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
 
-    // ---- stage the input tile (+ partners) into LDS: each wave takes whole
-    // rows in 64-column chunks and keeps kStageBatch loads in flight
-    const int wid = tid >> 6, ln = tid & 63, nw = nth >> 6;
-    const int cpr = (lx + 63) >> 6; // 64-column chunks per row
-    const int nitems = ly * cpr;
-    for (int it0 = wid; it0 < nitems; it0 += nw * kStageBatch) {
-        T v[kStageBatch];
-#pragma unroll
-        for (int u = 0; u < kStageBatch; ++u) {
-            const int it = it0 + u * nw;
-            const int row = it / cpr, col = (it - row * cpr) * 64 + ln;
-            const bool ok = it < nitems && col < lx;
-            v[u] = ok ? cvt<T>(in[lin2(n0, F.lox + col, F.loy + row)]) : T(0);
-        }
-#pragma unroll
-        for (int u = 0; u < kStageBatch; ++u) {
-            const int it = it0 + u * nw;
-            const int row = it / cpr, col = (it - row * cpr) * 64 + ln;
-            if (it < nitems && col < lx) vt[(row + 1) * pitch + col + 1] = v[u];
-        }
+    // ---- borders: partner column / row (or zeros), zero padding column lx and row ly
+    for (int r = tid; r < ly + 2; r += 256) {
+        T v = T(0);
+        if (cx && r >= 1 && r <= ly) v = cvt<T>(in[lin2(n0, gx_of(F, -1), gy_of(F, r - 1))]);
+        if (cx && cy && r == 0) v = cvt<T>(in[lin2(n0, gx_of(F, -1), gy_of(F, -1))]);
+        vt[r * pitch] = v;
+        vt[r * pitch + lx + 1] = T(0);
     }
-    if (cx) {
-        const int gx = gx_of(F, -1), col = F.d0 > 0 ? 0 : lx + 1;
-        for (int row = tid; row < ly; row += nth) vt[(row + 1) * pitch + col] = cvt<T>(in[lin2(n0, gx, F.loy + row)]);
+    for (int c = tid; c < lx; c += 256) {
+        vt[c + 1] = cy ? cvt<T>(in[lin2(n0, gx_of(F, c), gy_of(F, -1))]) : T(0);
+        vt[(ly + 1) * pitch + c + 1] = T(0);
     }
-    if (cy) {
-        const int gy = gy_of(F, -1), row = F.d1 > 0 ? 0 : ly + 1;
-        for (int col = tid; col < lx; col += nth) vt[row * pitch + col + 1] = cvt<T>(in[lin2(n0, F.lox + col, gy)]);
-    }
-    if (cx && cy && tid == 0) {
-        const int col = F.d0 > 0 ? 0 : lx + 1, row = F.d1 > 0 ? 0 : ly + 1;
-        vt[row * pitch + col] = cvt<T>(in[lin2(n0, gx_of(F, -1), gy_of(F, -1))]);
-    }
-    for (int i = tid; i < 4 * (lx + ly) + 3; i += nth) fx[i] = cvt<T>(fsrc[i]);
-    __syncthreads();
+    if (CPL)
+        for (int i = tid; i < 4 * (lx + ly) + 3; i += 256) fx[i] = cvt<T>(fsrc[i]);
 
-    // ---- the recurrence: wave 0
-    if (tid < 64) {
-        const int lane = tid;
-        const int L = (ly + R - 1) / R;
-        const int nr = lane < L ? min(R, ly - R * lane) : 0;
-        const int rlast = nr > 0 ? nr - 1 : 0;
-        const int nsteps = lx + L - 1;
-        const int nbytes = (lx + L - 1 + D) * 64 * R * (int)sizeof(S);
-        const __amdgpu_buffer_rsrc_t rinv = __builtin_amdgcn_make_buffer_rsrc((void *)s_inv_t, 0, nbytes, kBufCfg);
-        const __amdgpu_buffer_rsrc_t rax = __builtin_amdgcn_make_buffer_rsrc((void *)s_ax_t, 0, nbytes, kBufCfg);
-        const __amdgpu_buffer_rsrc_t ray = __builtin_amdgcn_make_buffer_rsrc((void *)s_ay_t, 0, nbytes, kBufCfg);
-        constexpr bool sc = SC;
-        const int vbytes = R * (int)sizeof(S);
-        auto boff = [&](int s) -> int {
-            const int x = s - lane;
-            return (nr > 0 && x >= 0 && x < lx) ? (s * 64 + lane) * vbytes : kOutOfRange;
-        };
-        // LDS addressing in local orientation
-        const int cstep = F.d0 > 0 ? 1 : -1, col0 = F.d0 > 0 ? 1 : lx; // column of local x = 0
-        const int rstep = F.d1 > 0 ? pitch : -pitch, row0 = (F.d1 > 0 ? 1 : ly) * pitch;
-        const int lane_c = min(lane, L - 1); // idle lanes address the last active lane's rows
-        const int rowbase = row0 + rstep * (R * lane_c);
-        V ri[D], ra[D], rb[D];
+    // ---- staging / write-back of column blocks by waves 1..3
+    constexpr int NH = 192;
+    constexpr int NB = (128 * KB + NH - 1) / NH;
+    const int ht = tid - 64;
+    auto stage = [&](int b) {
+        const int c0 = b * KB, nc = min(KB, lx - c0);
+        T v[NB];
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-            const int o = boff(k);
-            if (!sc) ri[k] = ldbuf<V>(rinv, o);
-            ra[k] = ldbuf<V>(rax, o);
-            rb[k] = ldbuf<V>(ray, o);
+        for (int u = 0; u < NB; ++u) {
+            const int e = ht + NH * u;
+            const int y = e / KB, c = e - y * KB;
+            v[u] = (y < ly && c < nc) ? cvt<T>(in[lin2(n0, gx_of(F, c0 + c), gy_of(F, y))]) : T(0);
         }
-        T left[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) left[r] = T(0);
-        T last = T(0);   // value of this lane's last row at the previous step
-        T xplast = T(0); // x-face partner of this lane's last row (set at x = 0)
-        T yprev = T(0);  // y-face partner at the previous column (lane 0, row 0)
-
-        // ---- step 0: only lane 0 works (local column 0); it holds the cross point
-        {
-            const int x = -lane;
-            if (lane == 0 && nr > 0 && lx > 0) {
-                T up = T(0), upx = T(0);
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    if (r < nr) {
-                        const int y = r;
-                        const int a = rowbase + rstep * r + col0;
-                        const T iv = sc ? T(1) : elem<T>(ri[0], r);
-                        const T ax = elem<T>(ra[0], r), ay = elem<T>(rb[0], r);
-                        const T rhs = sc ? vt[a] : iv * vt[a];
-                        T v, vq = T(0);
-                        if (cx && y == 0 && cy) {
-                            // cross point: A=(0,0), B=(-1,0), C=(0,-1), D=(-1,-1)
-                            const int aq = a - cstep, ac = a - rstep, ad = a - rstep - cstep;
-                            const T ivq = fx[0], aqp = fx[1], aqy = fx[2];
-                            const T ivc = fy[0], acp = fy[1], acd = fy[2];
-                            const T ivd = fk[0], adb = fk[1], adc = fk[2];
-                            const T rq = sc ? vt[aq] : ivq * vt[aq];
-                            const T rc = sc ? vt[ac] : ivc * vt[ac];
-                            const T rd = sc ? vt[ad] : ivd * vt[ad];
-                            T M[4][4] = {{T(1), -ax, -ay, T(0)},
-                                         {-aqp, T(1), T(0), -aqy},
-                                         {-acp, T(0), T(1), -acd},
-                                         {T(0), -adb, -adc, T(1)}};
-                            T b[4] = {rhs, rq, rc, rd};
-#pragma unroll
-                            for (int p = 0; p < 4; ++p) {
-                                const T ip = T(1) / M[p][p];
-#pragma unroll
-                                for (int i = p + 1; i < 4; ++i) {
-                                    const T l = M[i][p] * ip;
-#pragma unroll
-                                    for (int jj = p + 1; jj < 4; ++jj) M[i][jj] -= l * M[p][jj];
-                                    b[i] -= l * b[p];
-                                }
-                            }
-#pragma unroll
-                            for (int i = 3; i >= 0; --i) {
-                                T acc = b[i];
-#pragma unroll
-                                for (int jj = i + 1; jj < 4; ++jj) acc -= M[i][jj] * b[jj];
-                                b[i] = acc / M[i][i];
-                            }
-                            v = b[0];
-                            vq = b[1];
-                            yprev = b[2];
-                        } else if (cx) {
-                            const int aq = a - cstep;
-                            const T ivq = fx[4 * y], aqp = fx[4 * y + 1], aqy = fx[4 * y + 2], idt = fx[4 * y + 3];
-                            const T rq = sc ? vt[aq] : ivq * vt[aq];
-                            const T bq = rq + aqy * upx;
-                            v = idt * (rhs + ax * bq + ay * up);
-                            vq = bq + aqp * v;
-                        } else if (y == 0 && cy) {
-                            const int aq = a - rstep;
-                            const T ivq = fy[0], aqp = fy[1], idt = fy[3];
-                            const T rq = sc ? vt[aq] : ivq * vt[aq];
-                            v = idt * (rhs + ay * rq);
-                            vq = rq + aqp * v;
-                            yprev = vq;
-                        } else {
-                            v = rhs + ay * up;
-                        }
-                        vt[a] = v;
-                        left[r] = v;
-                        up = v;
-                        upx = vq;
-                    }
-                }
-                last = up;
-                xplast = upx;
-            }
-            (void)x;
-            const int o = boff(D);
-            if (!sc) ri[0] = ldbuf<V>(rinv, o);
-            ra[0] = ldbuf<V>(rax, o);
-            rb[0] = ldbuf<V>(ray, o);
+        for (int u = 0; u < NB; ++u) {
+            const int e = ht + NH * u;
+            const int y = e / KB, c = e - y * KB;
+            if (y < ly && c < nc) vt[(y + 1) * pitch + c0 + c + 1] = v[u];
         }
-
-        // ---- prologue, steps 1..Ps-1 (lane j meets the x face at step j):
-        // straight-line, face pairs formed with selects, idle lanes write to a
-        // scratch slot, so the coefficient loads stay D steps ahead.
-        const int Ps = 1 + D * ((L - 1 + D - 1) / D);
-        for (int s0 = 1; s0 < Ps; s0 += D) {
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-                const int slot = (1 + k) % D;
-                const int s = s0 + k;
-                T up = lane_up(last);
-                T upx = lane_up(xplast);
-                const int x = s - lane;
-                const bool act = nr > 0 && x >= 0 && x < lx;
-                const int xc = min(max(x, 0), lx - 1);
-                const int cidx = col0 + cstep * xc;
-                const bool isx0 = cx && x == 0;
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int rr = min(r, rlast);
-                    const bool valid = act && r < nr;
-                    const int y = R * lane_c + rr;
-                    const int a = rowbase + rstep * rr + cidx;
-                    const T iv = sc ? T(1) : elem<T>(ri[slot], r);
-                    const T ax = elem<T>(ra[slot], r), ay = elem<T>(rb[slot], r);
-                    const T rhs = sc ? vt[a] : iv * vt[a];
-                    const bool isx = isx0;
-                    const bool isy = cy && y == 0 && !isx;
-                    // partner record of this point's face (x face: row y, y face: column x)
-                    const T *fp = isx ? fx + 4 * y : fy + 4 * xc;
-                    const T ivq = fp[0], aqp = fp[1], aqu = fp[2], idt = fp[3];
-                    const int aq = a - (isx ? cstep : rstep);
-                    const T vq_in = vt[aq];
-                    const T rq = sc ? vq_in : ivq * vq_in;
-                    const T bq = rq + aqu * (isx ? upx : yprev);
-                    const bool face = isx || isy;
-                    const T L0 = isx ? bq : left[r];
-                    const T U0 = isy ? bq : up;
-                    const T c0 = face ? idt : T(1);
-                    const T v = c0 * (rhs + ax * L0 + ay * U0);
-                    const T vq = bq + aqp * v;
-                    yprev = (valid && isy) ? vq : yprev;
-                    vt[valid ? a : sink] = v;
-                    left[r] = valid ? v : left[r];
-                    up = valid ? v : up;
-                    upx = valid ? vq : upx;
-                }
-                last = act ? up : last;
-                xplast = (act && x == 0) ? upx : xplast;
-                // refill this ring slot with step s + D
-                const int o = boff(s + D);
-                if (!sc) ri[slot] = ldbuf<V>(rinv, o);
-                ra[slot] = ldbuf<V>(rax, o);
-                rb[slot] = ldbuf<V>(ray, o);
-            }
-        }
-
-        // ---- main phase, steps Ps..nsteps-1: every active point has x >= 1, so
-        // only lane 0 (row 0) carries a face, the y-face chain; its partner
-        // record is read at lane 0's column by all lanes (an LDS broadcast).
-        const bool l0cy = (lane == 0) && cy;
-        const int rowq = row0 - rstep; // LDS row of the y-face partners
-        // right-hand sides of the next step, read before this step's writes
-        T rn[R];
-        {
-            const int a0 = rowbase + col0 + cstep * min(max(Ps - lane, 0), lx - 1);
-#pragma unroll
-            for (int r = 0; r < R; ++r) rn[r] = vt[a0 + rstep * min(r, rlast)];
-        }
-        for (int s0 = Ps; s0 < nsteps; s0 += D) {
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-                const int slot = (1 + k) % D;
-                const int s = s0 + k;
-                const T up_in = lane_up(last);
-                const int x = s - lane;
-                const bool act = nr > 0 && x < lx;
-                const int a0 = rowbase + col0 + cstep * min(x, lx - 1);
-                T rc[R];
-                {
-                    const int an = rowbase + col0 + cstep * min(x + 1, lx - 1);
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        rc[r] = rn[r];
-                        rn[r] = vt[an + rstep * min(r, rlast)];
-                    }
-                }
-                const int x0 = min(s, lx - 1);
-                const T *fp = fy + 4 * x0;
-                const T ivq = fp[0], aqp = fp[1], aqu = fp[2], idt = fp[3];
-                const T vq_in = vt[rowq + col0 + cstep * x0];
-                const T bq = (sc ? vq_in : ivq * vq_in) + aqu * yprev;
-                T up = l0cy ? bq : up_in;
-                const T c0 = l0cy ? idt : T(1);
-                T v0 = T(0);
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const bool valid = act && r < nr;
-                    const int a = a0 + rstep * min(r, rlast);
-                    const T iv = sc ? T(1) : elem<T>(ri[slot], r);
-                    const T ax = elem<T>(ra[slot], r), ay = elem<T>(rb[slot], r);
-                    const T rhs = sc ? rc[r] : iv * rc[r];
-                    T v = rhs + ax * left[r] + ay * up;
-                    if (r == 0) {
-                        v = c0 * v;
-                        v0 = v;
-                    }
-                    vt[valid ? a : sink] = v;
-                    left[r] = v;
-                    up = (r < nr) ? v : up;
-                }
-                last = up;
-                yprev = bq + aqp * v0;
-                const int o = boff(s + D);
-                if (!sc) ri[slot] = ldbuf<V>(rinv, o);
-                ra[slot] = ldbuf<V>(rax, o);
-                rb[slot] = ldbuf<V>(ray, o);
-            }
-        }
-    }
-    __syncthreads();
-
-    // ---- write the tile back, same row-chunk order
+    };
     const T cs = (T)cscale;
-    for (int it0 = wid; it0 < nitems; it0 += nw * kStageBatch) {
-        T v[kStageBatch];
+    auto wback = [&](int b) {
+        const int c0 = b * KB, nc = min(KB, lx - c0);
+        T v[NB];
 #pragma unroll
-        for (int u = 0; u < kStageBatch; ++u) {
-            const int it = it0 + u * nw;
-            const int row = it / cpr, col = (it - row * cpr) * 64 + ln;
-            v[u] = (it < nitems && col < lx) ? vt[(row + 1) * pitch + col + 1] : T(0);
+        for (int u = 0; u < NB; ++u) {
+            const int e = ht + NH * u;
+            const int y = e / KB, c = e - y * KB;
+            v[u] = (y < ly && c < nc) ? vt[(y + 1) * pitch + c0 + c + 1] : T(0);
         }
 #pragma unroll
-        for (int u = 0; u < kStageBatch; ++u) {
-            const int it = it0 + u * nw;
-            const int row = it / cpr, col = (it - row * cpr) * 64 + ln;
-            if (it < nitems && col < lx) out[lin2(n0, F.lox + col, F.loy + row)] = (TOUT)(cs * v[u]);
+        for (int u = 0; u < NB; ++u) {
+            const int e = ht + NH * u;
+            const int y = e / KB, c = e - y * KB;
+            if (y < ly && c < nc) out[lin2(n0, gx_of(F, c0 + c), gy_of(F, y))] = (TOUT)(cs * v[u]);
+        }
+    };
+    if (wv >= 1) {
+        stage(0);
+        if (nblk > 1) stage(1);
+    }
+    __syncthreads();
+
+    // ---- recurrence state (wave 0)
+    const int lane_c = min(lane, L - 1);
+    const int rowa = (R * lane_c + 1) * pitch + 1; // LDS index of (x = 0, first row of this lane)
+    const int nbytes = tab[0];
+    const __amdgpu_buffer_rsrc_t rinv = __builtin_amdgcn_make_buffer_rsrc((void *)s_inv_t, 0, nbytes, kBufCfg);
+    const __amdgpu_buffer_rsrc_t rax = __builtin_amdgcn_make_buffer_rsrc((void *)s_ax_t, 0, nbytes, kBufCfg);
+    const __amdgpu_buffer_rsrc_t ray = __builtin_amdgcn_make_buffer_rsrc((void *)s_ay_t, 0, nbytes, kBufCfg);
+    const int voff = lane * R * (int)sizeof(S);
+    V ri[RING], ra[RING], rb[RING];
+    T rc[kPf][R];                 // right-hand sides of the next kPf steps
+    constexpr int kPy = 2;
+    T yq[kPy][5];                 // y-face record and partner value of the next kPy columns
+    T left[R];
+    T last = T(0), yprev = T(0), xplast = T(0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) left[r] = T(0);
+    if (wv == 0) {
+#pragma unroll
+        for (int k = 0; k < RING; ++k) {
+            const int so = tab[1 + k];
+            if (!SC) ri[k] = ldbuf<V>(rinv, voff, so);
+            ra[k] = ldbuf<V>(rax, voff, so);
+            rb[k] = ldbuf<V>(ray, voff, so);
+        }
+#pragma unroll
+        for (int k = 0; k < kPf; ++k) {
+            const int x = min(max(k - lane, -1), lx);
+#pragma unroll
+            for (int r = 0; r < R; ++r) rc[k][r] = vt[rowa + r * pitch + x];
+            if (CPL && k < kPy) {
+                const int xq = min(k, lx - 1);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) yq[k][q] = fy[4 * xq + q];
+                yq[k][4] = vt[xq + 1];
+            }
         }
     }
+
+    // x-face data of this lane's rows (partner in column -1): 1/Piv_Q * r_Q (or r_Q), a'_{Q->P},
+    // a'_{Q->upstream}, 1/det; read once, used when the lane reaches x = 0
+    const bool l0 = lane == 0;
+    T xrq[R], xaqp[R], xaqu[R], xidt[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        xrq[r] = T(0);
+        xaqp[r] = T(0);
+        xaqu[r] = T(0);
+        xidt[r] = T(1);
+    }
+    // cross point (cx and cy): lane 0's results at step 0, solved once before the loop
+    T cpv[R], cpupx = T(0), cpyprev = T(0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) cpv[r] = T(0);
+    if (CPL && cx && wv == 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int y = R * lane_c + r;
+            const T vq = vt[rowa + r * pitch - 1];
+            xrq[r] = SC ? vq : fx[4 * y] * vq;
+            xaqp[r] = fx[4 * y + 1];
+            xaqu[r] = fx[4 * y + 2];
+            xidt[r] = fx[4 * y + 3];
+        }
+        if (cy) {
+            // A = (0,0), B = (-1,0), C = (0,-1), D = (-1,-1); step 0 uses ring slot 0
+            const T iv = SC ? T(1) : elem<T>(ri[0], 0);
+            const T ax = elem<T>(ra[0], 0), ay = elem<T>(rb[0], 0);
+            const T rhs = SC ? rc[0][0] : iv * rc[0][0];
+            const T ivq = fx[0], aqp = fx[1], aqy = fx[2];
+            const T ivc = fy[0], acp = fy[1], acd = fy[2];
+            const T ivd = fk[0], adb = fk[1], adc = fk[2];
+            const T vb = vt[pitch], vc = vt[1], vd = vt[0];
+            const T rq = SC ? vb : ivq * vb, rcc = SC ? vc : ivc * vc, rd = SC ? vd : ivd * vd;
+            T M[4][4] = {{T(1), -ax, -ay, T(0)}, {-aqp, T(1), T(0), -aqy}, {-acp, T(0), T(1), -acd}, {T(0), -adb, -adc, T(1)}};
+            T bb[4] = {rhs, rq, rcc, rd};
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const T ip = T(1) / M[p][p];
+#pragma unroll
+                for (int i = p + 1; i < 4; ++i) {
+                    const T l = M[i][p] * ip;
+#pragma unroll
+                    for (int jj = p + 1; jj < 4; ++jj) M[i][jj] -= l * M[p][jj];
+                    bb[i] -= l * bb[p];
+                }
+            }
+#pragma unroll
+            for (int i = 3; i >= 0; --i) {
+                T acc = bb[i];
+#pragma unroll
+                for (int jj = i + 1; jj < 4; ++jj) acc -= M[i][jj] * bb[jj];
+                bb[i] = acc / M[i][i];
+            }
+            cpv[0] = bb[0];
+            cpupx = bb[1];
+            cpyprev = bb[2];
+            if (R == 2) {
+                // row 1 of lane 0: an x-face pair whose upstream partner is B and whose upper neighbour is A
+                const T iv1 = SC ? T(1) : elem<T>(ri[0], 1);
+                const T ax1 = elem<T>(ra[0], 1), ay1 = elem<T>(rb[0], 1);
+                const T rhs1 = SC ? rc[0][R - 1] : iv1 * rc[0][R - 1];
+                const T bq1 = xrq[R - 1] + xaqu[R - 1] * bb[1];
+                cpv[R - 1] = xidt[R - 1] * (rhs1 + ax1 * bq1 + ay1 * bb[0]);
+                cpupx = bq1 + xaqp[R - 1] * cpv[R - 1];
+            }
+        }
+    }
+
+    // one step; XF: some lane may be at x = 0 (the x-face pairs and the cross point)
+    auto step = [&](const int s, const int k, const bool XF) {
+        const int slot = k % RING, pk = k % kPf;
+        const int x = s - lane;
+        const T up_in = lane_up(last);
+        const T upx_in = XF ? lane_up(xplast) : T(0);
+        T cur[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) cur[r] = rc[pk][r];
+        {
+            const int xn = min(max(s + kPf - lane, -1), lx);
+#pragma unroll
+            for (int r = 0; r < R; ++r) rc[pk][r] = vt[rowa + r * pitch + xn];
+        }
+        // y face: lane 0, row 0, column s (partner Q in row -1)
+        T up0 = up_in, cy0 = T(1), bqy = T(0), aqpy = T(0);
+        if (CPL && cy) {
+            const int py = k % kPy;
+            const T ivq = yq[py][0], aqp = yq[py][1], aqu = yq[py][2], idt = yq[py][3], vq = yq[py][4];
+            const int xq = min(s + kPy, lx - 1);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) yq[py][q] = fy[4 * xq + q];
+            yq[py][4] = vt[xq + 1];
+            bqy = (SC ? vq : ivq * vq) + aqu * yprev;
+            aqpy = aqp;
+            up0 = l0 ? bqy : up_in;
+            cy0 = l0 ? idt : T(1);
+        }
+        const bool isx = XF && cx && x == 0;
+        T v[R];
+        T upx = upx_in;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const T iv = SC ? T(1) : elem<T>(ri[slot], r);
+            const T ax = elem<T>(ra[slot], r), ay = elem<T>(rb[slot], r);
+            const T rhs = SC ? cur[r] : iv * cur[r];
+            const T u = r == 0 ? up0 : v[r - 1];
+            T lf = left[r];
+            T c0 = r == 0 ? cy0 : T(1);
+            T bqx = T(0);
+            if (XF && cx) {
+                bqx = xrq[r] + xaqu[r] * upx;
+                lf = isx ? bqx : lf;
+                c0 = isx ? xidt[r] : c0;
+            }
+            const T val = c0 * (rhs + ax * lf + ay * u);
+            if (XF && cx) upx = isx ? bqx + xaqp[r] * val : upx;
+            v[r] = val;
+        }
+        if (XF && k == 0 && cx && cy && s == 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[r] = l0 ? cpv[r] : v[r];
+            upx = l0 ? cpupx : upx;
+        }
+        if (CPL && cy) {
+            const T yn = bqy + aqpy * v[0];
+            yprev = (XF && k == 0 && cx && s == 0) ? cpyprev : yn;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) left[r] = v[r];
+        last = v[R - 1];
+        if (XF && cx) xplast = isx ? upx : xplast;
+        const bool act = x >= 0 && x < lx && lane < L;
+        const int a = act ? rowa + x : sink + lane;
+#pragma unroll
+        for (int r = 0; r < R; ++r) vt[a + r * pitch] = v[r];
+        const int so = tab[1 + s + RING];
+        if (!SC) ri[slot] = ldbuf<V>(rinv, voff, so);
+        ra[slot] = ldbuf<V>(rax, voff, so);
+        rb[slot] = ldbuf<V>(ray, voff, so);
+    };
+
+    // helper waves: stage block i + 2, write back block i - lag
+    auto helpers = [&](int i) {
+        if (i + 2 < nblk) stage(i + 2);
+        if (i - lag >= 0 && i - lag < nblk) wback(i - lag);
+    };
+    // intervals in which some lane meets the x face, then the rest
+    const int nxf = (CPL && cx) ? min(niter, (L + KB - 1) / KB) : 0;
+    for (int i = 0; i < nxf; ++i) {
+        if (wv == 0) {
+#pragma unroll
+            for (int k = 0; k < KB; ++k) step(i * KB + k, k, CPL);
+        } else {
+            helpers(i);
+        }
+        __syncthreads();
+    }
+    for (int i = nxf; i < niter; ++i) {
+        if (wv == 0) {
+#pragma unroll
+            for (int k = 0; k < KB; ++k) step(i * KB + k, k, false);
+        } else {
+            helpers(i);
+        }
+        __syncthreads();
+    }
+    if (wv >= 1)
+        for (int b = max(0, niter - lag); b < nblk; ++b) wback(b);
 }
 
 template <int R, typename T, typename S, typename TIN, typename TOUT, bool SC, bool CPL>
@@ -580,8 +596,8 @@ __global__ void __launch_bounds__(256) k_fast2d(Fast2dArgs<S, TIN, TOUT> A) {
     const Frame2 F = frame2(A.g, td);
     const int64_t t = A.toff[blockIdx.x];
     fast2d_body<R, T, S, TIN, TOUT, SC, CPL>(F, A.g.n[0], (const GP<TIN> *)A.in, (GP<TOUT> *)A.out, A.s_inv + t,
-                                              A.s_ax + t, A.s_ay + t, (const GP<S> *)(A.face + A.foff[blockIdx.x]),
-                                              A.cscale, smem);
+                                              A.s_ax + t, A.s_ay + t, (const GP<int> *)(A.otab + A.ooff[blockIdx.x]),
+                                              (const GP<S> *)(A.face + A.foff[blockIdx.x]), A.cscale, smem);
 }
 
 // ------------------------------------------------------------------ end-face chains (2D), prefetched
@@ -769,10 +785,22 @@ __global__ void k_end_corners2d(EndFaceArgs<T, S, TIN, TOUT> A) {
 }
 
 // ------------------------------------------------------------------ launchers
+void fast2d_fill_tab(int lx, int ly, int R, size_t elem, int *tab) {
+    const int L = (ly + R - 1) / R, nsteps = lx + L - 1;
+    const int n = fast2d_tab_len(lx, ly, R);
+    tab[0] = (int)(fast2d_tile_elems(lx, ly, R, elem) * (int64_t)elem);
+    const int64_t end = (int64_t)lx * L;
+    for (int t = 0; t < n - 1; ++t) {
+        const int64_t slot = t < nsteps ? fast2d_step_base(t, lx, L) - std::max(0, t - lx + 1) : end;
+        tab[1 + t] = (int)(slot * R * (int64_t)elem);
+    }
+}
+
 size_t fast2d_lds_bytes(int lx, int ly, int R, size_t elem) {
-    int pitch = lx + 2;
-    if ((R * pitch) & 1) ++pitch;
-    return elem * ((size_t)(ly + 2) * pitch + 4 * (size_t)(lx + ly) + 8);
+    const int pitch = fast2d_pitch(lx, R);
+    const size_t sink = (size_t)(ly + 2) * pitch;
+    const size_t fx = (sink + 64 + pitch + 3) & ~(size_t)3;
+    return elem * (fx + 4 * (size_t)(lx + ly) + 4);
 }
 
 hipError_t launch_pack2d(const PassGeom &g, Store s, int R, bool transposed, const double *const *diag,
@@ -804,10 +832,10 @@ static hipError_t fast_impl(const Fast2dPass &p, const void *in, bool scale_by_p
     A.face = (const S *)p.face;
     A.toff = p.toff;
     A.foff = p.foff;
+    A.otab = p.otab;
+    A.ooff = p.ooff;
     A.in = (const TIN *)in;
     A.out = (TOUT *)out;
-    A.scale_by_piv = scale_by_piv ? 1 : 0;
-    A.coupled = p.coupled ? 1 : 0;
     A.cscale = cscale;
     size_t sm = fast2d_lds_bytes(p.lxmax, p.lymax, R, sizeof(T));
     hipLaunchKernelGGL((k_fast2d<R, T, S, TIN, TOUT, SC, CPL>), dim3(p.g.ntiles), dim3(256), sm, st, A);
@@ -903,7 +931,7 @@ __global__ void __launch_bounds__(256) k_b_fast2d(const BTile *__restrict__ tile
     fast2d_body<R, T, S, TIN, TOUT, SC, CPL>(
         F, P.n0, as_global<const TIN>(bslot(P, in_slot)), as_global<TOUT>(bslot(P, out_slot)),
         (const S *)P.s_inv[pass] + t, (const S *)P.s_ax[pass] + t, (const S *)P.s_ay[pass] + t,
-        as_global<const S>(P.face[pass]) + P.foff[tb.tix],
+        as_global<const int>(P.otab) + P.ooff[tb.tix], as_global<const S>(P.face[pass]) + P.foff[tb.tix],
         cs_from_prob ? P.c : 1.0, smem);
 }
 

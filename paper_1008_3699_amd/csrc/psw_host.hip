@@ -79,7 +79,8 @@ struct PrecState {
     bool fast = false;
     int R = 1, lxmax = 1, lymax = 1;
     FastPassBuf fp[4];
-    DevBuf toff, foff;
+    DevBuf toff, foff; // per tile: start of its packed coefficients / face records
+    DevBuf otab, ooff; // step-offset tables and their per-tile starts
 };
 
 struct psw_problem {
@@ -212,24 +213,31 @@ psw_status fast_setup(psw_problem *P, PrecState &S, hipStream_t st) {
     std::vector<int> lo0, len0, lo1, len1;
     partition(P->n[0], P->p[0], lo0, len0);
     partition(P->n[1], P->p[1], lo1, len1);
-    std::vector<int64_t> toff, foff;
+    Store s = store_of(P->prec);
+    size_t eb = store_bytes(s);
+    std::vector<int64_t> toff, foff, ooff;
+    std::vector<int> otab;
     int64_t t = 0, f = 0;
     for (int s1 = 0; s1 < P->p[1]; ++s1)
         for (int s0 = 0; s0 < P->p[0]; ++s0) {
-            int lx = len0[s0], ly = len1[s1];
-            int L = (ly + R - 1) / R;
+            const int lx = len0[s0], ly = len1[s1];
             toff.push_back(t);
             foff.push_back(f);
-            t += (int64_t)(lx + L - 1 + kFast2dDepth) * 64 * R;
+            ooff.push_back((int64_t)otab.size());
+            t += fast2d_tile_elems(lx, ly, R, eb);
             f += 4 * (int64_t)(lx + ly) + 3;
             f = (f + 7) & ~(int64_t)7;
+            const size_t o = otab.size();
+            otab.resize(o + fast2d_tab_len(lx, ly, R));
+            fast2d_fill_tab(lx, ly, R, eb, otab.data() + o);
         }
-    Store s = store_of(P->prec);
-    size_t eb = store_bytes(s);
-    if (!S.toff.ensure(sizeof(int64_t) * toff.size()) || !S.foff.ensure(sizeof(int64_t) * foff.size()))
+    if (!S.toff.ensure(sizeof(int64_t) * toff.size()) || !S.foff.ensure(sizeof(int64_t) * foff.size()) ||
+        !S.ooff.ensure(sizeof(int64_t) * ooff.size()) || !S.otab.ensure(sizeof(int) * otab.size()))
         return PSW_ENOMEM;
     HIPCHK(hipMemcpy(S.toff.p, toff.data(), sizeof(int64_t) * toff.size(), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(S.foff.p, foff.data(), sizeof(int64_t) * foff.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(S.ooff.p, ooff.data(), sizeof(int64_t) * ooff.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(S.otab.p, otab.data(), sizeof(int) * otab.size(), hipMemcpyHostToDevice));
     const double *d[7];
     diag64(P, d);
     for (int w = 0; w < 4; ++w) {
@@ -312,6 +320,8 @@ psw_status half(psw_problem *P, psw_precond kind, int which, const void *in, boo
         fp.face = S.fp[which].face.p;
         fp.toff = S.toff.as<int64_t>();
         fp.foff = S.foff.as<int64_t>();
+        fp.otab = S.otab.as<int>();
+        fp.ooff = S.ooff.as<int64_t>();
         if (which <= 1) {
             HIPCHK(launch_fast2d(fp, s, in, in_f64, scale_by_piv, out, out_f64, cscale, st));
         } else {
@@ -620,6 +630,8 @@ psw_status batch_build(BatchRun &B, int count, psw_problem *const *probs, const 
         }
         b.toff = S.toff.as<int64_t>();
         b.foff = S.foff.as<int64_t>();
+        b.otab = S.otab.as<int>();
+        b.ooff = S.ooff.as<int64_t>();
         for (int k = 0; k < 5; ++k) {
             b.diagS[k] = S.diag[k].p;
             b.diag64[k] = P->diag[k].as<double>();
