@@ -46,8 +46,9 @@ hipError_t launch_pack2d(const PassGeom &g, Store s, int R, bool transposed, con
 // step-offset table of a tile (host); tab must hold fast2d_tab_len(lx, ly, R) entries
 void fast2d_fill_tab(int lx, int ly, int R, size_t elem, int *tab);
 
+// add (optional, FP64, requires out_f64): out = 0.5 * (cscale * result) + cadd * add
 hipError_t launch_fast2d(const Fast2dPass &p, Store s, const void *in, bool in_f64, bool scale_by_piv, void *out,
-                         bool out_f64, double cscale, hipStream_t st);
+                         bool out_f64, double cscale, const double *add, double cadd, hipStream_t st);
 
 hipError_t launch_end_faces2d_fast(const PassGeom &g, Store s, const void *const *diag, const void *piv,
                                    const void *in, bool in_f64, bool scale_by_piv, void *out, bool out_f64,
@@ -102,7 +103,7 @@ struct BChunk {
 // one pass of the preconditioner over all tiles in `tiles` (same R)
 hipError_t launch_b_fast2d(const BTile *tiles, int ntiles, const BProb *probs, const int sig[2], int pass, int R,
                            Store s, int in_slot, bool in_f64, int out_slot, bool out_f64, bool scale_by_piv,
-                           bool coupled, bool cs_from_prob, size_t lds, hipStream_t st);
+                           bool coupled, bool cs_from_prob, int add_slot, size_t lds, hipStream_t st);
 // end faces and cross points of an end-coupled pass over all tiles
 hipError_t launch_b_end2d(const BTile *tiles, int ntiles, const BProb *probs, const int sig[2], Store s, int in_slot,
                           bool in_f64, int out_slot, bool out_f64, bool scale_by_piv, int facemax, hipStream_t st);

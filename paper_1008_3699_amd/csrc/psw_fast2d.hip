@@ -238,6 +238,8 @@ template <typename S, typename TIN, typename TOUT> struct Fast2dArgs {
     const TIN *in;
     TOUT *out;
     double cscale;
+    const double *add; // optional: out = 0.5 * (cscale * result) + cadd * add
+    double cadd;
 };
 
 // value of lane j-1 in lane j and 0 in lane 0: one DPP wave shift per 32 bits
@@ -301,7 +303,8 @@ template <int R, typename T, typename S, typename TIN, typename TOUT, bool SC, b
 __device__ __forceinline__ void fast2d_body(const Frame2 &F, int n0, const GP<TIN> *__restrict__ in,
                                             GP<TOUT> *__restrict__ out, const S *s_inv_t, const S *s_ax_t,
                                             const S *s_ay_t, const GP<int> *__restrict__ tab, const GP<S> *fsrc,
-                                            double cscale, unsigned char *smem) {
+                                            double cscale, const GP<double> *__restrict__ add, double cadd,
+                                            unsigned char *smem) {
     using V = typename Pack<S, R>::V;
     constexpr int RING = SC ? 16 : 8;
     constexpr int KB = kFast2dBlk;
@@ -366,6 +369,25 @@ __device__ __forceinline__ void fast2d_body(const Frame2 &F, int n0, const GP<TI
             const int e = ht + NH * u;
             const int y = e / KB, c = e - y * KB;
             v[u] = (y < ly && c < nc) ? vt[(y + 1) * pitch + c0 + c + 1] : T(0);
+        }
+        if (add) {
+            // the symmetric combination: 0.5 * (cscale * result) + cadd * add, in FP64;
+            // all addends are loaded before the first store
+            double av[NB];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                const int e = ht + NH * u;
+                const int y = e / KB, c = e - y * KB;
+                av[u] = (y < ly && c < nc) ? add[lin2(n0, gx_of(F, c0 + c), gy_of(F, y))] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                const int e = ht + NH * u;
+                const int y = e / KB, c = e - y * KB;
+                if (y < ly && c < nc)
+                    out[lin2(n0, gx_of(F, c0 + c), gy_of(F, y))] = (TOUT)(0.5 * (double)(cs * v[u]) + cadd * av[u]);
+            }
+            return;
         }
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
@@ -597,7 +619,8 @@ __global__ void __launch_bounds__(256) k_fast2d(Fast2dArgs<S, TIN, TOUT> A) {
     const int64_t t = A.toff[blockIdx.x];
     fast2d_body<R, T, S, TIN, TOUT, SC, CPL>(F, A.g.n[0], (const GP<TIN> *)A.in, (GP<TOUT> *)A.out, A.s_inv + t,
                                               A.s_ax + t, A.s_ay + t, (const GP<int> *)(A.otab + A.ooff[blockIdx.x]),
-                                              (const GP<S> *)(A.face + A.foff[blockIdx.x]), A.cscale, smem);
+                                              (const GP<S> *)(A.face + A.foff[blockIdx.x]), A.cscale,
+                                              (const GP<double> *)A.add, A.cadd, smem);
 }
 
 // ------------------------------------------------------------------ end-face chains (2D), prefetched
@@ -674,18 +697,57 @@ __device__ void end_face2d_body(const EndFrame2 &E, int a, int n0, const GP<S> *
         bQ[k] = rq * iQ;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        // x_P = e_P + m1 x_Q, x_Q = e_Q + m2 x_P  =>  x_P = (e_P + m1 e_Q) / (1 - m1 m2)
-        T xp = T(0), xq = T(0);
-        for (int k = 0; k < nb; ++k) {
-            const T ep = bP[k] + cP[k] * xp, eq = bQ[k] + cQ[k] * xq;
-            const T m1d = mPQ[k], m2 = mQP[k];
-            const T idet = T(1) + m1d * m2; // 1/(1 - m1 m2) = 1 + m1 m2 / (1 - m1 m2)
-            xp = ep * idet + m1d * eq;
-            xq = eq + m2 * xp;
-            bP[k] = xp;
-            bQ[k] = xq;
+    // The chain X_k = (x_P, x_Q)_k = A_k X_{k-1} + u_k, X_{-1} = 0, with
+    //   e_P = b_P + c_P x_P',  e_Q = b_Q + c_Q x_Q',
+    //   x_P = e_P idet + m1d e_Q,  x_Q = e_Q + m2 x_P   (idet = 1 + m1d m2).
+    // Each of the 64 threads takes a contiguous chunk of ch entries, composes
+    // its chunk's affine maps, a scan over the chunks gives every chunk its
+    // starting state, and the chunk is then stepped through in order.
+    const int nt = blockDim.x, t = threadIdx.x;
+    const int ch = (nb + nt - 1) / nt;
+    const int k0 = min(nb, t * ch), k1 = min(nb, k0 + ch);
+    T c00 = T(1), c01 = T(0), c10 = T(0), c11 = T(1), c0 = T(0), c1 = T(0); // identity map
+    for (int k = k0; k < k1; ++k) {
+        const T m1d = mPQ[k], m2 = mQP[k];
+        const T idet = T(1) + m1d * m2;
+        const T a00 = idet * cP[k], a01 = m1d * cQ[k], a10 = m2 * a00, a11 = idet * cQ[k];
+        const T u0 = idet * bP[k] + m1d * bQ[k], u1 = bQ[k] + m2 * u0;
+        // new = entry o chunk-so-far
+        const T n00 = a00 * c00 + a01 * c10, n01 = a00 * c01 + a01 * c11;
+        const T n10 = a10 * c00 + a11 * c10, n11 = a10 * c01 + a11 * c11;
+        const T n0 = a00 * c0 + a01 * c1 + u0, n1 = a10 * c0 + a11 * c1 + u1;
+        c00 = n00; c01 = n01; c10 = n10; c11 = n11; c0 = n0; c1 = n1;
+    }
+    // inclusive scan of the chunk maps (Hillis-Steele over the 64 threads)
+    T *sc = bQ + nb; // 6 * nt values
+    for (int off = 1; off < nt; off <<= 1) {
+        sc[6 * t + 0] = c00; sc[6 * t + 1] = c01; sc[6 * t + 2] = c10;
+        sc[6 * t + 3] = c11; sc[6 * t + 4] = c0; sc[6 * t + 5] = c1;
+        __syncthreads();
+        if (t >= off) {
+            const T *e = sc + 6 * (t - off);
+            const T e00 = e[0], e01 = e[1], e10 = e[2], e11 = e[3], e0 = e[4], e1 = e[5];
+            const T n00 = c00 * e00 + c01 * e10, n01 = c00 * e01 + c01 * e11;
+            const T n10 = c10 * e00 + c11 * e10, n11 = c10 * e01 + c11 * e11;
+            const T n0 = c00 * e0 + c01 * e1 + c0, n1 = c10 * e0 + c11 * e1 + c1;
+            c00 = n00; c01 = n01; c10 = n10; c11 = n11; c0 = n0; c1 = n1;
         }
+        __syncthreads();
+    }
+    // state before this chunk = the previous thread's inclusive result applied to X_{-1} = 0
+    sc[2 * t] = c0;
+    sc[2 * t + 1] = c1;
+    __syncthreads();
+    T xp = t > 0 ? sc[2 * (t - 1)] : T(0), xq = t > 0 ? sc[2 * (t - 1) + 1] : T(0);
+    __syncthreads();
+    for (int k = k0; k < k1; ++k) {
+        const T ep = bP[k] + cP[k] * xp, eq = bQ[k] + cQ[k] * xq;
+        const T m1d = mPQ[k], m2 = mQP[k];
+        const T idet = T(1) + m1d * m2;
+        xp = ep * idet + m1d * eq;
+        xq = eq + m2 * xp;
+        bP[k] = xp;
+        bQ[k] = xq;
     }
     __syncthreads();
     for (int k = threadIdx.x; k < nb; k += blockDim.x) {
@@ -823,7 +885,7 @@ hipError_t launch_pack2d(const PassGeom &g, Store s, int R, bool transposed, con
 
 template <int R, typename T, typename S, typename TIN, typename TOUT, bool SC, bool CPL>
 static hipError_t fast_impl(const Fast2dPass &p, const void *in, bool scale_by_piv, void *out, double cscale,
-                            hipStream_t st) {
+                            const double *add, double cadd, hipStream_t st) {
     Fast2dArgs<S, TIN, TOUT> A{};
     A.g = p.g;
     A.s_inv = (const S *)p.s_inv;
@@ -837,43 +899,50 @@ static hipError_t fast_impl(const Fast2dPass &p, const void *in, bool scale_by_p
     A.in = (const TIN *)in;
     A.out = (TOUT *)out;
     A.cscale = cscale;
+    A.add = add;
+    A.cadd = cadd;
     size_t sm = fast2d_lds_bytes(p.lxmax, p.lymax, R, sizeof(T));
     hipLaunchKernelGGL((k_fast2d<R, T, S, TIN, TOUT, SC, CPL>), dim3(p.g.ntiles), dim3(256), sm, st, A);
     return hipGetLastError();
 }
 
 template <int R, typename T, typename S, typename TIN, typename TOUT>
-static hipError_t fast_flags(const Fast2dPass &p, const void *in, bool scale, void *out, double cs, hipStream_t st) {
+static hipError_t fast_flags(const Fast2dPass &p, const void *in, bool scale, void *out, double cs, const double *add,
+                             double cadd, hipStream_t st) {
     if (scale) {
-        if (p.coupled) return fast_impl<R, T, S, TIN, TOUT, true, true>(p, in, scale, out, cs, st);
-        return fast_impl<R, T, S, TIN, TOUT, true, false>(p, in, scale, out, cs, st);
+        if (p.coupled) return fast_impl<R, T, S, TIN, TOUT, true, true>(p, in, scale, out, cs, add, cadd, st);
+        return fast_impl<R, T, S, TIN, TOUT, true, false>(p, in, scale, out, cs, add, cadd, st);
     }
-    if (p.coupled) return fast_impl<R, T, S, TIN, TOUT, false, true>(p, in, scale, out, cs, st);
-    return fast_impl<R, T, S, TIN, TOUT, false, false>(p, in, scale, out, cs, st);
+    if (p.coupled) return fast_impl<R, T, S, TIN, TOUT, false, true>(p, in, scale, out, cs, add, cadd, st);
+    return fast_impl<R, T, S, TIN, TOUT, false, false>(p, in, scale, out, cs, add, cadd, st);
 }
 
 template <typename T, typename S, typename TIN, typename TOUT>
-static hipError_t fast_r(const Fast2dPass &p, const void *in, bool scale, void *out, double cs, hipStream_t st) {
-    if (p.R == 1) return fast_flags<1, T, S, TIN, TOUT>(p, in, scale, out, cs, st);
-    return fast_flags<2, T, S, TIN, TOUT>(p, in, scale, out, cs, st);
+static hipError_t fast_r(const Fast2dPass &p, const void *in, bool scale, void *out, double cs, const double *add,
+                         double cadd, hipStream_t st) {
+    if (p.R == 1) return fast_flags<1, T, S, TIN, TOUT>(p, in, scale, out, cs, add, cadd, st);
+    return fast_flags<2, T, S, TIN, TOUT>(p, in, scale, out, cs, add, cadd, st);
 }
 
 hipError_t launch_fast2d(const Fast2dPass &p, Store s, const void *in, bool in_f64, bool scale_by_piv, void *out,
-                         bool out_f64, double cscale, hipStream_t st) {
+                         bool out_f64, double cscale, const double *add, double cadd, hipStream_t st) {
+    if (add && !out_f64) return hipErrorInvalidValue;
+#define PSW_F_ARGS p, in, scale_by_piv, out, cscale, add, cadd, st
     if (s == Store::F64) {
         if (!in_f64 || !out_f64) return hipErrorInvalidValue;
-        return fast_r<double, double, double, double>(p, in, scale_by_piv, out, cscale, st);
+        return fast_r<double, double, double, double>(PSW_F_ARGS);
     }
     if (s == Store::F32) {
-        if (in_f64 && !out_f64) return fast_r<float, float, double, float>(p, in, scale_by_piv, out, cscale, st);
-        if (!in_f64 && out_f64) return fast_r<float, float, float, double>(p, in, scale_by_piv, out, cscale, st);
-        if (in_f64 && out_f64) return fast_r<float, float, double, double>(p, in, scale_by_piv, out, cscale, st);
-        return fast_r<float, float, float, float>(p, in, scale_by_piv, out, cscale, st);
+        if (in_f64 && !out_f64) return fast_r<float, float, double, float>(PSW_F_ARGS);
+        if (!in_f64 && out_f64) return fast_r<float, float, float, double>(PSW_F_ARGS);
+        if (in_f64 && out_f64) return fast_r<float, float, double, double>(PSW_F_ARGS);
+        return fast_r<float, float, float, float>(PSW_F_ARGS);
     }
-    if (in_f64 && !out_f64) return fast_r<float, uint16_t, double, float>(p, in, scale_by_piv, out, cscale, st);
-    if (!in_f64 && out_f64) return fast_r<float, uint16_t, float, double>(p, in, scale_by_piv, out, cscale, st);
-    if (in_f64 && out_f64) return fast_r<float, uint16_t, double, double>(p, in, scale_by_piv, out, cscale, st);
-    return fast_r<float, uint16_t, float, float>(p, in, scale_by_piv, out, cscale, st);
+    if (in_f64 && !out_f64) return fast_r<float, uint16_t, double, float>(PSW_F_ARGS);
+    if (!in_f64 && out_f64) return fast_r<float, uint16_t, float, double>(PSW_F_ARGS);
+    if (in_f64 && out_f64) return fast_r<float, uint16_t, double, double>(PSW_F_ARGS);
+    return fast_r<float, uint16_t, float, float>(PSW_F_ARGS);
+#undef PSW_F_ARGS
 }
 
 template <typename T, typename S, typename TIN, typename TOUT>
@@ -886,7 +955,7 @@ static hipError_t endf_impl(const PassGeom &g, const void *const *diag, const vo
     A.in = (const TIN *)in;
     A.scale_by_piv = scale ? 1 : 0;
     A.out = (TOUT *)out;
-    size_t sm = sizeof(T) * 6 * (size_t)facemax;
+    size_t sm = sizeof(T) * 6 * ((size_t)facemax + 64); // chain data + scan area of 64 threads
     hipLaunchKernelGGL((k_end_faces2d_fast<T, S, TIN, TOUT>), dim3(g.ntiles * 2), dim3(64), sm, st, A);
     hipLaunchKernelGGL((k_end_corners2d<T, S, TIN, TOUT>), dim3((g.ntiles + 63) / 64), dim3(64), 0, st, A);
     return hipGetLastError();
@@ -920,7 +989,7 @@ __device__ __forceinline__ void *bslot(const BProb &P, int k) { return P.vec[k];
 
 template <int R, typename T, typename S, typename TIN, typename TOUT, bool SC, bool CPL>
 __global__ void __launch_bounds__(256) k_b_fast2d(const BTile *__restrict__ tiles, const BProb *__restrict__ probs, int sig0, int sig1,
-                                                  int pass, int in_slot, int out_slot, int cs_from_prob) {
+                                                  int pass, int in_slot, int out_slot, int cs_from_prob, int add_slot) {
     extern __shared__ __align__(16) unsigned char smem[];
     const BTile tb = tiles[blockIdx.x];
     const BProb &P = probs[tb.prob];
@@ -932,7 +1001,8 @@ __global__ void __launch_bounds__(256) k_b_fast2d(const BTile *__restrict__ tile
         F, P.n0, as_global<const TIN>(bslot(P, in_slot)), as_global<TOUT>(bslot(P, out_slot)),
         (const S *)P.s_inv[pass] + t, (const S *)P.s_ax[pass] + t, (const S *)P.s_ay[pass] + t,
         as_global<const int>(P.otab) + P.ooff[tb.tix], as_global<const S>(P.face[pass]) + P.foff[tb.tix],
-        cs_from_prob ? P.c : 1.0, smem);
+        cs_from_prob ? P.c : 1.0, add_slot >= 0 ? as_global<const double>(bslot(P, add_slot)) : nullptr, 0.5 * P.c,
+        smem);
 }
 
 template <typename T, typename S, typename TIN, typename TOUT>
@@ -971,33 +1041,35 @@ __global__ void k_b_end_corners2d(const BTile *__restrict__ tiles, int ntiles, c
 
 template <int R, typename T, typename S, typename TIN, typename TOUT>
 static hipError_t b_fast_flags(const BTile *tiles, int ntiles, const BProb *probs, const int sig[2], int pass,
-                               int in_slot, int out_slot, bool scale, bool coupled, bool csp, size_t lds,
+                               int in_slot, int out_slot, bool scale, bool coupled, bool csp, int add_slot, size_t lds,
                                hipStream_t st) {
     dim3 g(ntiles), b(256);
     const int c = csp ? 1 : 0;
     if (scale && coupled)
-        hipLaunchKernelGGL((k_b_fast2d<R, T, S, TIN, TOUT, true, true>), g, b, lds, st, tiles, probs, sig[0], sig[1], pass, in_slot, out_slot, c);
+        hipLaunchKernelGGL((k_b_fast2d<R, T, S, TIN, TOUT, true, true>), g, b, lds, st, tiles, probs, sig[0], sig[1], pass, in_slot, out_slot, c, add_slot);
     else if (scale)
-        hipLaunchKernelGGL((k_b_fast2d<R, T, S, TIN, TOUT, true, false>), g, b, lds, st, tiles, probs, sig[0], sig[1], pass, in_slot, out_slot, c);
+        hipLaunchKernelGGL((k_b_fast2d<R, T, S, TIN, TOUT, true, false>), g, b, lds, st, tiles, probs, sig[0], sig[1], pass, in_slot, out_slot, c, add_slot);
     else if (coupled)
-        hipLaunchKernelGGL((k_b_fast2d<R, T, S, TIN, TOUT, false, true>), g, b, lds, st, tiles, probs, sig[0], sig[1], pass, in_slot, out_slot, c);
+        hipLaunchKernelGGL((k_b_fast2d<R, T, S, TIN, TOUT, false, true>), g, b, lds, st, tiles, probs, sig[0], sig[1], pass, in_slot, out_slot, c, add_slot);
     else
-        hipLaunchKernelGGL((k_b_fast2d<R, T, S, TIN, TOUT, false, false>), g, b, lds, st, tiles, probs, sig[0], sig[1], pass, in_slot, out_slot, c);
+        hipLaunchKernelGGL((k_b_fast2d<R, T, S, TIN, TOUT, false, false>), g, b, lds, st, tiles, probs, sig[0], sig[1], pass, in_slot, out_slot, c, add_slot);
     return hipGetLastError();
 }
 
 template <typename T, typename S, typename TIN, typename TOUT>
 static hipError_t b_fast_r(const BTile *tiles, int ntiles, const BProb *probs, const int sig[2], int pass, int R,
-                           int in_slot, int out_slot, bool scale, bool coupled, bool csp, size_t lds, hipStream_t st) {
-    if (R == 1) return b_fast_flags<1, T, S, TIN, TOUT>(tiles, ntiles, probs, sig, pass, in_slot, out_slot, scale, coupled, csp, lds, st);
-    return b_fast_flags<2, T, S, TIN, TOUT>(tiles, ntiles, probs, sig, pass, in_slot, out_slot, scale, coupled, csp, lds, st);
+                           int in_slot, int out_slot, bool scale, bool coupled, bool csp, int add_slot, size_t lds,
+                           hipStream_t st) {
+    if (R == 1) return b_fast_flags<1, T, S, TIN, TOUT>(tiles, ntiles, probs, sig, pass, in_slot, out_slot, scale, coupled, csp, add_slot, lds, st);
+    return b_fast_flags<2, T, S, TIN, TOUT>(tiles, ntiles, probs, sig, pass, in_slot, out_slot, scale, coupled, csp, add_slot, lds, st);
 }
 
 hipError_t launch_b_fast2d(const BTile *tiles, int ntiles, const BProb *probs, const int sig[2], int pass, int R,
                            Store s, int in_slot, bool in_f64, int out_slot, bool out_f64, bool scale, bool coupled,
-                           bool csp, size_t lds, hipStream_t st) {
+                           bool csp, int add_slot, size_t lds, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
-#define PSW_B_ARGS tiles, ntiles, probs, sig, pass, R, in_slot, out_slot, scale, coupled, csp, lds, st
+    if (add_slot >= 0 && !out_f64) return hipErrorInvalidValue;
+#define PSW_B_ARGS tiles, ntiles, probs, sig, pass, R, in_slot, out_slot, scale, coupled, csp, add_slot, lds, st
     if (s == Store::F64) return b_fast_r<double, double, double, double>(PSW_B_ARGS);
     if (s == Store::F32) {
         if (in_f64 && !out_f64) return b_fast_r<float, float, double, float>(PSW_B_ARGS);
@@ -1015,7 +1087,7 @@ hipError_t launch_b_fast2d(const BTile *tiles, int ntiles, const BProb *probs, c
 template <typename T, typename S, typename TIN, typename TOUT>
 static hipError_t b_end_impl(const BTile *tiles, int ntiles, const BProb *probs, const int sig[2], int in_slot,
                              int out_slot, bool scale, int facemax, hipStream_t st) {
-    size_t sm = sizeof(T) * 6 * (size_t)facemax;
+    size_t sm = sizeof(T) * 6 * ((size_t)facemax + 64); // chain data + scan area of 64 threads
     hipLaunchKernelGGL((k_b_end_faces2d<T, S, TIN, TOUT>), dim3(ntiles * 2), dim3(64), sm, st, tiles, probs, sig[0],
                        sig[1], in_slot, out_slot, scale ? 1 : 0);
     hipLaunchKernelGGL((k_b_end_corners2d<T, S, TIN, TOUT>), dim3((ntiles + 63) / 64), dim3(64), 0, st, tiles, ntiles,

@@ -68,6 +68,43 @@ struct FastPassBuf {
     DevBuf inv, ax, ay, face;
 };
 
+// A second stream and two events: work that does not depend on the main
+// stream's next kernels forks onto it and joins back (also under capture).
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    ~SideStream() {
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+        if (s) (void)hipStreamDestroy(s);
+    }
+    bool ensure() {
+        if (s) return true;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return false;
+        if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) return false;
+        if (hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) return false;
+        return true;
+    }
+};
+
+// pinned host scalars and an event, for reading a device result without draining the stream
+struct HostScalars {
+    double *p = nullptr;
+    hipEvent_t ev = nullptr;
+    ~HostScalars() {
+        if (ev) (void)hipEventDestroy(ev);
+        if (p) (void)hipHostFree(p);
+    }
+    bool ensure() {
+        if (p) return true;
+        if (hipHostMalloc((void **)&p, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+            p = nullptr;
+            return false;
+        }
+        return hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+    }
+};
+
 struct PrecState {
     bool ready = false;
     double omega = 1.0;
@@ -105,6 +142,8 @@ struct psw_problem {
     DevBuf partials, scal;
     DevBuf gm_V, gm_Z, gm_h;
     size_t lds_limit = 65536;
+    SideStream side;
+    HostScalars hs;
 };
 
 namespace {
@@ -298,6 +337,50 @@ psw_status precond_setup(psw_problem *P, psw_precond kind, hipStream_t st) {
 }
 
 // one half-sweep; which: 0 fwd (N1), 1 bwd (N2, scaled by c), 2 (Piv-N2)^-T, 3 (Piv-N1)^-T
+Fast2dPass fast_pass_desc(psw_problem *P, PrecState &S, int which) {
+    int sig[3];
+    pass_sig(P, which, sig);
+    Fast2dPass fp{};
+    fp.g = geom(P, sig);
+    fp.R = S.R;
+    fp.coupled = which <= 1;
+    fp.lxmax = S.lxmax;
+    fp.lymax = S.lymax;
+    fp.s_inv = S.fp[which].inv.p;
+    fp.s_ax = S.fp[which].ax.p;
+    fp.s_ay = S.fp[which].ay.p;
+    fp.face = S.fp[which].face.p;
+    fp.toff = S.toff.as<int64_t>();
+    fp.foff = S.foff.as<int64_t>();
+    fp.otab = S.otab.as<int>();
+    fp.ooff = S.ooff.as<int64_t>();
+    return fp;
+}
+
+// pipelined pass `which` over all tiles (for the end-coupled passes 2, 3: the uncoupled interior only)
+psw_status fast_pass(psw_problem *P, psw_precond kind, int which, const void *in, bool in_f64, bool scale_by_piv,
+                     void *out, bool out_f64, double cscale, const double *add, double cadd, hipStream_t st) {
+    PrecState &S = P->pc[kind];
+    const Fast2dPass fp = fast_pass_desc(P, S, which);
+    HIPCHK(launch_fast2d(fp, store_of(P->prec), in, in_f64, scale_by_piv, out, out_f64, which <= 1 ? cscale : 1.0,
+                         add, cadd, st));
+    return PSW_OK;
+}
+
+// the coupled end faces and cross points of end-coupled pass `which` (2 or 3), after its interior
+psw_status fast_end(psw_problem *P, psw_precond kind, int which, const void *in, bool in_f64, bool scale_by_piv,
+                    void *out, bool out_f64, hipStream_t st) {
+    PrecState &S = P->pc[kind];
+    int sig[3];
+    pass_sig(P, which, sig);
+    const PassGeom g = geom(P, sig);
+    const void *d[7];
+    for (int k = 0; k < 7; ++k) d[k] = S.diag[k].p;
+    HIPCHK(launch_end_faces2d_fast(g, store_of(P->prec), d, S.piv.p, in, in_f64, scale_by_piv, out, out_f64,
+                                   std::max(S.lxmax, S.lymax), st));
+    return PSW_OK;
+}
+
 psw_status half(psw_problem *P, psw_precond kind, int which, const void *in, bool in_f64, bool scale_by_piv,
                 void *out, bool out_f64, double cscale, hipStream_t st) {
     PrecState &S = P->pc[kind];
@@ -308,28 +391,9 @@ psw_status half(psw_problem *P, psw_precond kind, int which, const void *in, boo
     const void *d[7];
     for (int k = 0; k < 7; ++k) d[k] = S.diag[k].p;
     if (S.fast) {
-        Fast2dPass fp{};
-        fp.g = g;
-        fp.R = S.R;
-        fp.coupled = which <= 1;
-        fp.lxmax = S.lxmax;
-        fp.lymax = S.lymax;
-        fp.s_inv = S.fp[which].inv.p;
-        fp.s_ax = S.fp[which].ax.p;
-        fp.s_ay = S.fp[which].ay.p;
-        fp.face = S.fp[which].face.p;
-        fp.toff = S.toff.as<int64_t>();
-        fp.foff = S.foff.as<int64_t>();
-        fp.otab = S.otab.as<int>();
-        fp.ooff = S.ooff.as<int64_t>();
-        if (which <= 1) {
-            HIPCHK(launch_fast2d(fp, s, in, in_f64, scale_by_piv, out, out_f64, cscale, st));
-        } else {
-            HIPCHK(launch_fast2d(fp, s, in, in_f64, scale_by_piv, out, out_f64, 1.0, st));
-            HIPCHK(launch_end_faces2d_fast(g, s, d, S.piv.p, in, in_f64, scale_by_piv, out, out_f64,
-                                           std::max(S.lxmax, S.lymax), st));
-        }
-        return PSW_OK;
+        psw_status ps = fast_pass(P, kind, which, in, in_f64, scale_by_piv, out, out_f64, cscale, nullptr, 0.0, st);
+        if (ps || which <= 1) return ps;
+        return fast_end(P, kind, which, in, in_f64, scale_by_piv, out, out_f64, st);
     }
     if (which <= 1)
         HIPCHK(launch_half_start(g, s, d, S.piv.p, in, in_f64, scale_by_piv, out, out_f64, cscale, st));
@@ -338,7 +402,6 @@ psw_status half(psw_problem *P, psw_precond kind, int which, const void *in, boo
     return PSW_OK;
 }
 
-// z = M^-1 r or (M^-1 + M^-T) r / 2
 psw_status precond_apply(psw_problem *P, psw_precond kind, int symmetric, const double *r, double *z,
                          hipStream_t st) {
     if (kind == PSW_NONE) {
@@ -356,6 +419,23 @@ psw_status precond_apply(psw_problem *P, psw_precond kind, int symmetric, const 
         return half(P, kind, 1, y, f64, true, z, true, S.c, st);
     }
     double *z1 = P->w_z1.as<double>();
+    if (S.fast) {
+        // z = (M^-1 r + M^-T r) / 2.  The transposed pass over r goes first so that its end
+        // faces (a small, latency-bound kernel) run on the side stream beside the forward pass;
+        // the backward pass finishes with the combination.
+        if (!P->side.ensure()) return PSW_EDEVICE;
+        void *y1 = P->w_y.p, *y2 = P->w_y2.p;
+        if ((ps = fast_pass(P, kind, 2, r, true, false, y2, f64, 1.0, nullptr, 0.0, st))) return ps;
+        HIPCHK(hipEventRecord(P->side.fork, st));
+        HIPCHK(hipStreamWaitEvent(P->side.s, P->side.fork, 0));
+        if ((ps = fast_end(P, kind, 2, r, true, false, y2, f64, P->side.s))) return ps;
+        HIPCHK(hipEventRecord(P->side.join, P->side.s));
+        if ((ps = fast_pass(P, kind, 0, r, true, false, y1, f64, 1.0, nullptr, 0.0, st))) return ps;
+        HIPCHK(hipStreamWaitEvent(st, P->side.join, 0));
+        if ((ps = fast_pass(P, kind, 3, y2, f64, true, z1, true, 1.0, nullptr, 0.0, st))) return ps;
+        if ((ps = fast_end(P, kind, 3, y2, f64, true, z1, true, st))) return ps;
+        return fast_pass(P, kind, 1, y1, f64, true, z, true, S.c, z1, 0.5 * S.c, st);
+    }
     if ((ps = half(P, kind, 0, r, true, false, y, f64, 1.0, st))) return ps;
     if ((ps = half(P, kind, 1, y, f64, true, z1, true, S.c, st))) return ps;
     void *y2 = P->w_y2.p;
@@ -443,24 +523,32 @@ psw_status solve_cg(psw_problem *P, psw_precond kind, double rtol, int64_t maxit
         if ((ps = precond_apply(P, kind, 1, r, z, st))) return ps;
         HIPCHK(launch_dot(r, z, N, part, s_rz, st));
         HIPCHK(hipMemcpyAsync(p, z, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+        if (!P->hs.ensure()) return PSW_ENOMEM;
+        double *h = P->hs.p;
         while (it < maxit) {
             HIPCHK(launch_spmv(P->dim, P->n, d, p, q, st));
             HIPCHK(launch_dot(p, q, N, part, s_pq, st));
             HIPCHK(launch_cg_update_xr(x, r, p, q, s_rz, s_pq, N, part, s_rr, st));
             ++it;
-            double h[2];
+            // p.q and r.r of this iteration go to the host behind an event; the rest of the
+            // iteration (which leaves x alone) is queued before the host waits for them, so the
+            // device stays busy while the stopping test runs
             HIPCHK(hipMemcpyAsync(h, s_pq, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
-            if (!(h[0] > 0.0) || !std::isfinite(h[1])) return PSW_EBREAKDOWN;
+            HIPCHK(hipEventRecord(P->hs.ev, st));
+            if ((ps = precond_apply(P, kind, 1, r, z, st))) return ps;
+            HIPCHK(launch_dot(r, z, N, part, s_rz2, st));
+            HIPCHK(launch_cg_update_p(p, z, s_rz2, s_rz, N, st));
+            std::swap(s_rz, s_rz2);
+            HIPCHK(hipEventSynchronize(P->hs.ev));
+            if (!(h[0] > 0.0) || !std::isfinite(h[1])) {
+                (void)hipStreamSynchronize(st);
+                return PSW_EBREAKDOWN;
+            }
             rel = std::sqrt(h[1]) / nf;
             if (rel <= rtol) {
                 conv = true;
                 break;
             }
-            if ((ps = precond_apply(P, kind, 1, r, z, st))) return ps;
-            HIPCHK(launch_dot(r, z, N, part, s_rz2, st));
-            HIPCHK(launch_cg_update_p(p, z, s_rz2, s_rz, N, st));
-            std::swap(s_rz, s_rz2);
         }
     }
     // true residual at exit
@@ -591,6 +679,7 @@ struct BatchRun {
     bool f64 = true;
     int sig[2] = {1, 1};
     int np = 0, nc = 0;
+    SideStream side;
 };
 
 bool batch_eligible(psw_problem *P, psw_precond kind) {
@@ -705,34 +794,53 @@ psw_status batch_build(BatchRun &B, int count, psw_problem *const *probs, const 
 
 // z = (M^-1 + M^-T) r / 2 for every active problem of the batch
 psw_status batch_precond(BatchRun &B, hipStream_t st) {
+    // the order of the single-problem symmetric preconditioner: transposed pass over r (its end
+    // faces on the side stream, beside the forward pass), forward, second transposed pass and
+    // its end faces, then the backward pass, which writes z = 0.5 c (result + z2)
     const BProb *dp = B.dprobs.as<BProb>();
     const int sf[2] = {B.sig[0], B.sig[1]}, sb[2] = {-B.sig[0], -B.sig[1]};
     const bool f64 = B.f64;
+    if (!B.side.ensure()) return PSW_EDEVICE;
     for (int g = 0; g < 2; ++g) {
         const int nt = (int)B.tiles[g].size();
         if (!nt) continue;
-        const BTile *t = B.dtiles[g].as<BTile>();
-        HIPCHK(launch_b_fast2d(t, nt, dp, sf, 0, g + 1, B.store, kSlotR, true, kSlotY1, f64, false, true, false, B.lds[g], st));
-        HIPCHK(launch_b_fast2d(t, nt, dp, sf, 2, g + 1, B.store, kSlotR, true, kSlotY2, f64, false, false, false, B.lds[g], st));
+        HIPCHK(launch_b_fast2d(B.dtiles[g].as<BTile>(), nt, dp, sf, 2, g + 1, B.store, kSlotR, true, kSlotY2, f64, false,
+                               false, false, -1, B.lds[g], st));
+    }
+    HIPCHK(hipEventRecord(B.side.fork, st));
+    HIPCHK(hipStreamWaitEvent(B.side.s, B.side.fork, 0));
+    for (int g = 0; g < 2; ++g) {
+        const int nt = (int)B.tiles[g].size();
+        if (!nt) continue;
+        HIPCHK(launch_b_end2d(B.dtiles[g].as<BTile>(), nt, dp, sf, B.store, kSlotR, true, kSlotY2, f64, false,
+                              B.facemax, B.side.s));
+    }
+    HIPCHK(hipEventRecord(B.side.join, B.side.s));
+    for (int g = 0; g < 2; ++g) {
+        const int nt = (int)B.tiles[g].size();
+        if (!nt) continue;
+        HIPCHK(launch_b_fast2d(B.dtiles[g].as<BTile>(), nt, dp, sf, 0, g + 1, B.store, kSlotR, true, kSlotY1, f64, false,
+                               true, false, -1, B.lds[g], st));
+    }
+    HIPCHK(hipStreamWaitEvent(st, B.side.join, 0));
+    for (int g = 0; g < 2; ++g) {
+        const int nt = (int)B.tiles[g].size();
+        if (!nt) continue;
+        HIPCHK(launch_b_fast2d(B.dtiles[g].as<BTile>(), nt, dp, sb, 3, g + 1, B.store, kSlotY2, f64, kSlotZ1, true, true,
+                               false, false, -1, B.lds[g], st));
     }
     for (int g = 0; g < 2; ++g) {
         const int nt = (int)B.tiles[g].size();
         if (!nt) continue;
-        HIPCHK(launch_b_end2d(B.dtiles[g].as<BTile>(), nt, dp, sf, B.store, kSlotR, true, kSlotY2, f64, false, B.facemax, st));
+        HIPCHK(launch_b_end2d(B.dtiles[g].as<BTile>(), nt, dp, sb, B.store, kSlotY2, f64, kSlotZ1, true, true, B.facemax,
+                              st));
     }
     for (int g = 0; g < 2; ++g) {
         const int nt = (int)B.tiles[g].size();
         if (!nt) continue;
-        const BTile *t = B.dtiles[g].as<BTile>();
-        HIPCHK(launch_b_fast2d(t, nt, dp, sb, 1, g + 1, B.store, kSlotY1, f64, kSlotZ1, true, true, true, true, B.lds[g], st));
-        HIPCHK(launch_b_fast2d(t, nt, dp, sb, 3, g + 1, B.store, kSlotY2, f64, kSlotY1, f64, true, false, false, B.lds[g], st));
+        HIPCHK(launch_b_fast2d(B.dtiles[g].as<BTile>(), nt, dp, sb, 1, g + 1, B.store, kSlotY1, f64, kSlotZ, true, true,
+                               true, true, kSlotZ1, B.lds[g], st));
     }
-    for (int g = 0; g < 2; ++g) {
-        const int nt = (int)B.tiles[g].size();
-        if (!nt) continue;
-        HIPCHK(launch_b_end2d(B.dtiles[g].as<BTile>(), nt, dp, sb, B.store, kSlotY2, f64, kSlotY1, f64, true, B.facemax, st));
-    }
-    HIPCHK(launch_b_combine(B.dchunks.as<BChunk>(), B.nc, dp, f64, st));
     return PSW_OK;
 }
 
