@@ -286,19 +286,121 @@ __host__ __device__ __forceinline__ int fast2d_pitch(int lx, int R) {
     return p;
 }
 
+// The two coupled start faces of a start-coupled pass, each a chain of 2x2
+// blocks: the y face pairs P = (x, 0) with Q = (x, -1) along x, the x face
+// pairs P = (0, y) with Q = (-1, y) along y (eq. 2d:sor2b2; the cross point
+// (0,0) with its three partners is the 4x4 block of eq. 2d:sor4b4 and starts
+// both chains).  A face chain involves no other point of the tile, so one
+// wave solves it before the sweep: every element is the affine map
+//   bq = rq + a_qu vQ',  vP = idt (rhs + a_own vP' + a_cross bq),  vQ = bq + a_qp vP
+// of the previous element's (vP', vQ'); each lane composes the maps of a
+// contiguous chunk, a shuffle scan over the lanes gives each chunk its
+// starting state, and the chunk is then stepped through in order.  vP of
+// element i is written to fix[i].
+template <typename T> struct Aff2 {
+    T a00, a01, a10, a11, u0, u1;
+};
+
+// l after e
+template <typename T> __device__ __forceinline__ Aff2<T> aff_compose(const Aff2<T> &l, const Aff2<T> &e) {
+    Aff2<T> n;
+    n.a00 = l.a00 * e.a00 + l.a01 * e.a10;
+    n.a01 = l.a00 * e.a01 + l.a01 * e.a11;
+    n.a10 = l.a10 * e.a00 + l.a11 * e.a10;
+    n.a11 = l.a10 * e.a01 + l.a11 * e.a11;
+    n.u0 = l.a00 * e.u0 + l.a01 * e.u1 + l.u0;
+    n.u1 = l.a10 * e.u0 + l.a11 * e.u1 + l.u1;
+    return n;
+}
+
+__device__ __forceinline__ float shfl_up1(float v, int d) { return __shfl_up(v, d); }
+__device__ __forceinline__ double shfl_up1(double v, int d) { return __shfl_up(v, d); }
+
+template <typename T> __device__ __forceinline__ Aff2<T> aff_shfl_up(const Aff2<T> &a, int d) {
+    Aff2<T> r;
+    r.a00 = shfl_up1(a.a00, d);
+    r.a01 = shfl_up1(a.a01, d);
+    r.a10 = shfl_up1(a.a10, d);
+    r.a11 = shfl_up1(a.a11, d);
+    r.u0 = shfl_up1(a.u0, d);
+    r.u1 = shfl_up1(a.u1, d);
+    return r;
+}
+
+// Data of chain element i: rhs of P, coupling along the chain, coupling to the
+// partner, and the partner record (rq = 1/Piv_Q r_Q or r_Q, a_qp, a_qu, idt).
+template <typename T> struct ChainEl {
+    T rhs, a_own, a_cross, rq, aqp, aqu, idt;
+};
+
+template <typename T, typename Get>
+__device__ void face_chain(int n, T vp0, T vq0, Get get, T *fix, int lane) {
+    constexpr int kKeep = 4; // elements per lane held in registers between the two passes
+    const int ch = (n + 63) / 64;
+    const int k0 = min(n, lane * ch), k1 = min(n, k0 + ch);
+    ChainEl<T> keep[kKeep];
+#pragma unroll
+    for (int q = 0; q < kKeep; ++q)
+        if (k0 + q < k1) keep[q] = get(k0 + q);
+    Aff2<T> m{T(1), T(0), T(0), T(1), T(0), T(0)};
+    for (int k = k0; k < k1; ++k) {
+        ChainEl<T> e;
+        if (k - k0 < kKeep) {
+#pragma unroll
+            for (int q = 0; q < kKeep; ++q)
+                if (q == k - k0) e = keep[q];
+        } else {
+            e = get(k);
+        }
+        Aff2<T> a;
+        a.a00 = e.idt * e.a_own;
+        a.a01 = e.idt * e.a_cross * e.aqu;
+        a.u0 = e.idt * (e.rhs + e.a_cross * e.rq);
+        a.a10 = e.aqp * a.a00;
+        a.a11 = e.aqu + e.aqp * a.a01;
+        a.u1 = e.rq + e.aqp * a.u0;
+        m = aff_compose(a, m);
+    }
+    for (int d = 1; d < 64; d <<= 1) {
+        const Aff2<T> o = aff_shfl_up(m, d);
+        if (lane >= d) m = aff_compose(m, o);
+    }
+    const Aff2<T> prev = aff_shfl_up(m, 1);
+    T vp = vp0, vq = vq0;
+    if (lane > 0) {
+        vp = prev.a00 * vp0 + prev.a01 * vq0 + prev.u0;
+        vq = prev.a10 * vp0 + prev.a11 * vq0 + prev.u1;
+    }
+    for (int k = k0; k < k1; ++k) {
+        ChainEl<T> e;
+        if (k - k0 < kKeep) {
+#pragma unroll
+            for (int q = 0; q < kKeep; ++q)
+                if (q == k - k0) e = keep[q];
+        } else {
+            e = get(k);
+        }
+        const T bq = e.rq + e.aqu * vq;
+        const T np = e.idt * (e.rhs + e.a_own * vp + e.a_cross * bq);
+        vq = bq + e.aqp * np;
+        vp = np;
+        fix[k] = np;
+    }
+}
+
 // One tile of a pass.  The tile is swept in local orientation (towards +x,
-// +y); the LDS copy of the input tile uses local coordinates too, with the
-// partners across the coupled start faces in column / row -1.
+// +y); the LDS copy of the input tile uses local coordinates too.
 //   wave 0     : the recurrence, kFast2dBlk anti-diagonal steps per barrier
 //                interval; lane j owns rows R*j .. R*j+R-1 and handles column
 //                x = s - j at step s; the row above arrives by a DPP shift.
 //   waves 1..3 : stage column block i + 2 and write back column block i - lag
-//                (all of whose points are final) during interval i.
+//                (all of whose points are final) during interval i; before
+//                the sweep, waves 1 and 2 solve the coupled start faces.
 // Coefficients stream from the compact sweep-major packing through a
-// register ring of RING steps; the right-hand sides and face records come
-// from LDS kPf steps ahead.  Lanes without a point at a step compute with
-// another slot's coefficients and finite LDS values; their results reach
-// no lane that has a point and are written to a per-lane sink.
+// register ring of RING steps; the right-hand sides come from LDS kPf steps
+// ahead.  Lanes without a point at a step compute with another slot's
+// coefficients and finite LDS values; their results reach no lane that has a
+// point and are written to a per-lane sink.
 template <int R, typename T, typename S, typename TIN, typename TOUT, bool SC, bool CPL>
 __device__ __forceinline__ void fast2d_body(const Frame2 &F, int n0, const GP<TIN> *__restrict__ in,
                                             GP<TOUT> *__restrict__ out, const S *s_inv_t, const S *s_ax_t,
@@ -317,28 +419,22 @@ __device__ __forceinline__ void fast2d_body(const Frame2 &F, int n0, const GP<TI
     const int lag = (L + KB - 2) / KB + 1; // block c is final after interval c + lag - 1
     const int pitch = fast2d_pitch(lx, R);
     T *vt = reinterpret_cast<T *>(smem);
-    const int sink = (ly + 2) * pitch;             // 64 + (R - 1) * pitch sink slots
-    T *fx = vt + ((sink + 64 + pitch + 3) & ~3);   // x-face partner records (4 per row)
-    T *fy = fx + 4 * ly;                           // y-face partner records (4 per column)
-    T *fk = fy + 4 * lx;                           // cross-point partner (3)
+    const int sink = (ly + 2) * pitch; // 64 + (R - 1) * pitch sink slots
+    T *yfix = vt + sink + 64 + pitch;  // solved y-face points (x, 0)
+    T *xfix = yfix + lx;               // solved x-face points (0, y)
     const int tid = threadIdx.x;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
 
-    // ---- borders: partner column / row (or zeros), zero padding column lx and row ly
+    // ---- borders: zero column -1 and lx, row -1 and ly (partners are read from memory by the face chains)
     for (int r = tid; r < ly + 2; r += 256) {
-        T v = T(0);
-        if (cx && r >= 1 && r <= ly) v = cvt<T>(in[lin2(n0, gx_of(F, -1), gy_of(F, r - 1))]);
-        if (cx && cy && r == 0) v = cvt<T>(in[lin2(n0, gx_of(F, -1), gy_of(F, -1))]);
-        vt[r * pitch] = v;
+        vt[r * pitch] = T(0);
         vt[r * pitch + lx + 1] = T(0);
     }
     for (int c = tid; c < lx; c += 256) {
-        vt[c + 1] = cy ? cvt<T>(in[lin2(n0, gx_of(F, c), gy_of(F, -1))]) : T(0);
+        vt[c + 1] = T(0);
         vt[(ly + 1) * pitch + c + 1] = T(0);
     }
-    if (CPL)
-        for (int i = tid; i < 4 * (lx + ly) + 3; i += 256) fx[i] = cvt<T>(fsrc[i]);
 
     // ---- staging / write-back of column blocks by waves 1..3
     constexpr int NH = 192;
@@ -396,85 +492,35 @@ __device__ __forceinline__ void fast2d_body(const Frame2 &F, int n0, const GP<TI
             if (y < ly && c < nc) out[lin2(n0, gx_of(F, c0 + c), gy_of(F, y))] = (TOUT)(cs * v[u]);
         }
     };
+    const int nbytes = tab[0];
     if (wv >= 1) {
         stage(0);
         if (nblk > 1) stage(1);
     }
-    __syncthreads();
-
-    // ---- recurrence state (wave 0)
-    const int lane_c = min(lane, L - 1);
-    const int rowa = (R * lane_c + 1) * pitch + 1; // LDS index of (x = 0, first row of this lane)
-    const int nbytes = tab[0];
-    const __amdgpu_buffer_rsrc_t rinv = __builtin_amdgcn_make_buffer_rsrc((void *)s_inv_t, 0, nbytes, kBufCfg);
-    const __amdgpu_buffer_rsrc_t rax = __builtin_amdgcn_make_buffer_rsrc((void *)s_ax_t, 0, nbytes, kBufCfg);
-    const __amdgpu_buffer_rsrc_t ray = __builtin_amdgcn_make_buffer_rsrc((void *)s_ay_t, 0, nbytes, kBufCfg);
-    const int voff = lane * R * (int)sizeof(S);
-    V ri[RING], ra[RING], rb[RING];
-    T rc[kPf][R];                 // right-hand sides of the next kPf steps
-    constexpr int kPy = 2;
-    T yq[kPy][5];                 // y-face record and partner value of the next kPy columns
-    T left[R];
-    T last = T(0), yprev = T(0), xplast = T(0);
-#pragma unroll
-    for (int r = 0; r < R; ++r) left[r] = T(0);
-    if (wv == 0) {
-#pragma unroll
-        for (int k = 0; k < RING; ++k) {
-            const int so = tab[1 + k];
-            if (!SC) ri[k] = ldbuf<V>(rinv, voff, so);
-            ra[k] = ldbuf<V>(rax, voff, so);
-            rb[k] = ldbuf<V>(ray, voff, so);
-        }
-#pragma unroll
-        for (int k = 0; k < kPf; ++k) {
-            const int x = min(max(k - lane, -1), lx);
-#pragma unroll
-            for (int r = 0; r < R; ++r) rc[k][r] = vt[rowa + r * pitch + x];
-            if (CPL && k < kPy) {
-                const int xq = min(k, lx - 1);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) yq[k][q] = fy[4 * xq + q];
-                yq[k][4] = vt[xq + 1];
-            }
-        }
-    }
-
-    // x-face data of this lane's rows (partner in column -1): 1/Piv_Q * r_Q (or r_Q), a'_{Q->P},
-    // a'_{Q->upstream}, 1/det; read once, used when the lane reaches x = 0
-    const bool l0 = lane == 0;
-    T xrq[R], xaqp[R], xaqu[R], xidt[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        xrq[r] = T(0);
-        xaqp[r] = T(0);
-        xaqu[r] = T(0);
-        xidt[r] = T(1);
-    }
-    // cross point (cx and cy): lane 0's results at step 0, solved once before the loop
-    T cpv[R], cpupx = T(0), cpyprev = T(0);
-#pragma unroll
-    for (int r = 0; r < R; ++r) cpv[r] = T(0);
-    if (CPL && cx && wv == 0) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int y = R * lane_c + r;
-            const T vq = vt[rowa + r * pitch - 1];
-            xrq[r] = SC ? vq : fx[4 * y] * vq;
-            xaqp[r] = fx[4 * y + 1];
-            xaqu[r] = fx[4 * y + 2];
-            xidt[r] = fx[4 * y + 3];
-        }
-        if (cy) {
-            // A = (0,0), B = (-1,0), C = (0,-1), D = (-1,-1); step 0 uses ring slot 0
-            const T iv = SC ? T(1) : elem<T>(ri[0], 0);
-            const T ax = elem<T>(ra[0], 0), ay = elem<T>(rb[0], 0);
-            const T rhs = SC ? rc[0][0] : iv * rc[0][0];
-            const T ivq = fx[0], aqp = fx[1], aqy = fx[2];
-            const T ivc = fy[0], acp = fy[1], acd = fy[2];
-            const T ivd = fk[0], adb = fk[1], adc = fk[2];
-            const T vb = vt[pitch], vc = vt[1], vd = vt[0];
-            const T rq = SC ? vb : ivq * vb, rcc = SC ? vc : ivc * vc, rd = SC ? vd : ivd * vd;
+    if (CPL && (wv == 1 || wv == 2) && (wv == 1 ? cy : cx)) {
+        // ---- coupled start faces (wave 1: y face, wave 2: x face)
+        const GP<S> *ci = (const GP<S> *)s_inv_t, *cax = (const GP<S> *)s_ax_t, *cay = (const GP<S> *)s_ay_t;
+        // packed coefficients of local point (x, y): lane j = y / R, element y % R of step x + j
+        auto coef = [&](int x, int y, T &iv, T &ax, T &ay) {
+            const int j = y / R, t = x + j;
+            const int64_t e = (fast2d_step_base(t, lx, L) + j - max(0, t - lx + 1)) * R + (y - j * R);
+            iv = SC ? T(1) : cvt<T>(ci[e]);
+            ax = cvt<T>(cax[e]);
+            ay = cvt<T>(cay[e]);
+        };
+        auto rhs_of = [&](T iv, T r) -> T { return SC ? r : iv * r; };
+        auto inv_at = [&](int x, int y) -> T { return cvt<T>(in[lin2(n0, gx_of(F, x), gy_of(F, y))]); };
+        const GP<S> *fxr = fsrc, *fyr = fsrc + 4 * ly, *fkr = fsrc + 4 * (lx + ly);
+        // cross point: A = (0,0), B = (-1,0), C = (0,-1), D = (-1,-1)
+        T vA = T(0), vB = T(0), vC = T(0);
+        if (cx && cy) {
+            T iv, ax, ay;
+            coef(0, 0, iv, ax, ay);
+            const T rhs = rhs_of(iv, inv_at(0, 0));
+            const T ivq = cvt<T>(fxr[0]), aqp = cvt<T>(fxr[1]), aqy = cvt<T>(fxr[2]);
+            const T ivc = cvt<T>(fyr[0]), acp = cvt<T>(fyr[1]), acd = cvt<T>(fyr[2]);
+            const T ivd = cvt<T>(fkr[0]), adb = cvt<T>(fkr[1]), adc = cvt<T>(fkr[2]);
+            const T rq = rhs_of(ivq, inv_at(-1, 0)), rcc = rhs_of(ivc, inv_at(0, -1)), rd = rhs_of(ivd, inv_at(-1, -1));
             T M[4][4] = {{T(1), -ax, -ay, T(0)}, {-aqp, T(1), T(0), -aqy}, {-acp, T(0), T(1), -acd}, {T(0), -adb, -adc, T(1)}};
             T bb[4] = {rhs, rq, rcc, rd};
 #pragma unroll
@@ -495,27 +541,91 @@ __device__ __forceinline__ void fast2d_body(const Frame2 &F, int n0, const GP<TI
                 for (int jj = i + 1; jj < 4; ++jj) acc -= M[i][jj] * bb[jj];
                 bb[i] = acc / M[i][i];
             }
-            cpv[0] = bb[0];
-            cpupx = bb[1];
-            cpyprev = bb[2];
-            if (R == 2) {
-                // row 1 of lane 0: an x-face pair whose upstream partner is B and whose upper neighbour is A
-                const T iv1 = SC ? T(1) : elem<T>(ri[0], 1);
-                const T ax1 = elem<T>(ra[0], 1), ay1 = elem<T>(rb[0], 1);
-                const T rhs1 = SC ? rc[0][R - 1] : iv1 * rc[0][R - 1];
-                const T bq1 = xrq[R - 1] + xaqu[R - 1] * bb[1];
-                cpv[R - 1] = xidt[R - 1] * (rhs1 + ax1 * bq1 + ay1 * bb[0]);
-                cpupx = bq1 + xaqp[R - 1] * cpv[R - 1];
-            }
+            vA = bb[0];
+            vB = bb[1];
+            vC = bb[2];
+        }
+        const int first = (cx && cy) ? 1 : 0; // the cross point is the chains' element 0
+        if (wv == 1) {
+            if (first && lane == 0) yfix[0] = vA;
+            face_chain<T>(
+                lx - first, vA, vC,
+                [&](int k) {
+                    const int x = k + first;
+                    ChainEl<T> e;
+                    T iv;
+                    coef(x, 0, iv, e.a_own, e.a_cross);
+                    e.rhs = rhs_of(iv, inv_at(x, 0));
+                    const T ivq = cvt<T>(fyr[4 * x]);
+                    e.aqp = cvt<T>(fyr[4 * x + 1]);
+                    e.aqu = cvt<T>(fyr[4 * x + 2]);
+                    e.idt = cvt<T>(fyr[4 * x + 3]);
+                    e.rq = rhs_of(ivq, inv_at(x, -1));
+                    return e;
+                },
+                yfix + first, lane);
+        } else {
+            if (first && lane == 0) xfix[0] = vA;
+            face_chain<T>(
+                ly - first, vA, vB,
+                [&](int k) {
+                    const int y = k + first;
+                    ChainEl<T> e;
+                    T iv;
+                    coef(0, y, iv, e.a_cross, e.a_own);
+                    e.rhs = rhs_of(iv, inv_at(0, y));
+                    const T ivq = cvt<T>(fxr[4 * y]);
+                    e.aqp = cvt<T>(fxr[4 * y + 1]);
+                    e.aqu = cvt<T>(fxr[4 * y + 2]);
+                    e.idt = cvt<T>(fxr[4 * y + 3]);
+                    e.rq = rhs_of(ivq, inv_at(-1, y));
+                    return e;
+                },
+                xfix + first, lane);
+        }
+    }
+    __syncthreads();
+
+    // ---- recurrence state (wave 0)
+    const int lane_c = min(lane, L - 1);
+    const int rowa = (R * lane_c + 1) * pitch + 1; // LDS index of (x = 0, first row of this lane)
+    const __amdgpu_buffer_rsrc_t rinv = __builtin_amdgcn_make_buffer_rsrc((void *)s_inv_t, 0, nbytes, kBufCfg);
+    const __amdgpu_buffer_rsrc_t rax = __builtin_amdgcn_make_buffer_rsrc((void *)s_ax_t, 0, nbytes, kBufCfg);
+    const __amdgpu_buffer_rsrc_t ray = __builtin_amdgcn_make_buffer_rsrc((void *)s_ay_t, 0, nbytes, kBufCfg);
+    const int voff = lane * R * (int)sizeof(S);
+    V ri[RING], ra[RING], rb[RING];
+    T rc[kPf][R]; // right-hand sides of the next kPf steps
+    T yf[kPf];    // solved y-face points of the next kPf columns
+    T left[R];
+    T last = T(0);
+    const bool l0 = lane == 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) left[r] = T(0);
+    T xf[R]; // solved x-face points of this lane's rows
+#pragma unroll
+    for (int r = 0; r < R; ++r) xf[r] = (CPL && cx) ? xfix[min(R * lane_c + r, ly - 1)] : T(0);
+    if (wv == 0) {
+#pragma unroll
+        for (int k = 0; k < RING; ++k) {
+            const int so = tab[1 + k];
+            if (!SC) ri[k] = ldbuf<V>(rinv, voff, so);
+            ra[k] = ldbuf<V>(rax, voff, so);
+            rb[k] = ldbuf<V>(ray, voff, so);
+        }
+#pragma unroll
+        for (int k = 0; k < kPf; ++k) {
+            const int x = min(max(k - lane, -1), lx);
+#pragma unroll
+            for (int r = 0; r < R; ++r) rc[k][r] = vt[rowa + r * pitch + x];
+            if (CPL) yf[k] = yfix[min(k, lx - 1)];
         }
     }
 
-    // one step; XF: some lane may be at x = 0 (the x-face pairs and the cross point)
+    // one step; XF: some lane may be at x = 0
     auto step = [&](const int s, const int k, const bool XF) {
         const int slot = k % RING, pk = k % kPf;
         const int x = s - lane;
         const T up_in = lane_up(last);
-        const T upx_in = XF ? lane_up(xplast) : T(0);
         T cur[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) cur[r] = rc[pk][r];
@@ -524,54 +634,27 @@ __device__ __forceinline__ void fast2d_body(const Frame2 &F, int n0, const GP<TI
 #pragma unroll
             for (int r = 0; r < R; ++r) rc[pk][r] = vt[rowa + r * pitch + xn];
         }
-        // y face: lane 0, row 0, column s (partner Q in row -1)
-        T up0 = up_in, cy0 = T(1), bqy = T(0), aqpy = T(0);
+        T yv = T(0);
         if (CPL && cy) {
-            const int py = k % kPy;
-            const T ivq = yq[py][0], aqp = yq[py][1], aqu = yq[py][2], idt = yq[py][3], vq = yq[py][4];
-            const int xq = min(s + kPy, lx - 1);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) yq[py][q] = fy[4 * xq + q];
-            yq[py][4] = vt[xq + 1];
-            bqy = (SC ? vq : ivq * vq) + aqu * yprev;
-            aqpy = aqp;
-            up0 = l0 ? bqy : up_in;
-            cy0 = l0 ? idt : T(1);
+            yv = yf[pk];
+            yf[pk] = yfix[min(s + kPf, lx - 1)];
         }
         const bool isx = XF && cx && x == 0;
         T v[R];
-        T upx = upx_in;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const T iv = SC ? T(1) : elem<T>(ri[slot], r);
             const T ax = elem<T>(ra[slot], r), ay = elem<T>(rb[slot], r);
             const T rhs = SC ? cur[r] : iv * cur[r];
-            const T u = r == 0 ? up0 : v[r - 1];
-            T lf = left[r];
-            T c0 = r == 0 ? cy0 : T(1);
-            T bqx = T(0);
-            if (XF && cx) {
-                bqx = xrq[r] + xaqu[r] * upx;
-                lf = isx ? bqx : lf;
-                c0 = isx ? xidt[r] : c0;
-            }
-            const T val = c0 * (rhs + ax * lf + ay * u);
-            if (XF && cx) upx = isx ? bqx + xaqp[r] * val : upx;
+            const T u = r == 0 ? up_in : v[r - 1];
+            T val = rhs + ax * left[r] + ay * u;
+            if (CPL && cy && r == 0) val = l0 ? yv : val;
+            if (XF && cx) val = isx ? xf[r] : val;
             v[r] = val;
-        }
-        if (XF && k == 0 && cx && cy && s == 0) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) v[r] = l0 ? cpv[r] : v[r];
-            upx = l0 ? cpupx : upx;
-        }
-        if (CPL && cy) {
-            const T yn = bqy + aqpy * v[0];
-            yprev = (XF && k == 0 && cx && s == 0) ? cpyprev : yn;
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) left[r] = v[r];
         last = v[R - 1];
-        if (XF && cx) xplast = isx ? upx : xplast;
         const bool act = x >= 0 && x < lx && lane < L;
         const int a = act ? rowa + x : sink + lane;
 #pragma unroll
@@ -587,25 +670,26 @@ __device__ __forceinline__ void fast2d_body(const Frame2 &F, int n0, const GP<TI
         if (i + 2 < nblk) stage(i + 2);
         if (i - lag >= 0 && i - lag < nblk) wback(i - lag);
     };
-    // intervals in which some lane meets the x face, then the rest
-    const int nxf = (CPL && cx) ? min(niter, (L + KB - 1) / KB) : 0;
-    for (int i = 0; i < nxf; ++i) {
-        if (wv == 0) {
+    // Wave 0 and the helper waves run separate loops with one barrier per
+    // interval each, so the recurrence state is not live in the helpers' code.
+    if (wv == 0) {
+        // intervals in which some lane meets the x face, then the rest
+        const int nxf = (CPL && cx) ? min(niter, (L + KB - 1) / KB) : 0;
+        for (int i = 0; i < nxf; ++i) {
 #pragma unroll
             for (int k = 0; k < KB; ++k) step(i * KB + k, k, CPL);
-        } else {
-            helpers(i);
+            __syncthreads();
         }
-        __syncthreads();
-    }
-    for (int i = nxf; i < niter; ++i) {
-        if (wv == 0) {
+        for (int i = nxf; i < niter; ++i) {
 #pragma unroll
             for (int k = 0; k < KB; ++k) step(i * KB + k, k, false);
-        } else {
-            helpers(i);
+            __syncthreads();
         }
-        __syncthreads();
+    } else {
+        for (int i = 0; i < niter; ++i) {
+            helpers(i);
+            __syncthreads();
+        }
     }
     if (wv >= 1)
         for (int b = max(0, niter - lag); b < nblk; ++b) wback(b);
@@ -861,8 +945,7 @@ void fast2d_fill_tab(int lx, int ly, int R, size_t elem, int *tab) {
 size_t fast2d_lds_bytes(int lx, int ly, int R, size_t elem) {
     const int pitch = fast2d_pitch(lx, R);
     const size_t sink = (size_t)(ly + 2) * pitch;
-    const size_t fx = (sink + 64 + pitch + 3) & ~(size_t)3;
-    return elem * (fx + 4 * (size_t)(lx + ly) + 4);
+    return elem * (sink + 64 + pitch + (size_t)(lx + ly));
 }
 
 hipError_t launch_pack2d(const PassGeom &g, Store s, int R, bool transposed, const double *const *diag,
