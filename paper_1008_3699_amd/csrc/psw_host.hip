@@ -526,9 +526,11 @@ psw_status solve_cg(psw_problem *P, psw_precond kind, double rtol, int64_t maxit
         if (!P->hs.ensure()) return PSW_ENOMEM;
         double *h = P->hs.p;
         while (it < maxit) {
+            // partial sums go to separate regions; the kernels that consume a dot product finish its sum
+            double *part_pq = part + kRedBlocks, *part_rz = part + 2 * kRedBlocks;
             HIPCHK(launch_spmv(P->dim, P->n, d, p, q, st));
-            HIPCHK(launch_dot(p, q, N, part, s_pq, st));
-            HIPCHK(launch_cg_update_xr(x, r, p, q, s_rz, s_pq, N, part, s_rr, st));
+            HIPCHK(launch_dot_partial(p, q, N, part_pq, st));
+            HIPCHK(launch_cg_update_xr(x, r, p, q, s_rz, part_pq, s_pq, N, part, s_rr, st));
             ++it;
             // p.q and r.r of this iteration go to the host behind an event; the rest of the
             // iteration (which leaves x alone) is queued before the host waits for them, so the
@@ -536,8 +538,8 @@ psw_status solve_cg(psw_problem *P, psw_precond kind, double rtol, int64_t maxit
             HIPCHK(hipMemcpyAsync(h, s_pq, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
             HIPCHK(hipEventRecord(P->hs.ev, st));
             if ((ps = precond_apply(P, kind, 1, r, z, st))) return ps;
-            HIPCHK(launch_dot(r, z, N, part, s_rz2, st));
-            HIPCHK(launch_cg_update_p(p, z, s_rz2, s_rz, N, st));
+            HIPCHK(launch_dot_partial(r, z, N, part_rz, st));
+            HIPCHK(launch_cg_update_p_red(p, z, part_rz, s_rz2, s_rz, N, st));
             std::swap(s_rz, s_rz2);
             HIPCHK(hipEventSynchronize(P->hs.ev));
             if (!(h[0] > 0.0) || !std::isfinite(h[1])) {

@@ -76,7 +76,13 @@ hipError_t launch_dot(const double *x, const double *y, int64_t N, double *parti
 // CG helpers with device-resident scalars.
 //   x += alpha p ; r -= alpha q ; alpha = s[0]/s[1]; partial dot r.r -> out
 hipError_t launch_cg_update_xr(double *x, double *r, const double *p, const double *q, const double *num,
-                               const double *den, int64_t N, double *partials, double *rr, hipStream_t st);
+                               const double *den_partials, double *den, int64_t N, double *partials, double *rr,
+                               hipStream_t st);
+// per-block partial sums of x.y (kRedBlocks of them)
+hipError_t launch_dot_partial(const double *x, const double *y, int64_t N, double *partials, hipStream_t st);
+// p = z + beta p with beta = (sum of num_partials) / den[0]; stores the sum to num[0]
+hipError_t launch_cg_update_p_red(double *p, const double *z, const double *num_partials, double *num,
+                                  const double *den, int64_t N, hipStream_t st);
 //   p = z + beta p ; beta = num/den
 hipError_t launch_cg_update_p(double *p, const double *z, const double *num, const double *den, int64_t N,
                               hipStream_t st);

@@ -874,11 +874,21 @@ hipError_t launch_dot(const double *x, const double *y, int64_t N, double *parti
     return hipGetLastError();
 }
 
+// sum of kRedBlocks partials in the fixed order of k_dot_final, by every block that needs it
+__device__ __forceinline__ double sum_partials(const double *p, double *sh) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < kRedBlocks; i += kRedThreads) acc += p[i];
+    return block_sum(acc, sh);
+}
+
+// x += alpha p, r -= alpha q, r.r partials; alpha = num / (sum of den_partials), the sum stored to den
 __global__ void __launch_bounds__(kRedThreads) k_cg_xr(double *x, double *r, const double *p, const double *q,
-                                                      const double *num, const double *den, int64_t N,
-                                                      double *partials) {
+                                                      const double *num, const double *den_partials, double *den,
+                                                      int64_t N, double *partials) {
     __shared__ double sh[kRedThreads];
-    const double alpha = num[0] / den[0];
+    const double pq = sum_partials(den_partials, sh);
+    if (blockIdx.x == 0 && threadIdx.x == 0) den[0] = pq;
+    const double alpha = num[0] / pq;
     double acc = 0.0;
     const int64_t stride = (int64_t)kRedBlocks * kRedThreads;
     for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < N; i += stride) {
@@ -892,9 +902,33 @@ __global__ void __launch_bounds__(kRedThreads) k_cg_xr(double *x, double *r, con
 }
 
 hipError_t launch_cg_update_xr(double *x, double *r, const double *p, const double *q, const double *num,
-                               const double *den, int64_t N, double *partials, double *rr, hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_xr, dim3(kRedBlocks), dim3(kRedThreads), 0, st, x, r, p, q, num, den, N, partials);
+                               const double *den_partials, double *den, int64_t N, double *partials, double *rr,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_xr, dim3(kRedBlocks), dim3(kRedThreads), 0, st, x, r, p, q, num, den_partials, den, N,
+                       partials);
     hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kRedThreads), 0, st, partials, rr);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot_partial(const double *x, const double *y, int64_t N, double *partials, hipStream_t st) {
+    hipLaunchKernelGGL(k_dot_partial, dim3(kRedBlocks), dim3(kRedThreads), 0, st, x, y, N, partials);
+    return hipGetLastError();
+}
+
+// p = z + beta p, beta = (sum of num_partials) / den; the sum stored to num
+__global__ void __launch_bounds__(kRedThreads) k_cg_p_red(double *p, const double *z, const double *num_partials,
+                                                         double *num, const double *den, int64_t N) {
+    __shared__ double sh[kRedThreads];
+    const double rz = sum_partials(num_partials, sh);
+    if (blockIdx.x == 0 && threadIdx.x == 0) num[0] = rz;
+    const double beta = rz / den[0];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = z[i] + beta * p[i];
+}
+
+hipError_t launch_cg_update_p_red(double *p, const double *z, const double *num_partials, double *num,
+                                  const double *den, int64_t N, hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_p_red, dim3(kRedBlocks), dim3(kRedThreads), 0, st, p, z, num_partials, num, den, N);
     return hipGetLastError();
 }
 
