@@ -402,6 +402,35 @@ psw_status half(psw_problem *P, psw_precond kind, int which, const void *in, boo
     return PSW_OK;
 }
 
+// The symmetric form in two pieces for the CG loop (pipelined 2D passes only):
+// z1 = c (backward pass) and z2 = the transposed pair with its end faces, so
+// that z = 0.5 z1 + 0.5 c z2.  Both end-face fixes run on the side stream,
+// beside the forward and the backward pass; st has joined both on return.
+psw_status precond_sym_split(psw_problem *P, psw_precond kind, const double *r, double *z1, double *z2,
+                             hipStream_t st) {
+    PrecState &S = P->pc[kind];
+    if (!S.fast) return PSW_ENOTSUP;
+    if (!P->side.ensure()) return PSW_EDEVICE;
+    const bool f64 = P->prec == PSW_F64;
+    void *y1 = P->w_y.p, *y2 = P->w_y2.p;
+    psw_status ps;
+    if ((ps = fast_pass(P, kind, 2, r, true, false, y2, f64, 1.0, nullptr, 0.0, st))) return ps;
+    HIPCHK(hipEventRecord(P->side.fork, st));
+    HIPCHK(hipStreamWaitEvent(P->side.s, P->side.fork, 0));
+    if ((ps = fast_end(P, kind, 2, r, true, false, y2, f64, P->side.s))) return ps;
+    HIPCHK(hipEventRecord(P->side.join, P->side.s));
+    if ((ps = fast_pass(P, kind, 0, r, true, false, y1, f64, 1.0, nullptr, 0.0, st))) return ps;
+    HIPCHK(hipStreamWaitEvent(st, P->side.join, 0));
+    if ((ps = fast_pass(P, kind, 3, y2, f64, true, z2, true, 1.0, nullptr, 0.0, st))) return ps;
+    HIPCHK(hipEventRecord(P->side.fork, st));
+    HIPCHK(hipStreamWaitEvent(P->side.s, P->side.fork, 0));
+    if ((ps = fast_end(P, kind, 3, y2, f64, true, z2, true, P->side.s))) return ps;
+    HIPCHK(hipEventRecord(P->side.join, P->side.s));
+    if ((ps = fast_pass(P, kind, 1, y1, f64, true, z1, true, S.c, nullptr, 0.0, st))) return ps;
+    HIPCHK(hipStreamWaitEvent(st, P->side.join, 0));
+    return PSW_OK;
+}
+
 psw_status precond_apply(psw_problem *P, psw_precond kind, int symmetric, const double *r, double *z,
                          hipStream_t st) {
     if (kind == PSW_NONE) {
@@ -520,14 +549,25 @@ psw_status solve_cg(psw_problem *P, psw_precond kind, double rtol, int64_t maxit
     int64_t it = 0;
     bool conv = rel <= rtol;
     if (!conv) {
-        if ((ps = precond_apply(P, kind, 1, r, z, st))) return ps;
-        HIPCHK(launch_dot(r, z, N, part, s_rz, st));
-        HIPCHK(hipMemcpyAsync(p, z, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+        // with the pipelined 2D passes the preconditioned residual stays in two pieces,
+        // z = 0.5 z1 + 0.5 c z2, formed inside the two kernels that read it
+        const bool split = kind != PSW_NONE && P->pc[kind].fast;
+        double *z2 = P->w_z1.as<double>();
+        const double hc = kind != PSW_NONE ? 0.5 * P->pc[kind].c : 0.0;
+        double *part_pq = part + kRedBlocks, *part_rz = part + 2 * kRedBlocks;
+        if (split) {
+            if ((ps = precond_sym_split(P, kind, r, z, z2, st))) return ps;
+            HIPCHK(launch_dot_partial_zz(r, z, z2, hc, N, part_rz, st));
+            HIPCHK(launch_dot_final(part_rz, s_rz, st));
+            HIPCHK(launch_zcomb(p, z, z2, hc, N, st));
+        } else {
+            if ((ps = precond_apply(P, kind, 1, r, z, st))) return ps;
+            HIPCHK(launch_dot(r, z, N, part, s_rz, st));
+            HIPCHK(hipMemcpyAsync(p, z, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+        }
         if (!P->hs.ensure()) return PSW_ENOMEM;
         double *h = P->hs.p;
         while (it < maxit) {
-            // partial sums go to separate regions; the kernels that consume a dot product finish its sum
-            double *part_pq = part + kRedBlocks, *part_rz = part + 2 * kRedBlocks;
             HIPCHK(launch_spmv(P->dim, P->n, d, p, q, st));
             HIPCHK(launch_dot_partial(p, q, N, part_pq, st));
             HIPCHK(launch_cg_update_xr(x, r, p, q, s_rz, part_pq, s_pq, N, part, s_rr, st));
@@ -537,9 +577,15 @@ psw_status solve_cg(psw_problem *P, psw_precond kind, double rtol, int64_t maxit
             // device stays busy while the stopping test runs
             HIPCHK(hipMemcpyAsync(h, s_pq, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
             HIPCHK(hipEventRecord(P->hs.ev, st));
-            if ((ps = precond_apply(P, kind, 1, r, z, st))) return ps;
-            HIPCHK(launch_dot_partial(r, z, N, part_rz, st));
-            HIPCHK(launch_cg_update_p_red(p, z, part_rz, s_rz2, s_rz, N, st));
+            if (split) {
+                if ((ps = precond_sym_split(P, kind, r, z, z2, st))) return ps;
+                HIPCHK(launch_dot_partial_zz(r, z, z2, hc, N, part_rz, st));
+                HIPCHK(launch_cg_update_p_red_zz(p, z, z2, hc, part_rz, s_rz2, s_rz, N, st));
+            } else {
+                if ((ps = precond_apply(P, kind, 1, r, z, st))) return ps;
+                HIPCHK(launch_dot_partial(r, z, N, part_rz, st));
+                HIPCHK(launch_cg_update_p_red(p, z, part_rz, s_rz2, s_rz, N, st));
+            }
             std::swap(s_rz, s_rz2);
             HIPCHK(hipEventSynchronize(P->hs.ev));
             if (!(h[0] > 0.0) || !std::isfinite(h[1])) {

@@ -78,8 +78,17 @@ hipError_t launch_dot(const double *x, const double *y, int64_t N, double *parti
 hipError_t launch_cg_update_xr(double *x, double *r, const double *p, const double *q, const double *num,
                                const double *den_partials, double *den, int64_t N, double *partials, double *rr,
                                hipStream_t st);
+// out[0] = sum of kRedBlocks partials (fixed order)
+hipError_t launch_dot_final(const double *partials, double *out, hipStream_t st);
 // per-block partial sums of x.y (kRedBlocks of them)
 hipError_t launch_dot_partial(const double *x, const double *y, int64_t N, double *partials, hipStream_t st);
+// with z = 0.5 z1 + b z2 formed on the fly: r.z partials; p = z + beta p (beta from r.z partials); z itself
+hipError_t launch_dot_partial_zz(const double *r, const double *z1, const double *z2, double b, int64_t N,
+                                 double *partials, hipStream_t st);
+hipError_t launch_cg_update_p_red_zz(double *p, const double *z1, const double *z2, double b,
+                                     const double *num_partials, double *num, const double *den, int64_t N,
+                                     hipStream_t st);
+hipError_t launch_zcomb(double *z, const double *z1, const double *z2, double b, int64_t N, hipStream_t st);
 // p = z + beta p with beta = (sum of num_partials) / den[0]; stores the sum to num[0]
 hipError_t launch_cg_update_p_red(double *p, const double *z, const double *num_partials, double *num,
                                   const double *den, int64_t N, hipStream_t st);

@@ -910,6 +910,11 @@ hipError_t launch_cg_update_xr(double *x, double *r, const double *p, const doub
     return hipGetLastError();
 }
 
+hipError_t launch_dot_final(const double *partials, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kRedThreads), 0, st, partials, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_dot_partial(const double *x, const double *y, int64_t N, double *partials, hipStream_t st) {
     hipLaunchKernelGGL(k_dot_partial, dim3(kRedBlocks), dim3(kRedThreads), 0, st, x, y, N, partials);
     return hipGetLastError();
@@ -924,6 +929,55 @@ __global__ void __launch_bounds__(kRedThreads) k_cg_p_red(double *p, const doubl
     const double beta = rz / den[0];
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = z[i] + beta * p[i];
+}
+
+// z = 0.5 z1 + b z2, with one rounding after the exact halving (the symmetric preconditioner's combination)
+__device__ __forceinline__ double zcomb(double z1, double z2, double b) { return __fma_rn(b, z2, 0.5 * z1); }
+
+__global__ void __launch_bounds__(kRedThreads) k_dot_partial_zz(const double *r, const double *z1, const double *z2,
+                                                               double b, int64_t N, double *partials) {
+    __shared__ double sh[kRedThreads];
+    double acc = 0.0;
+    const int64_t stride = (int64_t)kRedBlocks * kRedThreads;
+    for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < N; i += stride)
+        acc += r[i] * zcomb(z1[i], z2[i], b);
+    double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+hipError_t launch_dot_partial_zz(const double *r, const double *z1, const double *z2, double b, int64_t N,
+                                 double *partials, hipStream_t st) {
+    hipLaunchKernelGGL(k_dot_partial_zz, dim3(kRedBlocks), dim3(kRedThreads), 0, st, r, z1, z2, b, N, partials);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(kRedThreads) k_cg_p_red_zz(double *p, const double *z1, const double *z2, double b,
+                                                            const double *num_partials, double *num,
+                                                            const double *den, int64_t N) {
+    __shared__ double sh[kRedThreads];
+    const double rz = sum_partials(num_partials, sh);
+    if (blockIdx.x == 0 && threadIdx.x == 0) num[0] = rz;
+    const double beta = rz / den[0];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = zcomb(z1[i], z2[i], b) + beta * p[i];
+}
+
+hipError_t launch_cg_update_p_red_zz(double *p, const double *z1, const double *z2, double b,
+                                     const double *num_partials, double *num, const double *den, int64_t N,
+                                     hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_p_red_zz, dim3(kRedBlocks), dim3(kRedThreads), 0, st, p, z1, z2, b, num_partials, num,
+                       den, N);
+    return hipGetLastError();
+}
+
+__global__ void k_zcomb(double *z, const double *z1, const double *z2, double b, int64_t N) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+        z[i] = zcomb(z1[i], z2[i], b);
+}
+
+hipError_t launch_zcomb(double *z, const double *z1, const double *z2, double b, int64_t N, hipStream_t st) {
+    hipLaunchKernelGGL(k_zcomb, dim3(grid_for(N)), dim3(256), 0, st, z, z1, z2, b, N);
+    return hipGetLastError();
 }
 
 hipError_t launch_cg_update_p_red(double *p, const double *z, const double *num_partials, double *num,
