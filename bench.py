@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--serve-budget-gib", type=float, default=64.0, help="serve: admission budget (GiB of HBM)")
     ap.add_argument("--serve-plain-s", type=float, default=10.0,
                     help="serve: time spent solving a sample one by one with the plain FP64 solver")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="varcoef2048: only the timed half-sweeps of the roofline object and a plain copy of "
+                         "512 MiB (the reference for hardware byte counters); no solve")
     return ap.parse_args()
 
 
@@ -85,6 +88,15 @@ def main():
     g.precond_setup(args.precond)
     u = torch.zeros(N, dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
+    if args.roofline_only:
+        roofline = measure_roofline(g, N, args, stream)
+        # reference for byte counters: one plain device copy of 512 MiB
+        src = torch.ones(64 << 20, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"roofline": roofline, "copy_bytes_each_way": src.numel() * 8}), flush=True)
+        return
 
     def one_solve():
         u.zero_()
@@ -93,6 +105,8 @@ def main():
     for _ in range(args.warmup):
         one_solve()
     torch.cuda.synchronize()
+    # the dominant kernel (pass 0) is timed with HIP events on its own stream inside the timed solves
+    g.pass_timing_enable(0, True)
     lat = []
     infos = []
     t0 = time.perf_counter()
@@ -109,30 +123,9 @@ def main():
     half_sweeps = sum(4 * (it + 1) for it in iters)
     value = N * half_sweeps / elapsed / 1e9
 
-    # dominant kernel: forward start-coupled half-sweep, timed with HIP events on its stream.
-    # The four half-sweeps run in turn, as inside CG, so the timed pass finds the
-    # Infinity Cache holding the other passes' data (their coefficients exceed it).
-    r = torch.randn(N, dtype=torch.float64, device=dev)
-    y = torch.empty_like(r)
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.kernel_reps)]
-    for k in range(args.kernel_reps + 2):
-        if k >= 2:
-            evs[k - 2][0].record(stream)
-        g.precond_half(args.precond, 0, r, y)
-        if k >= 2:
-            evs[k - 2][1].record(stream)
-        for which in (1, 2, 3):
-            g.precond_half(args.precond, which, r, y)
-    torch.cuda.synchronize()
-    k_ms = sum(a.elapsed_time(b) for a, b in evs) / args.kernel_reps
-    bpp = {"f64": 40, "f32": 28, "bf16": 20}[args.prec]  # r(8) + Piv + 2 upstream couplings + y
-    alg_bytes = bpp * N
-    achieved = alg_bytes / (k_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_fast2d<2,double,...,SC=false,CPL=true> (forward start-coupled half-sweep)", "kernel_ms": round(k_ms, 4),
-                "bytes_per_point": bpp}
-
+    k_ms, k_n = g.pass_timing()
+    g.pass_timing_enable(0, False)
+    roofline = measure_roofline(g, N, args, stream, k_ms=k_ms, k_n=k_n)
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(w, n, p, args.precond, args.cpu_sample_s)
@@ -356,6 +349,51 @@ def bench_serve(args):
         "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(rec), flush=True)
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_fast2d_fwd_varcoef2048.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1008_3699_amd", "csrc", "psw_fast2d.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the timed kernel from the committed counter runs, or None when the
+    kernel source has changed since they were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        h = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != h:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def measure_roofline(g, N, args, stream, k_ms=None, k_n=None):
+    """Dominant kernel: the forward start-coupled half-sweep (pass 0).  k_ms: its mean duration
+    from the library's HIP events around its launches inside the timed solves.  Without it (the
+    --roofline-only run) the four passes run in turn as inside CG and pass 0 is timed the same way."""
+    import torch
+    how = "HIP events on the launching stream around every 8th pass-0 launch inside the timed solves"
+    if k_ms is None:
+        r = torch.randn(N, dtype=torch.float64, device=stream.device)
+        y = torch.empty_like(r)
+        g.pass_timing_enable(0, True)
+        for k in range(8 * args.kernel_reps):
+            for which in (0, 1, 2, 3):
+                g.precond_half(args.precond, which, r, y)
+        k_ms, k_n = g.pass_timing()
+        g.pass_timing_enable(0, False)
+        how = "HIP events around every 8th pass-0 launch, the four passes running in turn"
+    bpp = {"f64": 40, "f32": 28, "bf16": 20}[args.prec]  # r(8) + Piv + 2 upstream couplings + y
+    alg_bytes = bpp * N
+    achieved = alg_bytes / (k_ms * 1e-3) / 1e9
+    traffic = measured_traffic() if (args.prec == "f64" and args.n == 2048 and args.p == 16) else None
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "k_fast2d<2,double,...,SC=false,CPL=true> (forward start-coupled half-sweep)",
+            "kernel_ms": round(k_ms, 4), "timed_launches": k_n, "timing": how, "bytes_per_point": bpp,
+            "algorithmic_bytes": alg_bytes}
 
 
 def cpu_baseline(w, n, p, kind, budget_s):

@@ -188,6 +188,15 @@ psw_status psw_batch_solve(int count, psw_problem *const *probs, const double *c
 psw_status psw_autotune(int dim, const int64_t n[3], psw_prec prec, psw_precond kind, int p_out[3],
                         double *us_per_problem, void *stream);
 
+/* Measurement aid: while enabled, the library records HIP events on the
+ * launching stream around every 8th launch (at most 1024) of pipelined pass
+ * `which` (0..3; the 2D pipelined path only) of this problem, inside solves
+ * and preconditioner calls alike.  psw_pass_timing returns the mean duration
+ * of the recorded launches in ms and their number since the last enable
+ * (it waits for them to complete).  Enabling resets the record. */
+psw_status psw_pass_timing_enable(psw_problem *prob, int which, int enable);
+psw_status psw_pass_timing(psw_problem *prob, double *mean_ms, int64_t *count);
+
 /* ---------------------------------------------------------------- serving
  * A server solves a stream of independent problems A u = f with
  * -div(alpha grad u) + beta u on unit-spaced grids (2D 5-point or 3D

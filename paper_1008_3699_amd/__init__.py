@@ -70,6 +70,8 @@ def lib():
             "psw_dot": [vp, vp, vp, ctypes.POINTER(dbl), vp],
             "psw_solve": [vp, ci, ci, dbl, i64, ci, vp, vp, ctypes.POINTER(Info), vp],
             "psw_batch_solve": [ci, pp, pp, pp, ci, ci, dbl, i64, ctypes.POINTER(Info), vp],
+            "psw_pass_timing_enable": [vp, ci, ci],
+            "psw_pass_timing": [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -191,6 +193,15 @@ class Problem:
         _check(lib().psw_dot(self._h, _ptr(x, self.N, "x"), _ptr(y, self.N, "y"), ctypes.byref(out),
                              _stream(stream)), "psw_dot")
         return out.value
+
+    def pass_timing_enable(self, which, enable=True):
+        _check(lib().psw_pass_timing_enable(self._h, int(which), int(bool(enable))), "psw_pass_timing_enable")
+
+    def pass_timing(self):
+        """(mean ms, number of timed launches) of the pass selected by pass_timing_enable."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().psw_pass_timing(self._h, ctypes.byref(ms), ctypes.byref(n)), "psw_pass_timing")
+        return ms.value, n.value
 
     def solve(self, method, precond, f, u, rtol=1e-8, maxit=100000, restart=30, stream=None, check=True):
         info = Info()

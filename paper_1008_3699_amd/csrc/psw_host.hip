@@ -105,6 +105,19 @@ struct HostScalars {
     }
 };
 
+// timing of one pipelined pass inside solves: events around every kStride-th launch
+struct PassTiming {
+    static constexpr int kPool = 1024, kStride = 8;
+    bool on = false;
+    int which = 0;
+    int64_t calls = 0, used = 0;
+    std::vector<hipEvent_t> ev; // 2 * kPool
+    ~PassTiming() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
 struct PrecState {
     bool ready = false;
     double omega = 1.0;
@@ -144,6 +157,7 @@ struct psw_problem {
     size_t lds_limit = 65536;
     SideStream side;
     HostScalars hs;
+    PassTiming timing;
 };
 
 namespace {
@@ -362,8 +376,15 @@ psw_status fast_pass(psw_problem *P, psw_precond kind, int which, const void *in
                      void *out, bool out_f64, double cscale, const double *add, double cadd, hipStream_t st) {
     PrecState &S = P->pc[kind];
     const Fast2dPass fp = fast_pass_desc(P, S, which);
+    PassTiming &T = P->timing;
+    const bool timed = T.on && T.which == which && (T.calls++ % PassTiming::kStride) == 0 && T.used < PassTiming::kPool;
+    if (timed) HIPCHK(hipEventRecord(T.ev[2 * T.used], st));
     HIPCHK(launch_fast2d(fp, store_of(P->prec), in, in_f64, scale_by_piv, out, out_f64, which <= 1 ? cscale : 1.0,
                          add, cadd, st));
+    if (timed) {
+        HIPCHK(hipEventRecord(T.ev[2 * T.used + 1], st));
+        ++T.used;
+    }
     return PSW_OK;
 }
 
@@ -1491,6 +1512,38 @@ psw_status psw_server_destroy(psw_server *S) {
     if (S->w2.joinable()) S->w2.join();
     if (S->w3.joinable()) S->w3.join();
     delete S;
+    return PSW_OK;
+}
+
+psw_status psw_pass_timing_enable(psw_problem *P, int which, int enable) {
+    if (!P || which < 0 || which > 3) return PSW_EINVAL;
+    DeviceGuard dg(P->device);
+    PassTiming &T = P->timing;
+    if (enable && T.ev.empty()) {
+        T.ev.assign(2 * PassTiming::kPool, nullptr);
+        for (auto &e : T.ev)
+            if (hipEventCreate(&e) != hipSuccess) return PSW_EDEVICE;
+    }
+    T.on = enable != 0;
+    T.which = which;
+    T.calls = 0;
+    T.used = 0;
+    return PSW_OK;
+}
+
+psw_status psw_pass_timing(psw_problem *P, double *mean_ms, int64_t *count) {
+    if (!P || !mean_ms || !count) return PSW_EINVAL;
+    DeviceGuard dg(P->device);
+    PassTiming &T = P->timing;
+    double sum = 0.0;
+    for (int64_t i = 0; i < T.used; ++i) {
+        float ms = 0.f;
+        HIPCHK(hipEventSynchronize(T.ev[2 * i + 1]));
+        HIPCHK(hipEventElapsedTime(&ms, T.ev[2 * i], T.ev[2 * i + 1]));
+        sum += ms;
+    }
+    *count = T.used;
+    *mean_ms = T.used ? sum / (double)T.used : 0.0;
     return PSW_OK;
 }
 

@@ -223,3 +223,22 @@ def test_full_size_varcoef_2048_half_sweeps(kind):
     g.precond_half(kind, 2, r, out)
     yt = O.dsolve_t(2, n, p, pc.dirs_b, diags, pc.piv, w["f"])
     assert relmax(to_np(out), yt) <= 1e-12
+
+
+def test_pass_timing_records_launches():
+    """The measurement aid counts every 8th launch of the selected pass and reports a positive mean."""
+    import torch
+    n, p = (256, 192), (4, 3)
+    pr, diags = _prob(2, n, seed=8)
+    g = make_problem(2, n, pr["alphas"])
+    g.set_relaxation([1.0])
+    g.set_decomposition(p, overlap=2)
+    g.precond_setup("ilu0")
+    r = to_dev(pr["f"]); y = torch.empty_like(r)
+    g.pass_timing_enable(0, True)
+    for _ in range(17):
+        g.precond_half("ilu0", 0, r, y)
+        g.precond_half("ilu0", 1, r, y)
+    ms, cnt = g.pass_timing()
+    g.pass_timing_enable(0, False)
+    assert cnt == 3 and ms > 0.0  # launches 0, 8 and 16 of pass 0
