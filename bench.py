@@ -46,9 +46,11 @@ def parse():
                          "solved together per step; serve: a stream of Poisson arrivals through the server")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--plain-sample", type=int, default=24, help="batch512: problems solved one by one in FP64")
-    ap.add_argument("--serve-count", type=int, default=120, help="serve: number of requests in the stream")
+    ap.add_argument("--serve-count", type=int, default=40, help="serve: number of requests in the stream")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="serve: mean arrival rate (requests/s)")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0, help="serve: admission budget (GiB of HBM)")
+    ap.add_argument("--serve-precond", default="ssor", choices=["ilu0", "ssor"], help="serve: preconditioner")
+    ap.add_argument("--serve-lanes3d", type=int, default=4, help="serve: 3D requests solved at once")
     ap.add_argument("--serve-plain-s", type=float, default=10.0,
                     help="serve: time spent solving a sample one by one with the plain FP64 solver")
     ap.add_argument("--roofline-only", action="store_true",
@@ -265,11 +267,12 @@ def bench_serve(args):
     reqs = synth.serving_stream(count=args.serve_count, rate=args.serve_rate)
     fields = [synth.request_fields(r) for r in reqs]
     # tile shapes for every 2D size bucket are tuned before the stream starts
+    precond = args.serve_precond
     for b in sorted({max(32, ((r["n"][0] + 32) // 64) * 64) for r in reqs if r["dim"] == 2}):
-        P.autotune(2, (b, b), prec, args.precond)
+        P.autotune(2, (b, b), prec, precond)
     torch.cuda.synchronize()
     budget = int(args.serve_budget_gib * (1 << 30))
-    srv = P.Server(budget, prec=prec, precond=args.precond, rtol=args.rtol, maxit=args.maxit)
+    srv = P.Server(budget, prec=prec, precond=precond, rtol=args.rtol, maxit=args.maxit, lanes3d=args.serve_lanes3d)
     t0 = time.perf_counter()
     tickets = []
     for r, fl in zip(reqs, fields):
@@ -307,12 +310,12 @@ def bench_serve(args):
         else:
             pp = tuple(max(1, min(v // 2, -(-v // 32))) for v in n)
         g.set_decomposition(pp, overlap=2)
-        g.precond_setup(args.precond)
+        g.precond_setup(precond)
         f = torch.from_numpy(fl["f"]).to(dev)
         u = torch.zeros_like(f)
         torch.cuda.synchronize()
         a = time.perf_counter()
-        g.solve("cg", args.precond, f, u, rtol=args.rtol, maxit=args.maxit)
+        g.solve("cg", precond, f, u, rtol=args.rtol, maxit=args.maxit)
         torch.cuda.synchronize()
         t_plain += time.perf_counter() - a
         n_plain += 1
@@ -330,8 +333,9 @@ def bench_serve(args):
         "dtype": prec, "data": "synthetic",
         "config": {"workload": f"{len(reqs)} requests, Poisson arrivals at {args.serve_rate:g}/s, 2D 5-point "
                                "64^2..1024^2 and 3D 7-point 32^3..128^3, coefficients log-uniform [1e-2,1e2], "
-                               f"rhs U[-1,1], {args.precond.upper()}-PCG to {args.rtol:g}, FP64 CG / {prec} sweeps",
-                   "budget_gib": args.serve_budget_gib, "requests_2d": int((dims == 2).sum()),
+                               f"rhs U[-1,1], {precond.upper()}(1)-PCG to {args.rtol:g}, FP64 CG / {prec} sweeps",
+                   "budget_gib": args.serve_budget_gib, "lanes3d": args.serve_lanes3d,
+                   "requests_2d": int((dims == 2).sum()),
                    "requests_3d": int((dims == 3).sum())},
         "p50_ms": round(float(np.percentile(lat, 50)), 2),
         "p99_ms": round(float(np.percentile(lat, 99)), 2),

@@ -205,8 +205,9 @@ psw_status psw_pass_timing(psw_problem *prob, double *mean_ms, int64_t *count);
  * budget_bytes; requests wait in arrival order until their reservation fits.
  * 2D requests are batched continuously: between epochs of epoch_iters CG
  * iterations of all active 2D problems, admitted requests join and finished
- * ones leave and free their memory.  3D requests are solved one at a time on
- * a second stream that overlaps with the 2D batch.  A request's arithmetic
+ * ones leave and free their memory.  3D requests are solved by lanes3d worker
+ * lanes, one request each at a time on its own stream, overlapping with the
+ * 2D batch and with each other.  A request's arithmetic
  * does not depend on the other requests in the batch.  Thread-safe. */
 typedef struct psw_server psw_server;
 typedef struct {
@@ -216,6 +217,7 @@ typedef struct {
     int64_t maxit;       /* iteration limit per request */
     int epoch_iters;     /* CG iterations between admissions (rounded up to even; <= 0: 16) */
     int max_active;      /* most 2D problems in the batch at once (<= 0: 1024) */
+    int lanes3d;         /* 3D requests solved at once, each on its own stream (<= 0: 4; at most 16) */
 } psw_server_opts;
 
 psw_status psw_server_create(size_t budget_bytes, const psw_server_opts *opts, psw_server **out);

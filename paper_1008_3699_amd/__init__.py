@@ -244,7 +244,8 @@ def autotune(dim, n, prec="f64", precond="ssor", stream=None):
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int), ("precond", ctypes.c_int), ("rtol", ctypes.c_double),
-                ("maxit", ctypes.c_int64), ("epoch_iters", ctypes.c_int), ("max_active", ctypes.c_int)]
+                ("maxit", ctypes.c_int64), ("epoch_iters", ctypes.c_int), ("max_active", ctypes.c_int),
+                ("lanes3d", ctypes.c_int)]
 
 
 class Server:
@@ -255,7 +256,7 @@ class Server:
     """
 
     def __init__(self, budget_bytes, prec="f32", precond="ilu0", rtol=1e-8, maxit=100000, epoch_iters=16,
-                 max_active=1024):
+                 max_active=1024, lanes3d=4):
         L = lib()
         vp = ctypes.c_void_p
         L.psw_server_create.argtypes = [ctypes.c_size_t, ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
@@ -267,7 +268,8 @@ class Server:
         L.psw_server_destroy.argtypes = [vp]
         for fn in (L.psw_server_create, L.psw_server_submit, L.psw_server_poll, L.psw_server_destroy):
             fn.restype = ctypes.c_int
-        opts = ServerOpts(_PREC[prec], _KIND[precond], float(rtol), int(maxit), int(epoch_iters), int(max_active))
+        opts = ServerOpts(_PREC[prec], _KIND[precond], float(rtol), int(maxit), int(epoch_iters), int(max_active),
+                          int(lanes3d))
         h = ctypes.c_void_p()
         _check(L.psw_server_create(int(budget_bytes), ctypes.byref(opts), ctypes.byref(h)), "psw_server_create")
         self._h = h

@@ -1195,11 +1195,13 @@ struct psw_server {
     int64_t maxit = 100000;
     int epoch_iters = 16;
     int max_active = 1024;
+    int lanes3d = 4;
     bool stop = false;
     uint64_t next_id = 1;
     int device = 0;
     int64_t n_done = 0;
-    std::thread w2, w3;
+    std::thread w2;
+    std::vector<std::thread> w3;
 };
 
 namespace {
@@ -1447,9 +1449,10 @@ psw_status psw_server_create(size_t budget_bytes, const psw_server_opts *opts, p
         S->maxit = opts->maxit;
         if (opts->epoch_iters > 0) S->epoch_iters = (opts->epoch_iters + 1) & ~1;
         if (opts->max_active > 0) S->max_active = opts->max_active;
+        if (opts->lanes3d > 0) S->lanes3d = std::min(opts->lanes3d, 16);
     }
     S->w2 = std::thread(srv_lane2d, S);
-    S->w3 = std::thread(srv_lane3d, S);
+    for (int k = 0; k < S->lanes3d; ++k) S->w3.emplace_back(srv_lane3d, S);
     *out = S;
     return PSW_OK;
 }
@@ -1510,7 +1513,8 @@ psw_status psw_server_destroy(psw_server *S) {
         S->cv.notify_all();
     }
     if (S->w2.joinable()) S->w2.join();
-    if (S->w3.joinable()) S->w3.join();
+    for (auto &t : S->w3)
+        if (t.joinable()) t.join();
     delete S;
     return PSW_OK;
 }
