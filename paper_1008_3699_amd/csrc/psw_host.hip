@@ -97,7 +97,7 @@ struct HostScalars {
     }
     bool ensure() {
         if (p) return true;
-        if (hipHostMalloc((void **)&p, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        if (hipHostMalloc((void **)&p, (8 + kRedBlocks) * sizeof(double), hipHostMallocDefault) != hipSuccess) {
             p = nullptr;
             return false;
         }
@@ -548,6 +548,74 @@ psw_status solve_stationary(psw_problem *P, double rtol, int64_t maxit, const do
     return conv ? PSW_OK : PSW_ENOCONV;
 }
 
+// CG iterations on a 2D grid with r = f - A x already in w_r.  Per iteration:
+// the fused step (p, deferred x update, q = A p, p.q partials), the r update
+// with its r.r partials, the preconditioner and the r.z partials.  p alternates
+// between w_p and w_t; the last step's x update is applied on exit.
+psw_status cg2d_fused(psw_problem *P, psw_precond kind, bool split, double rtol, int64_t maxit, double nf, double *x,
+                      int64_t &it, bool &conv, hipStream_t st) {
+    const double *d[7];
+    diag64(P, d);
+    const int64_t N = P->N;
+    double *r = P->w_r.as<double>(), *z = P->w_z.as<double>(), *q = P->w_q.as<double>();
+    double *pa = P->w_p.as<double>(), *pb = P->w_t.as<double>();
+    double *z2 = split ? P->w_z1.as<double>() : nullptr;
+    const double hc = split ? 0.5 * P->pc[kind].c : 0.0;
+    double *s = P->scal.as<double>();
+    double *s_rz = s + 0, *s_rz2 = s + 1;
+    double *part = P->partials.as<double>();
+    double *part_pq = part + kRedBlocks, *part_rz = part + 2 * kRedBlocks, *out = part + 3 * kRedBlocks;
+    int npq = 0;
+    psw_status ps;
+    // z from r, then its r.z partials
+    auto precond = [&]() -> psw_status {
+        if (split) {
+            psw_status e = precond_sym_split(P, kind, r, z, z2, st);
+            if (e) return e;
+            HIPCHK(launch_dot_partial_zz(r, z, z2, hc, N, part_rz, st));
+        } else {
+            const double *zz = r;
+            if (kind != PSW_NONE) {
+                psw_status e = precond_apply(P, kind, 1, r, z, st);
+                if (e) return e;
+                zz = z;
+            }
+            HIPCHK(launch_dot_partial(r, zz, N, part_rz, st));
+        }
+        return PSW_OK;
+    };
+    const double *z1 = (split || kind != PSW_NONE) ? z : r;
+    if ((ps = precond())) return ps;
+    if (!P->hs.ensure()) return PSW_ENOMEM;
+    double *h = P->hs.p;
+    while (it < maxit) {
+        HIPCHK(launch_cg_pq2d(P->n[0], P->n[1], d, z1, z2, hc, pa, pb, q, x, part_rz, s_rz2, s_rz, out + 1, it == 0,
+                              part_pq, &npq, st));
+        std::swap(pa, pb);
+        std::swap(s_rz, s_rz2);
+        HIPCHK(launch_cg_r(r, q, s_rz, part_pq, npq, out, N, st));
+        ++it;
+        // p.q and the r.r partials go to the host behind an event; the next preconditioner is
+        // queued before the host waits for them, so the device stays busy during the test
+        HIPCHK(hipMemcpyAsync(h, out, (2 + kRedBlocks) * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipEventRecord(P->hs.ev, st));
+        if ((ps = precond())) return ps;
+        HIPCHK(hipEventSynchronize(P->hs.ev));
+        double rr = 0.0;
+        for (int b = 0; b < kRedBlocks; ++b) rr += h[2 + b];
+        if (!(h[0] > 0.0) || !std::isfinite(rr)) {
+            (void)hipStreamSynchronize(st);
+            return PSW_EBREAKDOWN;
+        }
+        if (std::sqrt(rr) / nf <= rtol) {
+            conv = true;
+            break;
+        }
+    }
+    if (it > 0) HIPCHK(launch_axpy_dev(x, out + 1, pa, N, st));
+    return PSW_OK;
+}
+
 psw_status solve_cg(psw_problem *P, psw_precond kind, double rtol, int64_t maxit, const double *f, double *x,
                     psw_info *info, hipStream_t st) {
     psw_status ps = ensure_work(P);
@@ -576,6 +644,11 @@ psw_status solve_cg(psw_problem *P, psw_precond kind, double rtol, int64_t maxit
         double *z2 = P->w_z1.as<double>();
         const double hc = kind != PSW_NONE ? 0.5 * P->pc[kind].c : 0.0;
         double *part_pq = part + kRedBlocks, *part_rz = part + 2 * kRedBlocks;
+        if (P->dim == 2) {
+            ps = cg2d_fused(P, kind, split, rtol, maxit, nf, x, it, conv, st);
+            if (ps) return ps;
+            goto done;
+        }
         if (split) {
             if ((ps = precond_sym_split(P, kind, r, z, z2, st))) return ps;
             HIPCHK(launch_dot_partial_zz(r, z, z2, hc, N, part_rz, st));
@@ -620,6 +693,7 @@ psw_status solve_cg(psw_problem *P, psw_precond kind, double rtol, int64_t maxit
             }
         }
     }
+done:
     // true residual at exit
     HIPCHK(launch_residual(P->dim, P->n, d, f, x, r, st));
     if ((ps = host_norm(P, r, &nr, st))) return ps;

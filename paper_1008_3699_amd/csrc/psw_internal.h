@@ -96,6 +96,20 @@ hipError_t launch_cg_update_p_red(double *p, const double *z, const double *num_
 hipError_t launch_cg_update_p(double *p, const double *z, const double *num, const double *den, int64_t N,
                               hipStream_t st);
 hipError_t launch_axpy(double *y, double a, const double *x, int64_t N, hipStream_t st);
+// y += a[0] x, a on the device
+hipError_t launch_axpy_dev(double *y, const double *a, const double *x, int64_t N, hipStream_t st);
+// Fused CG step on a 2D grid (5-point operator in diag[0..4]): beta = rz / rz_old[0] with rz the
+// sum of kRedBlocks partials (stored to rz_new[0]; beta = 0 when first), pnew = z + beta pold,
+// x += alpha_prev[0] pold (skipped when first), q = A pnew, and *npq (<= kRedBlocks) partials of p.q.
+// z = 0.5 z1 + hb z2 when z2 is given, else z1.  pnew must not alias pold.
+hipError_t launch_cg_pq2d(int n0, int n1, const double *const *diag, const double *z1, const double *z2, double hb,
+                          const double *pold, double *pnew, double *q, double *x, const double *rz_part,
+                          double *rz_new, const double *rz_old, const double *alpha_prev, bool first,
+                          double *pq_part, int *npq, hipStream_t st);
+// r -= alpha q, alpha = rz[0] / (sum of npq partials); out[0] = p.q, out[1] = alpha,
+// out[2 .. 2 + kRedBlocks) = partials of r.r
+hipError_t launch_cg_r(double *r, const double *q, const double *rz, const double *pq_part, int npq, double *out,
+                       int64_t N, hipStream_t st);
 hipError_t launch_copy_scaled(double *y, const double *x, double a, int64_t N, hipStream_t st);
 hipError_t launch_residual(int dim, const int n[3], const double *const *diag, const double *f,
                            const double *x, double *r, hipStream_t st);

@@ -970,6 +970,247 @@ hipError_t launch_cg_update_p_red_zz(double *p, const double *z1, const double *
     return hipGetLastError();
 }
 
+// ------------------------------------------------ fused CG step, 5-point operator
+// Lane l takes lane l-1's value (lane 0: 0), or lane l+1's value (lane 63: 0):
+// DPP wave shifts, 32 bits at a time, all lanes active.
+__device__ __forceinline__ double from_lower_lane(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffff), 0x138, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x138, 0xf, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double from_upper_lane(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffff), 0x130, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x130, 0xf, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum of n partials in a fixed order by one wave (lane-strided, then an xor
+// butterfly); every lane of every wave obtains the same value, with no barrier.
+__device__ __forceinline__ double wave_sum_partials(const double *p, int n) {
+    double acc = 0.0;
+    for (int i = (int)(threadIdx.x & 63); i < n; i += 64) acc += p[i];
+    for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+    return acc;
+}
+
+template <int V>
+__device__ __forceinline__ void ldv(const double *__restrict__ a, int64_t P, double (&o)[V]) {
+    if constexpr (V == 2) {
+        const double2 t = *reinterpret_cast<const double2 *>(a + P);
+        o[0] = t.x;
+        o[1] = t.y;
+    } else {
+        o[0] = a[P];
+    }
+}
+template <int V> __device__ __forceinline__ void stv(double *__restrict__ a, int64_t P, const double (&v)[V]) {
+    if constexpr (V == 2)
+        *reinterpret_cast<double2 *>(a + P) = make_double2(v[0], v[1]);
+    else
+        a[P] = v[0];
+}
+
+// inputs of the new p on one row (z pieces, old p) and the operator row with x
+template <int V> struct CgRowIn {
+    double z1[V], z2[V], po[V];
+};
+template <int V> struct CgRowOp {
+    double d[5][V], x[V];
+};
+
+// One CG step on a 2D grid, fused over tiles of kCgRows rows by 256 V columns
+// (V = 2 columns per lane where rows are 16-byte aligned):
+//   beta = rz / rz_old (rz from its partials; 0 on the first step), p = z + beta p_old,
+//   x += alpha_prev p_old (the previous step's update, deferred), q = A p,
+//   and the block's partial of p.q.
+// z = zcomb(z1, z2, hb) in the split form of the symmetric preconditioner, else z1.
+// p goes to a second buffer, so every thread forms the new p of its neighbours
+// from their old p: inside a wave by lane shifts, the rows above and below slide
+// through registers (read two rows ahead), and the column beyond each side of
+// the wave is formed once per tile by a gather and handed out row by row.
+// The blocks of one XCD (blockIdx mod 8) take one contiguous range of tiles,
+// so vertically adjacent tiles, and their halo rows, share that XCD's L2.
+constexpr int kCgRows = 16;
+template <bool SPLIT, int V>
+__global__ void __launch_bounds__(256) k_cg_pq2d(int n0, int n1, int nbx, int ntiles, int tpb, DiagPtrs D,
+                                                 const double *__restrict__ z1, const double *__restrict__ z2,
+                                                 double hb, const double *__restrict__ pold, double *__restrict__ pnew,
+                                                 double *__restrict__ q, double *__restrict__ x, const double *rz_part,
+                                                 double *rz_new, const double *rz_old, const double *alpha_prev,
+                                                 int first, double *pq_part) {
+    __shared__ double sh[256];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const double rz = wave_sum_partials(rz_part, kRedBlocks);
+    if (blockIdx.x == 0 && threadIdx.x == 0) rz_new[0] = rz;
+    const double beta = first ? 0.0 : rz / rz_old[0];
+    const double alpha = first ? 0.0 : alpha_prev[0];
+    auto newp = [&](double a1, double a2, double po) {
+        const double z = SPLIT ? zcomb(a1, a2, hb) : a1;
+        return first ? z : __fma_rn(beta, po, z);
+    };
+    auto load_in = [&](CgRowIn<V> &r, int64_t P) {
+        ldv<V>(z1, P, r.z1);
+        if (SPLIT) ldv<V>(z2, P, r.z2);
+        if (!first) ldv<V>(pold, P, r.po);
+    };
+    auto load_op = [&](CgRowOp<V> &o, int64_t P) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) ldv<V>(D.d[k], P, o.d[k]);
+        if (!first) ldv<V>(x, P, o.x);
+    };
+    auto form = [&](const CgRowIn<V> &r, double (&o)[V]) {
+#pragma unroll
+        for (int c = 0; c < V; ++c) o[c] = newp(r.z1[c], SPLIT ? r.z2[c] : 0.0, first ? 0.0 : r.po[c]);
+    };
+    const int G = gridDim.x;
+    const int vb = (int)(blockIdx.x & 7) * (G >> 3) + (int)(blockIdx.x >> 3);
+    const int t0 = vb * tpb, t1 = min(t0 + tpb, ntiles);
+    double acc = 0.0;
+    for (int t = t0; t < t1; ++t) {
+        const int c0 = (t % nbx) * (256 * V) + wave * (64 * V); // the wave's first column
+        const int i = c0 + lane * V;
+        const int j0 = (t / nbx) * kCgRows, j1 = min(j0 + kCgRows, n1);
+        const bool in = i < n0;
+        const int ic = in ? i : 0; // loads of lanes beyond the grid read column 0 and are dropped
+        // new p on the columns beyond the wave's two sides, rows j0-1 .. j1: lanes 0.. left, 32.. right
+        double hn = 0.0;
+        {
+            const int hr = lane & 31, hrow = j0 - 1 + hr;
+            const int hcol = (lane >> 5) ? c0 + 64 * V : c0 - 1;
+            if (hr < j1 - j0 + 2 && hrow >= 0 && hrow < n1 && hcol >= 0 && hcol < n0) {
+                const int64_t H = (int64_t)hrow * n0 + hcol;
+                hn = newp(z1[H], SPLIT ? z2[H] : 0.0, first ? 0.0 : pold[H]);
+            }
+        }
+        double pm[V], pc[V], oc[V];
+        CgRowIn<V> ra, rb; // new-p inputs of rows j+1 and j+2
+        CgRowOp<V> oa, ob; // operator rows j and j+1
+        {
+            CgRowIn<V> r;
+            load_in(r, (int64_t)max(j0 - 1, 0) * n0 + ic);
+            form(r, pm);
+            load_in(r, (int64_t)j0 * n0 + ic);
+            form(r, pc);
+#pragma unroll
+            for (int c = 0; c < V; ++c) oc[c] = first ? 0.0 : r.po[c];
+        }
+        load_in(ra, (int64_t)min(j0 + 1, n1 - 1) * n0 + ic);
+        load_op(oa, (int64_t)j0 * n0 + ic);
+        for (int j = j0; j < j1; ++j) {
+            load_in(rb, (int64_t)min(j + 2, n1 - 1) * n0 + ic);
+            load_op(ob, (int64_t)min(j + 1, n1 - 1) * n0 + ic);
+            double pp[V];
+            form(ra, pp);
+            const double sl = from_lower_lane(pc[V - 1]), sr = from_upper_lane(pc[0]); // every lane takes part
+            const double h = __shfl(hn, (lane == 63 ? 32 : 0) + (j - j0 + 1), 64);
+            if (in) {
+                const int64_t P = (int64_t)j * n0 + i;
+                double qa[V], xn[V];
+#pragma unroll
+                for (int c = 0; c < V; ++c) {
+                    const double pl = c > 0 ? pc[c - 1] : (lane == 0 ? h : sl);
+                    const double pr = c < V - 1 ? pc[c + 1] : (lane == 63 ? h : sr);
+                    double a = oa.d[0][c] * pc[c];
+                    if (i + c > 0) a -= oa.d[1][c] * pl;
+                    if (i + c < n0 - 1) a -= oa.d[2][c] * pr;
+                    if (j > 0) a -= oa.d[3][c] * pm[c];
+                    if (j < n1 - 1) a -= oa.d[4][c] * pp[c];
+                    qa[c] = a;
+                    acc += pc[c] * a;
+                    xn[c] = first ? 0.0 : oa.x[c] + alpha * oc[c];
+                }
+                stv<V>(q, P, qa);
+                stv<V>(pnew, P, pc);
+                if (!first) stv<V>(x, P, xn);
+            }
+#pragma unroll
+            for (int c = 0; c < V; ++c) {
+                pm[c] = pc[c];
+                pc[c] = pp[c];
+                oc[c] = first ? 0.0 : ra.po[c];
+            }
+            ra = rb;
+            oa = ob;
+        }
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) pq_part[blockIdx.x] = s;
+}
+
+hipError_t launch_cg_pq2d(int n0, int n1, const double *const *diag, const double *z1, const double *z2, double hb,
+                          const double *pold, double *pnew, double *q, double *x, const double *rz_part,
+                          double *rz_new, const double *rz_old, const double *alpha_prev, bool first,
+                          double *pq_part, int *npq, hipStream_t st) {
+    DiagPtrs D{};
+    bool al = n0 % 2 == 0;
+    for (int k = 0; k < 5; ++k) {
+        D.d[k] = diag[k];
+        al = al && ((uintptr_t)diag[k] & 15) == 0;
+    }
+    for (const void *ptr : {(const void *)z1, (const void *)z2, (const void *)pold, (const void *)pnew,
+                            (const void *)q, (const void *)x})
+        al = al && ((uintptr_t)ptr & 15) == 0;
+    const int V = al ? 2 : 1;
+    const int nbx = (n0 + 256 * V - 1) / (256 * V), nby = (n1 + kCgRows - 1) / kCgRows;
+    const int ntiles = nbx * nby;
+    int grid = std::min(ntiles, kRedBlocks);
+    grid = (grid + 7) / 8 * 8; // at most kRedBlocks, a multiple of 8
+    *npq = grid;
+    const int tpb = (ntiles + grid - 1) / grid;
+#define PSW_CG_PQ(S, VV)                                                                                              \
+    hipLaunchKernelGGL((k_cg_pq2d<S, VV>), dim3(grid), dim3(256), 0, st, n0, n1, nbx, ntiles, tpb, D, z1, z2, hb,   \
+                       pold, pnew, q, x, rz_part, rz_new, rz_old, alpha_prev, (int)first, pq_part)
+    if (z2) {
+        if (V == 2) PSW_CG_PQ(true, 2); else PSW_CG_PQ(true, 1);
+    } else {
+        if (V == 2) PSW_CG_PQ(false, 2); else PSW_CG_PQ(false, 1);
+    }
+#undef PSW_CG_PQ
+    return hipGetLastError();
+}
+
+// r -= alpha q with alpha = rz / (sum of npq p.q partials); out[0] = p.q, out[1] = alpha,
+// out[2 + b] = block b's partial of r.r (kRedBlocks of them)
+__global__ void __launch_bounds__(kRedThreads) k_cg_r(double *r, const double *q, const double *rz,
+                                                     const double *pq_part, int npq, double *out, int64_t N) {
+    __shared__ double sh[kRedThreads];
+    const double pq = wave_sum_partials(pq_part, npq);
+    const double alpha = rz[0] / pq;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        out[0] = pq;
+        out[1] = alpha;
+    }
+    double acc = 0.0;
+    const int64_t stride = (int64_t)kRedBlocks * kRedThreads;
+    for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < N; i += stride) {
+        const double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        acc += ri * ri;
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[2 + blockIdx.x] = s;
+}
+
+hipError_t launch_cg_r(double *r, const double *q, const double *rz, const double *pq_part, int npq, double *out,
+                       int64_t N, hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_r, dim3(kRedBlocks), dim3(kRedThreads), 0, st, r, q, rz, pq_part, npq, out, N);
+    return hipGetLastError();
+}
+
+__global__ void k_axpy_dev(double *y, const double *a, const double *x, int64_t N) {
+    const double s = a[0];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] += s * x[i];
+}
+
+hipError_t launch_axpy_dev(double *y, const double *a, const double *x, int64_t N, hipStream_t st) {
+    hipLaunchKernelGGL(k_axpy_dev, dim3(grid_for(N)), dim3(256), 0, st, y, a, x, N);
+    return hipGetLastError();
+}
+
 __global__ void k_zcomb(double *z, const double *z1, const double *z2, double b, int64_t N) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
         z[i] = zcomb(z1[i], z2[i], b);

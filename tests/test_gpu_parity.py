@@ -205,6 +205,32 @@ def test_krylov_iterations_match_oracle(kind, dim, n, p):
     assert info["converged"] and abs(info["iters"] - it_gm) <= 1, (info, it_gm)
 
 
+@pytest.mark.parametrize("kind", ["none", "ssor", "ilu0"])
+@pytest.mark.parametrize("n,p", [((300, 37), (3, 2)), ((260, 70), (2, 4))])
+def test_cg_2d_ragged_strips_match_oracle(kind, n, p):
+    """The fused 2D CG step works on strips of 16 rows by 256 columns: grids with a ragged last
+    strip in both directions and more than one column band reach the oracle's iterate."""
+    pr, diags = _prob(2, n, seed=21)
+    Aop = lambda v: O.spmv(2, n, diags, v)
+    if kind == "none":
+        apply_m = lambda v: v.copy()
+    else:
+        apply_m = O.Precond(kind, 2, n, p, diags, omega=1.0).apply_sym
+    xr, it_ref, _ = O.cg(Aop, apply_m, pr["f"], rtol=1e-8)
+    g = make_problem(2, n, pr["alphas"])
+    g.set_relaxation([1.0])
+    g.set_decomposition(p, overlap=2)
+    import torch
+    f = to_dev(pr["f"])
+    u = torch.zeros(int(np.prod(n)), dtype=torch.float64, device=dev())
+    info = g.solve("cg", kind, f, u, rtol=1e-8)
+    # unpreconditioned CG runs hundreds of steps; rounding order may move the stop by a few
+    slack = 1 if kind != "none" else max(2, it_ref // 100)
+    assert info["converged"] and abs(info["iters"] - it_ref) <= slack, (info, it_ref)
+    assert info["relres"] <= 1e-8
+    assert np.linalg.norm(to_np(u) - xr) <= 1e-6 * np.linalg.norm(xr)
+
+
 @pytest.mark.parametrize("kind", ["ssor", "ilu0"])
 def test_full_size_varcoef_2048_half_sweeps(kind):
     """The benchmark workload at full size: 2048^2, 16x16 subdomains, overlap 4; every output point."""
