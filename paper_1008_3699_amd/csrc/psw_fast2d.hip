@@ -55,6 +55,9 @@ template <> __device__ __forceinline__ float cvt<float, double>(double v) { retu
 template <> __device__ __forceinline__ double cvt<double, float>(float v) { return (double)v; }
 template <> __device__ __forceinline__ float cvt<float, uint16_t>(uint16_t v) { return bf16f(v); }
 
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __fma_rn(a, b, c); }
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __fmaf_rn(a, b, c); }
+
 __device__ __forceinline__ int dkk(int a, int s) { return s < 0 ? 1 + 2 * a : 2 + 2 * a; }
 
 __device__ __forceinline__ int64_t lin2(int n0, int gx, int gy) { return (int64_t)gx + (int64_t)n0 * gy; }
@@ -621,8 +624,8 @@ __device__ __forceinline__ void fast2d_body(const Frame2 &F, int n0, const GP<TI
         }
     }
 
-    // one step; XF: some lane may be at x = 0
-    auto step = [&](const int s, const int k, const bool XF) {
+    // one step; XF: some lane may be at x = 0; so: offset of the slot read RING steps ahead
+    auto step = [&](const int s, const int k, const bool XF, const int so) {
         const int slot = k % RING, pk = k % kPf;
         const int x = s - lane;
         const T up_in = lane_up(last);
@@ -634,8 +637,10 @@ __device__ __forceinline__ void fast2d_body(const Frame2 &F, int n0, const GP<TI
 #pragma unroll
             for (int r = 0; r < R; ++r) rc[pk][r] = vt[rowa + r * pitch + xn];
         }
+        // read whether or not the y face is coupled (used only if it is): a branch here
+        // would split the unrolled interval into one block per step
         T yv = T(0);
-        if (CPL && cy) {
+        if (CPL) {
             yv = yf[pk];
             yf[pk] = yfix[min(s + kPf, lx - 1)];
         }
@@ -647,7 +652,9 @@ __device__ __forceinline__ void fast2d_body(const Frame2 &F, int n0, const GP<TI
             const T ax = elem<T>(ra[slot], r), ay = elem<T>(rb[slot], r);
             const T rhs = SC ? cur[r] : iv * cur[r];
             const T u = r == 0 ? up_in : v[r - 1];
-            T val = rhs + ax * left[r] + ay * u;
+            // fused multiply-adds written out, so that the rounding does not depend on how
+            // the compiler contracts the unrolled interval
+            T val = fmadd(ay, u, fmadd(ax, left[r], rhs));
             if (CPL && cy && r == 0) val = l0 ? yv : val;
             if (XF && cx) val = isx ? xf[r] : val;
             v[r] = val;
@@ -659,10 +666,12 @@ __device__ __forceinline__ void fast2d_body(const Frame2 &F, int n0, const GP<TI
         const int a = act ? rowa + x : sink + lane;
 #pragma unroll
         for (int r = 0; r < R; ++r) vt[a + r * pitch] = v[r];
-        const int so = tab[1 + s + RING];
         if (!SC) ri[slot] = ldbuf<V>(rinv, voff, so);
         ra[slot] = ldbuf<V>(rax, voff, so);
         rb[slot] = ldbuf<V>(ray, voff, so);
+        // keeps each step's loads in step order, so the ring's loads stay in flight across
+        // the interval's end instead of being drained by a wait at the loop head
+        __builtin_amdgcn_sched_barrier(0);
     };
 
     // helper waves: stage block i + 2, write back block i - lag
@@ -673,16 +682,33 @@ __device__ __forceinline__ void fast2d_body(const Frame2 &F, int n0, const GP<TI
     // Wave 0 and the helper waves run separate loops with one barrier per
     // interval each, so the recurrence state is not live in the helpers' code.
     if (wv == 0) {
+        // The slot offsets of an interval are read one interval ahead into scalar
+        // registers: a scalar load inside a step would make the step wait for it
+        // together with all LDS reads in flight (they share one counter).
+        int so_n[KB];
+        auto offsets = [&](int i) {
+#pragma unroll
+            for (int k = 0; k < KB; ++k) so_n[k] = tab[1 + i * KB + k + RING];
+        };
+        offsets(0);
         // intervals in which some lane meets the x face, then the rest
         const int nxf = (CPL && cx) ? min(niter, (L + KB - 1) / KB) : 0;
         for (int i = 0; i < nxf; ++i) {
+            int so[KB];
 #pragma unroll
-            for (int k = 0; k < KB; ++k) step(i * KB + k, k, CPL);
+            for (int k = 0; k < KB; ++k) so[k] = so_n[k];
+            offsets(i + 1);
+#pragma unroll
+            for (int k = 0; k < KB; ++k) step(i * KB + k, k, CPL, so[k]);
             __syncthreads();
         }
         for (int i = nxf; i < niter; ++i) {
+            int so[KB];
 #pragma unroll
-            for (int k = 0; k < KB; ++k) step(i * KB + k, k, false);
+            for (int k = 0; k < KB; ++k) so[k] = so_n[k];
+            offsets(i + 1);
+#pragma unroll
+            for (int k = 0; k < KB; ++k) step(i * KB + k, k, false, so[k]);
             __syncthreads();
         }
     } else {
