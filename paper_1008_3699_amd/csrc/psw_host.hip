@@ -131,6 +131,10 @@ struct PrecState {
     FastPassBuf fp[4];
     DevBuf toff, foff; // per tile: start of its packed coefficients / face records
     DevBuf otab, ooff; // step-offset tables and their per-tile starts
+    // 3D path with the tile in LDS (FP32 arithmetic): level-major packed coefficients
+    bool tile3 = false;
+    int len0max = 1;
+    DevBuf t3pk[4], t3off;
 };
 
 struct psw_problem {
@@ -310,6 +314,45 @@ psw_status fast_setup(psw_problem *P, PrecState &S, hipStream_t st) {
     return PSW_OK;
 }
 
+// 3D problems swept in FP32 whose tiles fit in LDS: pack the four passes' coefficients
+psw_status tile3_setup(psw_problem *P, PrecState &S, hipStream_t st) {
+    S.tile3 = false;
+    if (P->dim != 3 || P->prec == PSW_F64 || P->cmax > 1024) return PSW_OK;
+    const char *e = std::getenv("PSW_FORCE_GENERIC");
+    if (e && e[0] == '1') return PSW_OK;
+    std::vector<int> lo[3], len[3];
+    for (int a = 0; a < 3; ++a) partition(P->n[a], P->p[a], lo[a], len[a]);
+    const int len0max = *std::max_element(len[0].begin(), len[0].end());
+    int sig[3];
+    pass_sig(P, 0, sig);
+    if (tile3_lds_bytes(geom(P, sig), len0max, sizeof(float)) > P->lds_limit) return PSW_OK;
+    // slots per tile, in the tile order of the decomposition (x fastest)
+    std::vector<int64_t> off;
+    int64_t tot = 0;
+    for (int t = 0; t < P->p[2]; ++t)
+        for (int u = 0; u < P->p[1]; ++u)
+            for (int r = 0; r < P->p[0]; ++r) {
+                off.push_back(tot);
+                const int64_t C = (int64_t)len[1][u] * len[2][t];
+                tot += (int64_t)(len[0][r] + len[1][u] + len[2][t] - 2) * C;
+            }
+    if ((int)off.size() != P->ntiles) return PSW_EINVAL;
+    const Store s = store_of(P->prec);
+    if (!S.t3off.ensure(sizeof(int64_t) * off.size())) return PSW_ENOMEM;
+    HIPCHK(hipMemcpy(S.t3off.p, off.data(), sizeof(int64_t) * off.size(), hipMemcpyHostToDevice));
+    const double *d[7];
+    diag64(P, d);
+    for (int w = 0; w < 4; ++w) {
+        if (!S.t3pk[w].ensure(pack3_slot_bytes(s) * (size_t)tot)) return PSW_ENOMEM;
+        pass_sig(P, w, sig);
+        HIPCHK(launch_pack3(geom(P, sig), s, w >= 2, d, S.piv64.as<double>(), S.t3off.as<int64_t>(), S.t3pk[w].p,
+                            st));
+    }
+    S.len0max = len0max;
+    S.tile3 = true;
+    return PSW_OK;
+}
+
 // preconditioner state for kind (SSOR: Piv = D/w, c = 2-w; ILU0: Piv = D~, c = 1)
 psw_status precond_setup(psw_problem *P, psw_precond kind, hipStream_t st) {
     if (kind != PSW_SSOR && kind != PSW_ILU0) return PSW_EINVAL;
@@ -346,6 +389,7 @@ psw_status precond_setup(psw_problem *P, psw_precond kind, hipStream_t st) {
     }
     HIPCHK(launch_convert(S.piv64.as<double>(), S.piv.p, s, P->N, 1.0, st));
     if ((ps = fast_setup(P, S, st))) return ps;
+    if ((ps = tile3_setup(P, S, st))) return ps;
     S.ready = true;
     return PSW_OK;
 }
@@ -415,6 +459,12 @@ psw_status half(psw_problem *P, psw_precond kind, int which, const void *in, boo
         psw_status ps = fast_pass(P, kind, which, in, in_f64, scale_by_piv, out, out_f64, cscale, nullptr, 0.0, st);
         if (ps || which <= 1) return ps;
         return fast_end(P, kind, which, in, in_f64, scale_by_piv, out, out_f64, st);
+    }
+    if (S.tile3) {
+        HIPCHK(launch_tile3(g, s, which <= 1, d, S.piv.p, S.t3pk[which].p, S.t3off.as<int64_t>(), S.len0max, in,
+                            in_f64, scale_by_piv, out, out_f64, which <= 1 ? cscale : 1.0, st));
+        if (which >= 2) HIPCHK(launch_end_fixups3(g, s, d, S.piv.p, in, in_f64, scale_by_piv, out, out_f64, st));
+        return PSW_OK;
     }
     if (which <= 1)
         HIPCHK(launch_half_start(g, s, d, S.piv.p, in, in_f64, scale_by_piv, out, out_f64, cscale, st));

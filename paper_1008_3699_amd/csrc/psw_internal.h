@@ -53,6 +53,21 @@ hipError_t launch_half_end(const PassGeom &g, Store s, const void *const *diag, 
                            const void *in, bool in_f64, bool scale_by_piv, void *out, bool out_f64,
                            hipStream_t st);
 
+// 3D half-sweeps with the whole tile in LDS (FP32 arithmetic; FP32 or BF16 storage).
+// Packed coefficients per pass: pack3_slot_bytes(s) per slot, level-major per tile,
+// (len0 + len1 + len2 - 2) * len1 * len2 slots from poff[tile].
+size_t pack3_slot_bytes(Store s);
+size_t tile3_lds_bytes(const PassGeom &g, int len0max, size_t elem);
+hipError_t launch_pack3(const PassGeom &g, Store s, bool transposed, const double *const *diag, const double *piv,
+                        const int64_t *poff, void *pk, hipStream_t st);
+// start: the start-coupled pass (out = cscale * result); else the interior of an
+// end-coupled pass, to be followed by launch_end_fixups3
+hipError_t launch_tile3(const PassGeom &g, Store s, bool start, const void *const *diag, const void *piv,
+                        const void *pk, const int64_t *poff, int len0max, const void *in, bool in_f64,
+                        bool scale_by_piv, void *out, bool out_f64, double cscale, hipStream_t st);
+hipError_t launch_end_fixups3(const PassGeom &g, Store s, const void *const *diag, const void *piv, const void *in,
+                              bool in_f64, bool scale_by_piv, void *out, bool out_f64, hipStream_t st);
+
 // ILU(0) pivots of the decomposed factorisation, FP64.
 hipError_t launch_ilu_pivots(const PassGeom &g, const double *const *diag, double *piv, int *bad,
                              hipStream_t st);

@@ -616,11 +616,16 @@ static hipError_t end_part_impl(const PassGeom &g, const void *const *diag, cons
         dim3 grid(g.ntiles), blk(block_threads(g));
         if (g.dim == 2) hipLaunchKernelGGL((k_sweep_end_interior<2, T, S, TIN, TOUT>), grid, blk, sm, st, A);
         else hipLaunchKernelGGL((k_sweep_end_interior<3, T, S, TIN, TOUT>), grid, blk, sm, st, A);
-    } else {
+    } else if (part == 1) {
         if (g.dim == 2)
             hipLaunchKernelGGL((k_end_corners<2, T, S, TIN, TOUT>), dim3((g.ntiles + 63) / 64), dim3(64), 0, st, A);
         else
             hipLaunchKernelGGL((k_end_corners<3, T, S, TIN, TOUT>), dim3((g.ntiles + 63) / 64), dim3(64), 0, st, A);
+    } else {
+        if (g.dim != 3) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_end_faces<3, T, S, TIN, TOUT>), dim3(g.ntiles * 3), dim3(64), 0, st, A);
+        hipLaunchKernelGGL((k_end_edges<T, S, TIN, TOUT>), dim3((g.ntiles * 3 + 63) / 64), dim3(64), 0, st, A);
+        hipLaunchKernelGGL((k_end_corners<3, T, S, TIN, TOUT>), dim3((g.ntiles + 63) / 64), dim3(64), 0, st, A);
     }
     return hipGetLastError();
 }
@@ -1290,6 +1295,302 @@ hipError_t launch_multi_dot(const double *V, const double *w, int k, int64_t N, 
     hipLaunchKernelGGL(k_multi_dot_partial, dim3(kRedBlocks, k), dim3(kRedThreads), 0, st, V, w, N, partials);
     hipLaunchKernelGGL(k_dot_final, dim3(k), dim3(kRedThreads), 0, st, partials, out);
     return hipGetLastError();
+}
+
+
+// ------------------------------------------------------------------ 3D half-sweeps with the tile in LDS
+// For FP32 arithmetic (FP32 or BF16 storage) a whole 3D tile fits in LDS.  The
+// workgroup stages the tile's input with row loads along x, sweeps it level by
+// level (level t = l0 + l1 + l2 in local orientation, one barrier per level)
+// with the results written in place, and writes the tile back with row stores.
+// Thread c owns pencil c = l1 + L1 l2 and handles l0 = t - l1 - l2 at level t;
+// its upstream neighbours sit at -1, -pitch and -pitch L1 in the pencil-major
+// LDS tile.  Coefficients come packed per pass in level-major order, slot
+// t C + c, so that one level's loads are contiguous: 1/Piv and the three
+// upstream couplings divided by Piv, in the storage precision, read PD levels
+// ahead.  Start-coupled passes solve the coupled blocks at the start faces
+// (2x2 on faces, 4x4 on edges, 8x8 at the corner) as the generic kernel does,
+// with the partners' values in LDS rings.
+template <typename S> struct alignas(4 * sizeof(S)) Pk3 {
+    S inv, c0, c1, c2;
+};
+
+__host__ __device__ __forceinline__ int tile3_pitch(int len0) { return len0 + (len0 & 1); } // pitch - 1 odd
+
+size_t tile3_lds_bytes(const PassGeom &g, int len0max, size_t elem) {
+    return elem * ((size_t)tile3_pitch(len0max) * g.cmax + 2 * (size_t)g.cmax + 4 * (size_t)g.l2max +
+                   4 * (size_t)g.l1max + 2);
+}
+
+__device__ __forceinline__ float s2f(float v) { return v; }
+__device__ __forceinline__ float s2f(uint16_t v) { return bf16_to_f32(v); }
+template <typename S> __device__ __forceinline__ S f2s(double v);
+template <> __device__ __forceinline__ float f2s<float>(double v) { return (float)v; }
+template <> __device__ __forceinline__ uint16_t f2s<uint16_t>(double v) { return f64_to_bf16(v); }
+
+// packed coefficients of one pass; transposed: couplings of the upstream
+// neighbour towards the point (end-coupled passes), else of the point towards it
+template <typename S>
+__global__ void __launch_bounds__(256) k_pack3(PassGeom g, int transposed, DiagPtrs dg, const double *piv,
+                                               const int64_t *poff, Pk3<S> *pk) {
+    const TileDesc td = g.tiles[blockIdx.x];
+    const TileFrame F = make_frame<3>(g, td);
+    const int len0 = F.len[0], L1 = F.len[1], L2 = F.len[2], C = L1 * L2;
+    Pk3<S> *out = pk + poff[blockIdx.x];
+    for (int e = threadIdx.x; e < len0 * C; e += blockDim.x) {
+        const int l0 = e % len0, c = e / len0;
+        const int l[3] = {l0, c % L1, c / L1};
+        int gp[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) gp[a] = F.base[a] + F.d[a] * l[a];
+        const int64_t P = lin(g.n, gp);
+        const double inv = 1.0 / piv[P];
+        double cf[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cf[a] = 0.0;
+            if (l[a] > 0) {
+                if (transposed) {
+                    int r[3] = {gp[0], gp[1], gp[2]};
+                    r[a] -= F.d[a];
+                    cf[a] = dg.d[dk(a, F.d[a])][lin(g.n, r)] * inv;
+                } else {
+                    cf[a] = dg.d[dk(a, -F.d[a])][P] * inv;
+                }
+            }
+        }
+        Pk3<S> v;
+        v.inv = f2s<S>(inv);
+        v.c0 = f2s<S>(cf[0]);
+        v.c1 = f2s<S>(cf[1]);
+        v.c2 = f2s<S>(cf[2]);
+        out[(int64_t)(l[0] + l[1] + l[2]) * C + c] = v;
+    }
+}
+
+template <typename S, typename TIN, typename TOUT> struct Tile3Args {
+    PassGeom g;
+    const S *diag[7];
+    const S *piv;
+    const Pk3<S> *pk;
+    const int64_t *poff;
+    const TIN *in;
+    int scale_by_piv;
+    TOUT *out;
+    double cscale;
+    int len0max;
+};
+
+constexpr int kTile3Pd = 8; // levels by which the packed coefficients are read ahead
+
+template <typename T, typename S, typename TIN, typename TOUT, bool CPL>
+__global__ void __launch_bounds__(1024) k_tile3(Tile3Args<S, TIN, TOUT> A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const PassGeom &g = A.g;
+    const TileDesc td = g.tiles[blockIdx.x];
+    const TileFrame F = make_frame<3>(g, td);
+    const int len0 = F.len[0], L1 = F.len[1], L2 = F.len[2];
+    const int C = L1 * L2;
+    const int nlev = len0 + L1 + L2 - 2;
+    const int pitch = tile3_pitch(len0);
+    T *own = reinterpret_cast<T *>(smem);
+    Rings<T> rg;
+    {
+        T *p = own + (size_t)tile3_pitch(A.len0max) * g.cmax;
+        rg.cmax = g.cmax;
+        rg.l1max = g.l1max;
+        rg.l2max = g.l2max;
+        rg.own = nullptr; // own values live in the tile
+        rg.xp = p; p += 2 * g.cmax;
+        rg.yp = p; p += 2 * g.l2max;
+        rg.zp = p; p += 2 * g.l1max;
+        rg.xyp = p; p += 2 * g.l2max;
+        rg.xzp = p; p += 2 * g.l1max;
+        rg.yzp = p;
+    }
+    const int nth = blockDim.x;
+    const int np = len0 * C;
+    for (int e = threadIdx.x; e < np; e += nth) {
+        const int l0 = e % len0, c = e / len0;
+        const int gp[3] = {F.base[0] + F.d[0] * l0, F.base[1] + F.d[1] * (c % L1), F.base[2] + F.d[2] * (c / L1)};
+        own[c * pitch + l0] = ldv<T>(A.in, lin(g.n, gp));
+    }
+    __syncthreads();
+
+    const int c = threadIdx.x;
+    const bool have = c < C;
+    const int l1 = have ? c % L1 : 0, l2 = have ? c / L1 : 0;
+    const Pk3<S> *pk = A.pk + A.poff[blockIdx.x] + (have ? c : 0); // threads beyond the tile read slot 0
+    const bool scale = A.scale_by_piv != 0;
+    constexpr int PD = kTile3Pd;
+    // The ring's loads are unconditional and each slot is reloaded after its last use in the
+    // level, so the slot keeps its registers and no wait is needed before the level's barrier.
+    Pk3<S> ring[PD];
+#pragma unroll
+    for (int k = 0; k < PD; ++k) ring[k] = pk[(int64_t)min(k, nlev - 1) * C];
+    for (int t0 = 0; t0 < nlev; t0 += PD) {
+#pragma unroll
+        for (int k = 0; k < PD; ++k) {
+            const int t = t0 + k;
+            if (t < nlev) {
+                const Pk3<S> &cf = ring[k];
+                const int l0 = t - l1 - l2;
+                if (have && l0 >= 0 && l0 < len0) {
+                    int Am = 0;
+                    if (CPL) {
+                        if (l0 == 0 && F.start_cpl[0]) Am |= 1;
+                        if (l1 == 0 && F.start_cpl[1]) Am |= 2;
+                        if (l2 == 0 && F.start_cpl[2]) Am |= 4;
+                    }
+                    const int o = c * pitch + l0;
+                    if (Am == 0) {
+                        T acc = own[o];
+                        if (!scale) acc *= s2f(cf.inv);
+                        if (l0 > 0) acc = __fmaf_rn(s2f(cf.c0), own[o - 1], acc);
+                        if (l1 > 0) acc = __fmaf_rn(s2f(cf.c1), own[o - pitch], acc);
+                        if (l2 > 0) acc = __fmaf_rn(s2f(cf.c2), own[o - pitch * L1], acc);
+                        own[o] = acc;
+                    } else if (CPL) {
+                        // coupled block: own point plus partners across the coupled start faces
+                        const int cur = t & 1, prv = cur ^ 1;
+                        const int l[3] = {l0, l1, l2};
+                        int gp[3];
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) gp[a] = F.base[a] + F.d[a] * l[a];
+                        T M[8][8], R[8];
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) {
+                            R[i] = T(0);
+#pragma unroll
+                            for (int j = 0; j < 8; ++j) M[i][j] = (i == j) ? T(1) : T(0);
+                        }
+#pragma unroll
+                        for (int B = 0; B < 8; ++B) {
+                            if (B & ~Am) continue;
+                            int gq[3], dq[3];
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) {
+                                const bool fl = (B >> a) & 1;
+                                gq[a] = gp[a] - (fl ? F.d[a] : 0);
+                                dq[a] = fl ? -F.d[a] : F.d[a];
+                            }
+                            const int64_t Q = lin(g.n, gq);
+                            const T D = ldv<T>(A.piv, Q);
+                            const T sc = T(1) / D;
+                            T acc = ldv<T>(A.in, Q);
+                            if (scale) acc *= D;
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) {
+                                const int su = -dq[a];
+                                int q[3] = {gq[0], gq[1], gq[2]};
+                                q[a] += su;
+                                if (q[a] >= 0 && q[a] < g.n[a]) {
+                                    const T coef = ldv<T>(A.diag[dk(a, su)], Q);
+                                    if ((Am >> a) & 1) {
+                                        M[B][B ^ (1 << a)] -= sc * coef;
+                                    } else {
+                                        // B = 0: the own upstream neighbour (inside the tile, l[a] > 0)
+                                        const T v = B == 0 ? own[o - (a == 0 ? 1 : (a == 1 ? pitch : pitch * L1))]
+                                                           : *rg.slot(B, prv, l1 - (a == 1), l2 - (a == 2), L1);
+                                        acc += coef * v;
+                                    }
+                                }
+                            }
+                            R[B] = sc * acc;
+                        }
+                        if ((Am & (Am - 1)) == 0) {
+                            const int b = Am;
+                            const T det = T(1) - M[0][b] * M[b][0];
+                            const T x0 = (R[0] - M[0][b] * R[b]) / det;
+                            const T x1 = (R[b] - M[b][0] * R[0]) / det;
+                            R[0] = x0;
+                            R[b] = x1;
+                        } else {
+                            ge_solve<T, 8>(M, R);
+                        }
+                        own[o] = R[0];
+#pragma unroll
+                        for (int B = 1; B < 7; ++B)
+                            if (!(B & ~Am)) *rg.slot(B, cur, l1, l2, L1) = R[B];
+                    }
+                }
+                ring[k] = pk[(int64_t)min(t + PD, nlev - 1) * C];
+                __syncthreads();
+            }
+        }
+    }
+    const T cs = (T)A.cscale;
+    for (int e = threadIdx.x; e < np; e += nth) {
+        const int l0 = e % len0, c2 = e / len0;
+        const int gp[3] = {F.base[0] + F.d[0] * l0, F.base[1] + F.d[1] * (c2 % L1), F.base[2] + F.d[2] * (c2 / L1)};
+        A.out[lin(g.n, gp)] = (TOUT)(cs * own[c2 * pitch + l0]);
+    }
+}
+
+hipError_t launch_pack3(const PassGeom &g, Store s, bool transposed, const double *const *diag, const double *piv,
+                        const int64_t *poff, void *pk, hipStream_t st) {
+    if (g.dim != 3 || s == Store::F64) return hipErrorInvalidValue;
+    DiagPtrs D{};
+    for (int k = 0; k < 7; ++k) D.d[k] = diag[k];
+    if (s == Store::F32)
+        hipLaunchKernelGGL(k_pack3<float>, dim3(g.ntiles), dim3(256), 0, st, g, (int)transposed, D, piv, poff,
+                           (Pk3<float> *)pk);
+    else
+        hipLaunchKernelGGL(k_pack3<uint16_t>, dim3(g.ntiles), dim3(256), 0, st, g, (int)transposed, D, piv, poff,
+                           (Pk3<uint16_t> *)pk);
+    return hipGetLastError();
+}
+
+size_t pack3_slot_bytes(Store s) { return s == Store::F32 ? sizeof(Pk3<float>) : sizeof(Pk3<uint16_t>); }
+
+template <typename S, typename TIN, typename TOUT>
+static hipError_t tile3_impl(const PassGeom &g, bool start, const void *const *diag, const void *piv, const void *pk,
+                             const int64_t *poff, int len0max, const void *in, bool scale_by_piv, void *out,
+                             double cscale, hipStream_t st) {
+    Tile3Args<S, TIN, TOUT> A{};
+    A.g = g;
+    for (int k = 0; k < 7; ++k) A.diag[k] = (const S *)diag[k];
+    A.piv = (const S *)piv;
+    A.pk = (const Pk3<S> *)pk;
+    A.poff = poff;
+    A.in = (const TIN *)in;
+    A.scale_by_piv = scale_by_piv ? 1 : 0;
+    A.out = (TOUT *)out;
+    A.cscale = cscale;
+    A.len0max = len0max;
+    if (g.cmax > 1024) return hipErrorInvalidValue;
+    const int nth = std::max(64, (g.cmax + 63) / 64 * 64);
+    const size_t sm = tile3_lds_bytes(g, len0max, sizeof(float));
+    if (start)
+        hipLaunchKernelGGL((k_tile3<float, S, TIN, TOUT, true>), dim3(g.ntiles), dim3(nth), sm, st, A);
+    else
+        hipLaunchKernelGGL((k_tile3<float, S, TIN, TOUT, false>), dim3(g.ntiles), dim3(nth), sm, st, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile3(const PassGeom &g, Store s, bool start, const void *const *diag, const void *piv,
+                        const void *pk, const int64_t *poff, int len0max, const void *in, bool in_f64,
+                        bool scale_by_piv, void *out, bool out_f64, double cscale, hipStream_t st) {
+    if (g.dim != 3 || s == Store::F64) return hipErrorInvalidValue;
+#define PSW_T3(S, TIN, TOUT) \
+    tile3_impl<S, TIN, TOUT>(g, start, diag, piv, pk, poff, len0max, in, scale_by_piv, out, cscale, st)
+    if (s == Store::F32) {
+        if (in_f64 && !out_f64) return PSW_T3(float, double, float);
+        if (!in_f64 && out_f64) return PSW_T3(float, float, double);
+        if (in_f64 && out_f64) return PSW_T3(float, double, double);
+        return PSW_T3(float, float, float);
+    }
+    if (in_f64 && !out_f64) return PSW_T3(uint16_t, double, float);
+    if (!in_f64 && out_f64) return PSW_T3(uint16_t, float, double);
+    if (in_f64 && out_f64) return PSW_T3(uint16_t, double, double);
+    return PSW_T3(uint16_t, float, float);
+#undef PSW_T3
+}
+
+// the coupled end faces, edges and corners of an end-coupled 3D pass (after its interior)
+hipError_t launch_end_fixups3(const PassGeom &g, Store s, const void *const *diag, const void *piv, const void *in,
+                              bool in_f64, bool scale_by_piv, void *out, bool out_f64, hipStream_t st) {
+    return end_part(g, s, diag, piv, in, in_f64, scale_by_piv, out, out_f64, 2, st);
 }
 
 } // namespace psw

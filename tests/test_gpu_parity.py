@@ -149,8 +149,6 @@ def test_spmv_and_dot(dim, n):
 @pytest.mark.parametrize("prec,bound", [("f32", 1e-5), ("bf16", 3e-2)])
 @pytest.mark.parametrize("dim,n,p", [(2, (40, 36), (4, 3)), (2, (260, 200), (2, 2)), (3, (12, 10, 9), (2, 2, 3))])
 def test_precond_mixed_precision_error(prec, bound, dim, n, p, path):
-    if dim == 3 and path == "pipelined":
-        pytest.skip("3D problems use the generic kernels only")
     pr, diags = _prob(dim, n, seed=17)
     g = make_problem(dim, n, pr["alphas"], prec=prec)
     g.set_relaxation([1.0])
@@ -164,6 +162,54 @@ def test_precond_mixed_precision_error(prec, bound, dim, n, p, path):
             ref = pc.apply_sym(pr["f"]) if sym else pc.apply(pr["f"])
             err = np.linalg.norm(to_np(z) - ref) / np.linalg.norm(ref)
             assert err <= bound, (kind, sym, err)
+
+
+TILE3_CASES = [((12, 10, 9), (2, 2, 3)), ((9, 9, 9), (1, 1, 1)), ((17, 13, 11), (3, 2, 2)), ((16, 8, 6), (4, 2, 3)),
+               ((40, 32, 32), (2, 1, 1))]
+
+
+@pytest.mark.parametrize("prec,bound", [("f32", 2e-6), ("bf16", 2e-2)])
+@pytest.mark.parametrize("n,p", TILE3_CASES)
+def test_tile3_half_sweeps(prec, bound, n, p, monkeypatch):
+    """3D passes with the whole tile in LDS (FP32 arithmetic): every pass against the FP64 oracle, and
+    against the generic level kernels in the same precision.  Ragged tiles, a single tile, and tiles of
+    20 x 32 x 32 points (the largest cross-section, 1024 pencils, that one workgroup holds)."""
+    import torch
+    dim = 3
+    pr, diags = _prob(dim, n, seed=31)
+    outs = {}
+    for mode in ("tile", "generic"):
+        if mode == "generic":
+            monkeypatch.setenv("PSW_FORCE_GENERIC", "1")
+        else:
+            monkeypatch.delenv("PSW_FORCE_GENERIC", raising=False)
+        g = make_problem(dim, n, pr["alphas"], prec=prec)
+        g.set_relaxation([1.2])
+        g.set_decomposition(p, overlap=2, phase=0)
+        for kind in ("ssor", "ilu0"):
+            out = torch.empty(int(np.prod(n)), dtype=torch.float64, device=dev())
+            inputs = {0: pr["f"], 1: pr["u"], 2: pr["f"], 3: pr["u"]}
+            for which in range(4):
+                g.precond_half(kind, which, to_dev(inputs[which]), out)
+                outs[(mode, kind, which)] = to_np(out)
+            z = torch.empty_like(out)
+            g.precond_apply(kind, to_dev(pr["f"]), z, symmetric=True)
+            outs[(mode, kind, "sym")] = to_np(z)
+    for kind in ("ssor", "ilu0"):
+        pc = O.Precond(kind, dim, n, p, diags, omega=1.2)
+        refs = {
+            0: pc.forward(pr["f"]),
+            1: pc.backward(pr["u"]),
+            2: O.dsolve_t(dim, n, p, pc.dirs_b, diags, pc.piv, pr["f"]),
+            3: pc.c * O.dsolve_t(dim, n, p, pc.dirs_f, diags, pc.piv, pc.piv * pr["u"]),
+            "sym": pc.apply_sym(pr["f"]),
+        }
+        for which, ref in refs.items():
+            a, b = outs[("tile", kind, which)], outs[("generic", kind, which)]
+            err = np.linalg.norm(a - ref) / np.linalg.norm(ref)
+            print(f"{kind} {which}: tile {err:.2e} generic {np.linalg.norm(b - ref) / np.linalg.norm(ref):.2e}", flush=True)
+            assert err <= bound, (kind, which, err)
+            assert np.linalg.norm(a - b) / np.linalg.norm(ref) <= 2 * bound, (kind, which)
 
 
 def test_stationary_solve_poisson_64():
