@@ -94,6 +94,24 @@ __device__ __forceinline__ void ge_solve(T (&M)[NB][NB], T (&R)[NB]) {
     }
 }
 
+// The 2x2 block on rows / columns {0, b} of an NB x NB system (b a single bit, the
+// one coupled face of the point), with compile-time indices so that M and R stay in
+// registers (a runtime index would put them in scratch memory).
+template <typename T, int NB, int B>
+__device__ __forceinline__ void solve2_at(T (&M)[NB][NB], T (&R)[NB]) {
+    const T det = T(1) - M[0][B] * M[B][0];
+    const T x0 = (R[0] - M[0][B] * R[B]) / det;
+    const T x1 = (R[B] - M[B][0] * R[0]) / det;
+    R[0] = x0;
+    R[B] = x1;
+}
+template <typename T, int NB>
+__device__ __forceinline__ void solve2(T (&M)[NB][NB], T (&R)[NB], int b) {
+    if (b == 1) solve2_at<T, NB, 1>(M, R);
+    else if (NB > 2 && b == 2) solve2_at<T, NB, (NB > 2 ? 2 : 1)>(M, R);
+    else if (NB > 4 && b == 4) solve2_at<T, NB, (NB > 4 ? 4 : 1)>(M, R);
+}
+
 // LDS slot rings: one double-buffered slot per (block type B, position).
 // B is the set of start-face axes a point was shifted across (0 = own point).
 template <typename T> struct Rings {
@@ -145,6 +163,7 @@ template <typename S, typename TIN, typename TOUT> struct StartArgs {
     int scale_by_piv;
     TOUT *out;
     double cscale;
+    int faces_only; // solve only the coupled blocks at the start faces (they involve no interior point)
 };
 
 template <int DIM, typename T, typename S, typename TIN, typename TOUT, bool STAT>
@@ -156,7 +175,15 @@ __global__ void __launch_bounds__(256) k_sweep_start(StartArgs<S, TIN, TOUT> A) 
     Rings<T> rg = make_rings<T>(smem, g);
     const int L1 = F.len[1], L2 = F.len[2];
     const int C = L1 * L2;
-    const int nlev = F.len[0] + F.len[1] + F.len[2] - 2;
+    int nlev = F.len[0] + F.len[1] + F.len[2] - 2;
+    if (!STAT && A.faces_only) {
+        // the last level holding a point of a coupled start face (l_a = 0): len_b + len_c - 2
+        int m = -1;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+            if (F.start_cpl[a]) m = max(m, F.len[0] + F.len[1] + F.len[2] - F.len[a] - 2);
+        nlev = m + 1;
+    }
     constexpr int NB = 1 << DIM;
 
     for (int t = 0; t < nlev; ++t) {
@@ -174,6 +201,7 @@ __global__ void __launch_bounds__(256) k_sweep_start(StartArgs<S, TIN, TOUT> A) 
                 if (l[a] == 0 && F.start_cpl[a]) Am |= 1 << a;
 
             if (Am == 0) {
+                if (!STAT && A.faces_only) continue;
                 // interior point: single update
                 const int64_t P = lin(g.n, gp);
                 int corner = 0;
@@ -253,12 +281,7 @@ __global__ void __launch_bounds__(256) k_sweep_start(StartArgs<S, TIN, TOUT> A) 
                 }
                 if ((Am & (Am - 1)) == 0) {
                     // 2x2 (eq. 1d:sorc / eq. 2d:sor2b2)
-                    const int b = Am;
-                    T det = T(1) - M[0][b] * M[b][0];
-                    T x0 = (R[0] - M[0][b] * R[b]) / det;
-                    T x1 = (R[b] - M[b][0] * R[0]) / det;
-                    R[0] = x0;
-                    R[b] = x1;
+                    solve2<T, NB>(M, R, Am);
                 } else {
                     ge_solve<T, NB>(M, R);
                 }
@@ -384,12 +407,7 @@ __device__ void end_block(const EndArgs<S, TIN, TOUT> &A, const int gp[3], const
         R[B] = acc / D;
     }
     if ((Am & (Am - 1)) == 0) {
-        const int b = Am;
-        T det = T(1) - M[0][b] * M[b][0];
-        T x0 = (R[0] - M[0][b] * R[b]) / det;
-        T x1 = (R[b] - M[b][0] * R[0]) / det;
-        R[0] = x0;
-        R[b] = x1;
+        solve2<T, NB>(M, R, Am);
     } else {
         ge_solve<T, NB>(M, R);
     }
@@ -556,8 +574,9 @@ hipError_t launch_sweep_stationary(const PassGeom &g, const double *const *diag,
 
 template <typename T, typename S, typename TIN, typename TOUT>
 static hipError_t start_impl(const PassGeom &g, const void *const *diag, const void *piv, const void *in,
-                             bool scale_by_piv, void *out, double cscale, hipStream_t st) {
+                             bool scale_by_piv, void *out, double cscale, hipStream_t st, bool faces_only = false) {
     StartArgs<S, TIN, TOUT> A{};
+    A.faces_only = faces_only ? 1 : 0;
     A.g = g;
     for (int k = 0; k < 2 * g.dim + 1; ++k) A.diag[k] = (const S *)diag[k];
     A.piv = (const S *)piv;
@@ -1318,8 +1337,7 @@ template <typename S> struct alignas(4 * sizeof(S)) Pk3 {
 __host__ __device__ __forceinline__ int tile3_pitch(int len0) { return len0 + (len0 & 1); } // pitch - 1 odd
 
 size_t tile3_lds_bytes(const PassGeom &g, int len0max, size_t elem) {
-    return elem * ((size_t)tile3_pitch(len0max) * g.cmax + 2 * (size_t)g.cmax + 4 * (size_t)g.l2max +
-                   4 * (size_t)g.l1max + 2);
+    return elem * (size_t)tile3_pitch(len0max) * g.cmax;
 }
 
 __device__ __forceinline__ float s2f(float v) { return v; }
@@ -1394,26 +1412,17 @@ __global__ void __launch_bounds__(1024) k_tile3(Tile3Args<S, TIN, TOUT> A) {
     const int nlev = len0 + L1 + L2 - 2;
     const int pitch = tile3_pitch(len0);
     T *own = reinterpret_cast<T *>(smem);
-    Rings<T> rg;
-    {
-        T *p = own + (size_t)tile3_pitch(A.len0max) * g.cmax;
-        rg.cmax = g.cmax;
-        rg.l1max = g.l1max;
-        rg.l2max = g.l2max;
-        rg.own = nullptr; // own values live in the tile
-        rg.xp = p; p += 2 * g.cmax;
-        rg.yp = p; p += 2 * g.l2max;
-        rg.zp = p; p += 2 * g.l1max;
-        rg.xyp = p; p += 2 * g.l2max;
-        rg.xzp = p; p += 2 * g.l1max;
-        rg.yzp = p;
-    }
     const int nth = blockDim.x;
     const int np = len0 * C;
+    // the input, and for a start-coupled pass the values of the coupled start-face points,
+    // which the level kernel has already solved into out (unscaled)
     for (int e = threadIdx.x; e < np; e += nth) {
-        const int l0 = e % len0, c = e / len0;
-        const int gp[3] = {F.base[0] + F.d[0] * l0, F.base[1] + F.d[1] * (c % L1), F.base[2] + F.d[2] * (c / L1)};
-        own[c * pitch + l0] = ldv<T>(A.in, lin(g.n, gp));
+        const int l0 = e % len0, c = e / len0, l1 = c % L1, l2 = c / L1;
+        const int gp[3] = {F.base[0] + F.d[0] * l0, F.base[1] + F.d[1] * l1, F.base[2] + F.d[2] * l2};
+        const bool face = CPL && ((l0 == 0 && F.start_cpl[0]) || (l1 == 0 && F.start_cpl[1]) ||
+                                  (l2 == 0 && F.start_cpl[2]));
+        const int64_t P = lin(g.n, gp);
+        own[c * pitch + l0] = face ? ldv<T>((const TOUT *)A.out, P) : ldv<T>(A.in, P);
     }
     __syncthreads();
 
@@ -1450,68 +1459,6 @@ __global__ void __launch_bounds__(1024) k_tile3(Tile3Args<S, TIN, TOUT> A) {
                         if (l1 > 0) acc = __fmaf_rn(s2f(cf.c1), own[o - pitch], acc);
                         if (l2 > 0) acc = __fmaf_rn(s2f(cf.c2), own[o - pitch * L1], acc);
                         own[o] = acc;
-                    } else if (CPL) {
-                        // coupled block: own point plus partners across the coupled start faces
-                        const int cur = t & 1, prv = cur ^ 1;
-                        const int l[3] = {l0, l1, l2};
-                        int gp[3];
-#pragma unroll
-                        for (int a = 0; a < 3; ++a) gp[a] = F.base[a] + F.d[a] * l[a];
-                        T M[8][8], R[8];
-#pragma unroll
-                        for (int i = 0; i < 8; ++i) {
-                            R[i] = T(0);
-#pragma unroll
-                            for (int j = 0; j < 8; ++j) M[i][j] = (i == j) ? T(1) : T(0);
-                        }
-#pragma unroll
-                        for (int B = 0; B < 8; ++B) {
-                            if (B & ~Am) continue;
-                            int gq[3], dq[3];
-#pragma unroll
-                            for (int a = 0; a < 3; ++a) {
-                                const bool fl = (B >> a) & 1;
-                                gq[a] = gp[a] - (fl ? F.d[a] : 0);
-                                dq[a] = fl ? -F.d[a] : F.d[a];
-                            }
-                            const int64_t Q = lin(g.n, gq);
-                            const T D = ldv<T>(A.piv, Q);
-                            const T sc = T(1) / D;
-                            T acc = ldv<T>(A.in, Q);
-                            if (scale) acc *= D;
-#pragma unroll
-                            for (int a = 0; a < 3; ++a) {
-                                const int su = -dq[a];
-                                int q[3] = {gq[0], gq[1], gq[2]};
-                                q[a] += su;
-                                if (q[a] >= 0 && q[a] < g.n[a]) {
-                                    const T coef = ldv<T>(A.diag[dk(a, su)], Q);
-                                    if ((Am >> a) & 1) {
-                                        M[B][B ^ (1 << a)] -= sc * coef;
-                                    } else {
-                                        // B = 0: the own upstream neighbour (inside the tile, l[a] > 0)
-                                        const T v = B == 0 ? own[o - (a == 0 ? 1 : (a == 1 ? pitch : pitch * L1))]
-                                                           : *rg.slot(B, prv, l1 - (a == 1), l2 - (a == 2), L1);
-                                        acc += coef * v;
-                                    }
-                                }
-                            }
-                            R[B] = sc * acc;
-                        }
-                        if ((Am & (Am - 1)) == 0) {
-                            const int b = Am;
-                            const T det = T(1) - M[0][b] * M[b][0];
-                            const T x0 = (R[0] - M[0][b] * R[b]) / det;
-                            const T x1 = (R[b] - M[b][0] * R[0]) / det;
-                            R[0] = x0;
-                            R[b] = x1;
-                        } else {
-                            ge_solve<T, 8>(M, R);
-                        }
-                        own[o] = R[0];
-#pragma unroll
-                        for (int B = 1; B < 7; ++B)
-                            if (!(B & ~Am)) *rg.slot(B, cur, l1, l2, L1) = R[B];
                     }
                 }
                 ring[k] = pk[(int64_t)min(t + PD, nlev - 1) * C];
@@ -1561,8 +1508,12 @@ static hipError_t tile3_impl(const PassGeom &g, bool start, const void *const *d
     if (g.cmax > 1024) return hipErrorInvalidValue;
     const int nth = std::max(64, (g.cmax + 63) / 64 * 64);
     const size_t sm = tile3_lds_bytes(g, len0max, sizeof(float));
-    if (start)
+    if (start) {
+        // the coupled start faces first (level kernel, faces only, unscaled into out)
+        hipError_t e = start_impl<float, S, TIN, TOUT>(g, diag, piv, in, scale_by_piv, out, 1.0, st, true);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_tile3<float, S, TIN, TOUT, true>), dim3(g.ntiles), dim3(nth), sm, st, A);
+    }
     else
         hipLaunchKernelGGL((k_tile3<float, S, TIN, TOUT, false>), dim3(g.ntiles), dim3(nth), sm, st, A);
     return hipGetLastError();
