@@ -41,10 +41,13 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample-s", type=float, default=15.0)
-    ap.add_argument("--workload", default="varcoef2048", choices=["varcoef2048", "batch512", "serve"],
+    ap.add_argument("--workload", default="varcoef2048", choices=["varcoef2048", "batch512", "serve", "poisson3d256"],
                     help="varcoef2048: one 2048^2 solve per step (default); batch512: 512 anisotropic problems "
                          "solved together per step; serve: a stream of Poisson arrivals through the server")
     ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--n3", type=int, default=256, help="poisson3d256: grid points per axis")
+    ap.add_argument("--p3", type=int, default=8, help="poisson3d256: subdomains per axis")
+    ap.add_argument("--prec3", default="f32", choices=["f32", "bf16"], help="poisson3d256: sweep precision")
     ap.add_argument("--plain-sample", type=int, default=24, help="batch512: problems solved one by one in FP64")
     ap.add_argument("--serve-count", type=int, default=40, help="serve: number of requests in the stream")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="serve: mean arrival rate (requests/s)")
@@ -76,6 +79,8 @@ def main():
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "poisson3d256":
+        return bench_poisson3d(args)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     n, p = args.n, args.p
@@ -398,6 +403,111 @@ def measure_roofline(g, N, args, stream, k_ms=None, k_n=None):
             "kernel": "k_fast2d<2,double,...,SC=false,CPL=true> (forward start-coupled half-sweep)",
             "kernel_ms": round(k_ms, 4), "timed_launches": k_n, "timing": how, "bytes_per_point": bpp,
             "algorithmic_bytes": alg_bytes}
+
+
+def bench_poisson3d(args):
+    """3D Poisson, 7-point, n^3 grid (256^3), p^3 subdomains (8^3), overlap 2: FP64 CG with ILU(0) (or
+    SSOR) sweeps in FP32 (FP32- or BF16-stored coefficients) to 1e-8."""
+    import numpy as np
+    import torch
+
+    import paper_1008_3699_amd as P
+    import synth
+
+    dev = torch.device("cuda:0")
+    n, p = args.n3, args.p3
+    w = synth.poisson_3d(n=n)
+    N = n ** 3
+    g = P.Problem(3, (n, n, n))
+    g.assemble([torch.from_numpy(a).to(dev) for a in w["alphas"]], 0.0, args.prec3)
+    g.set_relaxation([1.0])
+    g.set_decomposition((p, p, p), overlap=2, phase=0)
+    g.precond_setup(args.precond)
+    f = torch.from_numpy(w["f"]).to(dev)
+    u = torch.zeros(N, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+
+    def one_solve():
+        u.zero_()
+        return g.solve("cg", args.precond, f, u, rtol=args.rtol, maxit=args.maxit)
+
+    for _ in range(args.warmup):
+        one_solve()
+    torch.cuda.synchronize()
+    lat, infos = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        infos.append(one_solve())
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - s0)
+    elapsed = time.perf_counter() - t0
+    iters = [i["iters"] for i in infos]
+    value = N * sum(4 * (it + 1) for it in iters) / elapsed / 1e9
+
+    # the forward half-sweep (start-face level kernel + LDS-tile interior kernel), timed with events
+    # on the stream it runs on, after the timed solves
+    y = torch.empty_like(f)
+    stream = torch.cuda.current_stream()
+    reps = 20
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record(stream)
+        g.precond_half(args.precond, 0, f, y)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    bpp = 8 + 16 + 8  # FP64 input, packed FP32 coefficients (1/Piv and three couplings), FP64 output
+    if args.prec3 == "bf16":
+        bpp = 8 + 8 + 8
+    achieved = N * bpp / (ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+                "frac": round(achieved / 8000.0, 4), "traffic": None,
+                "kernel": "3D forward start-coupled half-sweep: k_sweep_start (start faces only) + k_tile3 (interior)",
+                "kernel_ms": round(ms, 4), "timed_launches": reps,
+                "timing": "HIP events on the launching stream around standalone pass-0 applications after the timed solves",
+                "bytes_per_point": bpp, "algorithmic_bytes": N * bpp}
+    cpu = None
+    if not args.no_cpu:
+        from oracle import oracle as O
+        diags = O.assemble(3, (n, n, n), w["alphas"])
+        pc = O.Precond(args.precond, 3, (n, n, n), (p, p, p), diags, omega=1.0)
+        t1 = time.perf_counter()
+        halves = 0
+        while True:
+            pc.forward(w["f"])
+            halves += 1
+            if time.perf_counter() - t1 > args.cpu_sample_s:
+                break
+        dt = time.perf_counter() - t1
+        cpu = {"value": round(N * halves / dt / 1e9, 5), "unit": "Gpoints/s", "cores": 1, "kind": "oracle",
+               "sample": f"{halves} forward half-sweeps of the {args.precond} preconditioner on the full {n}^3 grid "
+                         f"({p}^3 subdomains), single-threaded C oracle in FP64"}
+    rec = {
+        "metric": "sweep Gpoints/s (whole job, PCG to 1e-8)",
+        "value": round(value, 3),
+        "unit": "Gpoints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec3,
+        "data": "synthetic",
+        "config": {"workload": f"3D Poisson 7-point {n}^3, {p}^3 subdomains, overlap 2, FP64 CG with "
+                               f"{args.prec3.upper()} {args.precond.upper()} sweeps (symmetric form) to {args.rtol:g}",
+                   "n": n, "subdomains": [p, p, p], "overlap": 2, "precond": args.precond},
+        "solves_per_s": round(args.steps / elapsed, 4),
+        "latency_p50_s": round(float(np.percentile(lat, 50)), 4),
+        "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
+        "iterations": iters,
+        "relres": [i["relres"] for i in infos],
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
 
 
 def cpu_baseline(w, n, p, kind, budget_s):

@@ -94,22 +94,13 @@ __device__ __forceinline__ void ge_solve(T (&M)[NB][NB], T (&R)[NB]) {
     }
 }
 
-// The 2x2 block on rows / columns {0, b} of an NB x NB system (b a single bit, the
-// one coupled face of the point), with compile-time indices so that M and R stay in
-// registers (a runtime index would put them in scratch memory).
-template <typename T, int NB, int B>
-__device__ __forceinline__ void solve2_at(T (&M)[NB][NB], T (&R)[NB]) {
-    const T det = T(1) - M[0][B] * M[B][0];
-    const T x0 = (R[0] - M[0][B] * R[B]) / det;
-    const T x1 = (R[B] - M[B][0] * R[0]) / det;
-    R[0] = x0;
-    R[B] = x1;
-}
-template <typename T, int NB>
-__device__ __forceinline__ void solve2(T (&M)[NB][NB], T (&R)[NB], int b) {
-    if (b == 1) solve2_at<T, NB, 1>(M, R);
-    else if (NB > 2 && b == 2) solve2_at<T, NB, (NB > 2 ? 2 : 1)>(M, R);
-    else if (NB > 4 && b == 4) solve2_at<T, NB, (NB > 4 ? 4 : 1)>(M, R);
+// Workgroup barrier that orders LDS only: the waves wait for their own LDS
+// accesses, not for global stores in flight.  For level loops whose global
+// writes no thread of the workgroup reads back.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // LDS slot rings: one double-buffered slot per (block type B, position).
@@ -167,8 +158,7 @@ template <typename S, typename TIN, typename TOUT> struct StartArgs {
 };
 
 template <int DIM, typename T, typename S, typename TIN, typename TOUT, bool STAT>
-__global__ void __launch_bounds__(256) k_sweep_start(StartArgs<S, TIN, TOUT> A) {
-    extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void sweep_start_body(const StartArgs<S, TIN, TOUT> &A, unsigned char *smem) {
     const PassGeom &g = A.g;
     const TileDesc td = g.tiles[blockIdx.x];
     const TileFrame F = make_frame<DIM>(g, td);
@@ -230,6 +220,64 @@ __global__ void __launch_bounds__(256) k_sweep_start(StartArgs<S, TIN, TOUT> A) 
                 *rg.slot(0, cur, l1, l2, L1) = x;
                 A.out[P] = (TOUT)((T)A.cscale * x);
             } else {
+                // one member of the coupled block: block point B (partner across the start
+                // faces in B); returns its right-hand side, its coupling to the partner across
+                // the single coupled face `cross` in mx (the generic path below keeps all of them)
+                auto member = [&](int B, T &mx) -> T {
+                    int gq[3], dq[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const bool fl = (B >> a) & 1;
+                        gq[a] = gp[a] - (fl ? F.d[a] : 0);
+                        dq[a] = fl ? -F.d[a] : F.d[a];
+                    }
+                    const int64_t Q = lin(g.n, gq);
+                    int corner = 0;
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) corner |= (dq[a] < 0) << a;
+                    const T w = STAT ? (T)A.omega[corner] : T(1);
+                    const T D = STAT ? ldv<T>(A.diag[0], Q) : ldv<T>(A.piv, Q);
+                    const T sc = w / D;
+                    T acc = ldv<T>(A.in, Q);
+                    if (!STAT && A.scale_by_piv) acc *= D;
+                    mx = T(0);
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) {
+                        const int su = -dq[a];
+                        int q[3] = {gq[0], gq[1], gq[2]};
+                        q[a] += su;
+                        if (q[a] >= 0 && q[a] < g.n[a]) {
+                            const T coef = ldv<T>(A.diag[dk(a, su)], Q);
+                            if ((Am >> a) & 1) {
+                                mx -= sc * coef;
+                            } else {
+                                const T v = *rg.slot(B, prv, l1 - (a == 1), l2 - (a == 2), L1);
+                                acc += coef * v;
+                            }
+                        }
+                        if (STAT) {
+                            int r[3] = {gq[0], gq[1], gq[2]};
+                            r[a] += dq[a];
+                            if (r[a] >= 0 && r[a] < g.n[a])
+                                acc += ldv<T>(A.diag[dk(a, dq[a])], Q) * ldv<T>(A.uold, lin(g.n, r));
+                        }
+                    }
+                    return STAT ? (T(1) - w) * ldv<T>(A.uold, Q) + sc * acc : sc * acc;
+                };
+                if ((Am & (Am - 1)) == 0) {
+                    // one coupled face: the 2x2 block (eq. 1d:sorc / eq. 2d:sor2b2) in scalars, so
+                    // that nothing of it is indexed at run time
+                    T m0, mb;
+                    const T r0 = member(0, m0), rb = member(Am, mb);
+                    const T det = T(1) - m0 * mb;
+                    const T x0 = (r0 - m0 * rb) / det;
+                    const T x1 = (rb - mb * r0) / det;
+                    const int64_t P = lin(g.n, gp);
+                    A.out[P] = (TOUT)((T)A.cscale * x0);
+                    *rg.slot(0, cur, l1, l2, L1) = x0;
+                    *rg.slot(Am, cur, l1, l2, L1) = x1;
+                    continue;
+                }
                 // coupled block: own point plus partners across the coupled start faces
                 T M[NB][NB], R[NB];
 #pragma unroll
@@ -279,12 +327,7 @@ __global__ void __launch_bounds__(256) k_sweep_start(StartArgs<S, TIN, TOUT> A) 
                     }
                     R[B] = STAT ? (T(1) - w) * ldv<T>(A.uold, Q) + sc * acc : sc * acc;
                 }
-                if ((Am & (Am - 1)) == 0) {
-                    // 2x2 (eq. 1d:sorc / eq. 2d:sor2b2)
-                    solve2<T, NB>(M, R, Am);
-                } else {
-                    ge_solve<T, NB>(M, R);
-                }
+                ge_solve<T, NB>(M, R);
                 const int64_t P = lin(g.n, gp);
                 A.out[P] = (TOUT)((T)A.cscale * R[0]);
 #pragma unroll
@@ -294,8 +337,22 @@ __global__ void __launch_bounds__(256) k_sweep_start(StartArgs<S, TIN, TOUT> A) 
                 }
             }
         }
-        __syncthreads();
+        lds_barrier(); // out is written, never read back, inside the sweep
     }
+}
+
+template <int DIM, typename T, typename S, typename TIN, typename TOUT, bool STAT>
+__global__ void __launch_bounds__(256) k_sweep_start(StartArgs<S, TIN, TOUT> A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    sweep_start_body<DIM, T, S, TIN, TOUT, STAT>(A, smem);
+}
+
+// the coupled start faces only, one pencil per thread (up to 1024), so that a thread
+// meets at most one face point per level
+template <typename T, typename S, typename TIN, typename TOUT>
+__global__ void __launch_bounds__(1024) k_start_faces3(StartArgs<S, TIN, TOUT> A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    sweep_start_body<3, T, S, TIN, TOUT, false>(A, smem);
 }
 
 // ------------------------------------------------------------------ end-coupled (transposed) sweep
@@ -362,6 +419,47 @@ __device__ void end_block(const EndArgs<S, TIN, TOUT> &A, const int gp[3], const
                           int Am) {
     constexpr int NB = 1 << DIM;
     const PassGeom &g = A.g;
+    if ((Am & (Am - 1)) == 0) {
+        // one coupled face: the 2x2 block in scalars (nothing indexed at run time)
+        auto member = [&](int B, T &mx, int64_t &Qo) -> T {
+            int gq[3], dq[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const bool fl = (B >> a) & 1;
+                gq[a] = gp[a] + (fl ? d[a] : 0);
+                dq[a] = fl ? -d[a] : d[a];
+            }
+            const int64_t Q = lin(g.n, gq);
+            Qo = Q;
+            const T D = ldv<T>(A.piv, Q);
+            T acc = ldv<T>(A.in, Q);
+            if (A.scale_by_piv) acc *= D;
+            mx = T(0);
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                if ((Am >> a) & 1) {
+                    const int s2 = ((B >> a) & 1) ? -d[a] : d[a];
+                    int q[3] = {gq[0], gq[1], gq[2]};
+                    q[a] += s2;
+                    mx -= ldv<T>(A.diag[dk(a, -s2)], lin(g.n, q)) / D;
+                }
+                if (((Am >> a) & 1) || l[a] > 0) {
+                    int r[3] = {gq[0], gq[1], gq[2]};
+                    r[a] -= dq[a];
+                    const int64_t Ri = lin(g.n, r);
+                    acc += ldv<T>(A.diag[dk(a, dq[a])], Ri) * ldv<T>(A.out, Ri);
+                }
+            }
+            return acc / D;
+        };
+        T m0, mb;
+        int64_t Q0, Qb;
+        const T r0 = member(0, m0, Q0), rb = member(Am, mb, Qb);
+        const T det = T(1) - m0 * mb;
+        A.out[Q0] = (TOUT)((r0 - m0 * rb) / det);
+        A.out[Qb] = (TOUT)((rb - mb * r0) / det);
+        return;
+    }
     T M[NB][NB], R[NB];
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
@@ -406,11 +504,7 @@ __device__ void end_block(const EndArgs<S, TIN, TOUT> &A, const int gp[3], const
         }
         R[B] = acc / D;
     }
-    if ((Am & (Am - 1)) == 0) {
-        solve2<T, NB>(M, R, Am);
-    } else {
-        ge_solve<T, NB>(M, R);
-    }
+    ge_solve<T, NB>(M, R);
 #pragma unroll
     for (int B = 0; B < NB; ++B)
         if (!(B & ~Am)) A.out[idx[B]] = (TOUT)R[B];
@@ -590,6 +684,9 @@ static hipError_t start_impl(const PassGeom &g, const void *const *diag, const v
     dim3 grid(g.ntiles), blk(block_threads(g));
     if (g.dim == 2)
         hipLaunchKernelGGL((k_sweep_start<2, T, S, TIN, TOUT, false>), grid, blk, sm, st, A);
+    else if (faces_only && g.cmax <= 1024)
+        hipLaunchKernelGGL((k_start_faces3<T, S, TIN, TOUT>), grid, dim3(std::max(64, (g.cmax + 63) / 64 * 64)), sm,
+                           st, A);
     else
         hipLaunchKernelGGL((k_sweep_start<3, T, S, TIN, TOUT, false>), grid, blk, sm, st, A);
     return hipGetLastError();
@@ -1462,7 +1559,7 @@ __global__ void __launch_bounds__(1024) k_tile3(Tile3Args<S, TIN, TOUT> A) {
                     }
                 }
                 ring[k] = pk[(int64_t)min(t + PD, nlev - 1) * C];
-                __syncthreads();
+                lds_barrier();
             }
         }
     }
