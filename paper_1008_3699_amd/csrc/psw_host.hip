@@ -463,7 +463,8 @@ psw_status half(psw_problem *P, psw_precond kind, int which, const void *in, boo
     if (S.tile3) {
         HIPCHK(launch_tile3(g, s, which <= 1, d, S.piv.p, S.t3pk[which].p, S.t3off.as<int64_t>(), S.len0max, in,
                             in_f64, scale_by_piv, out, out_f64, which <= 1 ? cscale : 1.0, st));
-        if (which >= 2) HIPCHK(launch_end_fixups3(g, s, d, S.piv.p, in, in_f64, scale_by_piv, out, out_f64, st));
+        if (which >= 2)
+            HIPCHK(launch_end_fixups3(g, s, d, S.piv.p, in, in_f64, scale_by_piv, out, out_f64, S.len0max, st));
         return PSW_OK;
     }
     if (which <= 1)

@@ -66,7 +66,7 @@ hipError_t launch_tile3(const PassGeom &g, Store s, bool start, const void *cons
                         const void *pk, const int64_t *poff, int len0max, const void *in, bool in_f64,
                         bool scale_by_piv, void *out, bool out_f64, double cscale, hipStream_t st);
 hipError_t launch_end_fixups3(const PassGeom &g, Store s, const void *const *diag, const void *piv, const void *in,
-                              bool in_f64, bool scale_by_piv, void *out, bool out_f64, hipStream_t st);
+                              bool in_f64, bool scale_by_piv, void *out, bool out_f64, int len0max, hipStream_t st);
 
 // ILU(0) pivots of the decomposed factorisation, FP64.
 hipError_t launch_ilu_pivots(const PassGeom &g, const double *const *diag, double *piv, int *bad,

@@ -136,7 +136,7 @@ __device__ __forceinline__ Rings<T> make_rings(void *smem, const PassGeom &g) {
     return r;
 }
 
-size_t rings_bytes(const PassGeom &g, size_t elem) {
+__host__ __device__ size_t rings_bytes(const PassGeom &g, size_t elem) {
     return elem * (size_t)(4 * g.cmax + 4 * g.l2max + 4 * g.l1max + 2);
 }
 
@@ -355,6 +355,181 @@ __global__ void __launch_bounds__(1024) k_start_faces3(StartArgs<S, TIN, TOUT> A
     sweep_start_body<3, T, S, TIN, TOUT, false>(A, smem);
 }
 
+// The coupled start faces of a 3D preconditioner pass with their data gathered
+// into LDS first.  Everything a face block needs that does not depend on the
+// sweep (the right-hand sides of its points scaled by 1/Piv, and each point's
+// three couplings scaled by 1/Piv) is loaded once, with all loads in flight
+// together; the level loop then reads LDS and the rings only.  A point on one
+// coupled face has a record of two members, a point on an edge or the corner
+// a record of eight member slots (indexed by the member's face bits).
+// Level order, ring use and block equations are those of the generic kernel.
+__host__ __device__ __forceinline__ int faces3_rec_floats(int len0, int len1, int len2, int lmax) {
+    return 8 * (len1 * len2 + len0 * len2 + len0 * len1) + 32 * (3 * lmax + 1);
+}
+
+template <typename T, typename S, typename TIN, typename TOUT>
+__global__ void __launch_bounds__(1024) k_start_faces3g(StartArgs<S, TIN, TOUT> A, int lmax) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const PassGeom &g = A.g;
+    const TileDesc td = g.tiles[blockIdx.x];
+    const TileFrame F = make_frame<3>(g, td);
+    const int len[3] = {F.len[0], F.len[1], F.len[2]};
+    const int L1 = len[1];
+    Rings<T> rg = make_rings<T>(smem, g);
+    const size_t rb = (rings_bytes(g, sizeof(T)) + 15) / 16 * 16;
+    // rings start at zero: a weight of zero (no upstream point) then meets a finite value
+    for (size_t i = threadIdx.x; i < rings_bytes(g, sizeof(T)) / sizeof(T); i += blockDim.x)
+        reinterpret_cast<T *>(smem)[i] = T(0);
+    T *rec1 = reinterpret_cast<T *>(smem + rb);                      // single-face records, 8 values each
+    const int nf[3] = {len[1] * len[2], len[0] * len[2], len[0] * len[1]};
+    T *recm = rec1 + 8 * (nf[0] + nf[1] + nf[2]);                       // edge / corner records, 32 values each
+    const int nth = blockDim.x;
+    const bool scale = A.scale_by_piv != 0;
+
+    // face a, index j -> local point (scalars) and its coupled-face mask; owned by the lowest
+    // coupled face.  Scalars only: an array selected at run time would live in scratch memory.
+    auto point = [&](int a, int j, int &l0, int &l1, int &l2, int &Am) -> bool {
+        if (a == 0) {
+            l0 = 0;
+            l1 = j % len[1];
+            l2 = j / len[1];
+        } else if (a == 1) {
+            l1 = 0;
+            l0 = j % len[0];
+            l2 = j / len[0];
+        } else {
+            l2 = 0;
+            l0 = j % len[0];
+            l1 = j / len[0];
+        }
+        Am = (l0 == 0 && F.start_cpl[0] ? 1 : 0) | (l1 == 0 && F.start_cpl[1] ? 2 : 0) |
+             (l2 == 0 && F.start_cpl[2] ? 4 : 0);
+        return F.start_cpl[a] && (Am & ((1 << a) - 1)) == 0;
+    };
+    auto rec_of = [&](int a, int j, int l0, int l1, int l2, int Am) -> T * {
+        if ((Am & (Am - 1)) == 0) {
+            const int off = a == 0 ? 0 : (a == 1 ? nf[0] : nf[0] + nf[1]);
+            return rec1 + 8 * (off + j);
+        }
+        if (Am == 7) return recm + 32 * (3 * lmax);
+        const int e = Am == 3 ? 0 : (Am == 5 ? 1 : 2); // x-y edge (along z), x-z (along y), y-z (along x)
+        const int pos = Am == 3 ? l2 : (Am == 5 ? l1 : l0);
+        return recm + 32 * (e * lmax + pos);
+    };
+    // member B of the block at local point (l0, l1, l2): r = rhs / Piv, w[a] = coupling along a / Piv
+    auto gather = [&](int l0, int l1, int l2, int B, T *r4) {
+        const int l[3] = {l0, l1, l2};
+        int gq[3], dq[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const bool fl = (B >> a) & 1;
+            gq[a] = F.base[a] + F.d[a] * l[a] - (fl ? F.d[a] : 0);
+            dq[a] = fl ? -F.d[a] : F.d[a];
+        }
+        const int64_t Q = lin(g.n, gq);
+        const T D = ldv<T>(A.piv, Q);
+        const T sc = T(1) / D;
+        T acc = ldv<T>(A.in, Q);
+        if (scale) acc *= D;
+        r4[0] = sc * acc;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int su = -dq[a];
+            int q[3] = {gq[0], gq[1], gq[2]};
+            q[a] += su;
+            r4[1 + a] = (q[a] >= 0 && q[a] < g.n[a]) ? sc * ldv<T>(A.diag[dk(a, su)], Q) : T(0);
+        }
+    };
+
+    // ---- gather
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (!F.start_cpl[a]) continue;
+        for (int j = threadIdx.x; j < nf[a]; j += nth) {
+            int l0, l1, l2, Am;
+            if (!point(a, j, l0, l1, l2, Am)) continue;
+            T *rc = rec_of(a, j, l0, l1, l2, Am);
+            if ((Am & (Am - 1)) == 0) {
+                gather(l0, l1, l2, 0, rc);
+                gather(l0, l1, l2, Am, rc + 4);
+            } else {
+#pragma unroll
+                for (int B = 0; B < 8; ++B)
+                    if (!(B & ~Am)) gather(l0, l1, l2, B, rc + 4 * B);
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- levels: the last one holding a face point is len_b + len_c - 2
+    int nlev = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        if (F.start_cpl[a]) nlev = max(nlev, len[0] + len[1] + len[2] - len[a] - 1);
+    for (int t = 0; t < nlev; ++t) {
+        const int cur = t & 1, prv = cur ^ 1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (!F.start_cpl[a]) continue;
+            for (int j = threadIdx.x; j < nf[a]; j += nth) {
+                int l0, l1, l2, Am;
+                if (!point(a, j, l0, l1, l2, Am)) continue;
+                if (l0 + l1 + l2 != t) continue;
+                const T *rc = rec_of(a, j, l0, l1, l2, Am);
+                // right-hand side of member B with the upstream values outside the block
+                auto rhs = [&](int B, const T *r4) -> T {
+                    T x = r4[0];
+                    // zero weight where the upstream point does not exist (the ring slot is finite)
+                    if (!(Am & 1)) x += r4[1] * *rg.slot(B, prv, l1, l2, L1);
+                    if (!(Am & 2)) x += r4[2] * *rg.slot(B, prv, max(l1 - 1, 0), l2, L1);
+                    if (!(Am & 4)) x += r4[3] * *rg.slot(B, prv, l1, max(l2 - 1, 0), L1);
+                    return x;
+                };
+                T x0;
+                if ((Am & (Am - 1)) == 0) {
+                    const int bit = Am == 1 ? 0 : (Am == 2 ? 1 : 2);
+                    const T R0 = rhs(0, rc), Rb = rhs(Am, rc + 4);
+                    const T m0 = -rc[1 + bit], mb = -rc[4 + 1 + bit];
+                    const T det = T(1) - m0 * mb;
+                    x0 = (R0 - m0 * Rb) / det;
+                    const T xb = (Rb - mb * R0) / det;
+                    *rg.slot(Am, cur, l1, l2, L1) = xb;
+                } else {
+                    T M[8][8], R[8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        R[i] = T(0);
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) M[i][k] = (i == k) ? T(1) : T(0);
+                    }
+#pragma unroll
+                    for (int B = 0; B < 8; ++B) {
+                        if (B & ~Am) continue;
+                        const T *r4 = rc + 4 * B;
+                        R[B] = rhs(B, r4);
+#pragma unroll
+                        for (int q = 0; q < 3; ++q)
+                            if ((Am >> q) & 1) M[B][B ^ (1 << q)] = -r4[1 + q];
+                    }
+                    ge_solve<T, 8>(M, R);
+                    x0 = R[0];
+#pragma unroll
+                    for (int B = 1; B < 7; ++B)
+                        if (!(B & ~Am)) *rg.slot(B, cur, l1, l2, L1) = R[B];
+                }
+                *rg.slot(0, cur, l1, l2, L1) = x0;
+                const int gp[3] = {F.base[0] + F.d[0] * l0, F.base[1] + F.d[1] * l1, F.base[2] + F.d[2] * l2};
+                A.out[lin(g.n, gp)] = (TOUT)((T)A.cscale * x0);
+            }
+        }
+        lds_barrier(); // out is written, never read back, inside the sweep
+    }
+}
+
+size_t faces3_lds_bytes(const PassGeom &g, int fmax, size_t elem) {
+    return (rings_bytes(g, elem) + 15) / 16 * 16 + elem * (size_t)fmax;
+}
+
 // ------------------------------------------------------------------ end-coupled (transposed) sweep
 template <typename S, typename TIN, typename TOUT> struct EndArgs {
     PassGeom g;
@@ -544,6 +719,232 @@ __global__ void __launch_bounds__(256) k_end_faces(EndArgs<S, TIN, TOUT> A) {
     }
 }
 
+// Faces (3D) with the data gathered first.  Face AX of a tile sweeping towards it:
+// points P = (len_AX - 1, lb, lc) with partners Q = P + d_AX e_AX; points that also
+// lie on another coupled end face are left to the edge and corner kernels.  All a
+// 2x2 block needs except the values of its in-face upstream neighbours is gathered
+// into LDS first (the right-hand side with the upstream value across AX, the two
+// in-face couplings and the cross coupling, divided by the pivot, for P and Q);
+// the wavefront over (lb, lc) then touches LDS only.  Equations as in end_block.
+template <int AX, typename T, typename S, typename TIN, typename TOUT>
+__device__ __forceinline__ void end_face3g_body(const EndArgs<S, TIN, TOUT> &A, const TileFrame &F,
+                                                unsigned char *smem) {
+    constexpr int a = AX, b = (AX + 1) % 3, c = (AX + 2) % 3;
+    const PassGeom &g = A.g;
+    const int nb = F.end_cpl[b] ? F.len[b] - 1 : F.len[b];
+    const int nc = F.end_cpl[c] ? F.len[c] - 1 : F.len[c];
+    const int np = nb * nc;
+    T *rec = reinterpret_cast<T *>(smem); // 8 values per point
+    T *vP = rec + 8 * np, *vQ = vP + np;   // solved values of the P and Q planes
+    const int nth = blockDim.x;
+    for (int j = threadIdx.x; j < np; j += nth) {
+        int l[3];
+        l[a] = F.len[a] - 1;
+        l[b] = j % nb;
+        l[c] = j / nb;
+        int gp[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) gp[q] = F.base[q] + F.d[q] * l[q];
+        T *rc = rec + 8 * j;
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            int gq[3] = {gp[0], gp[1], gp[2]}, dq[3] = {F.d[0], F.d[1], F.d[2]};
+            if (m) {
+                gq[a] += F.d[a];
+                dq[a] = -F.d[a];
+            }
+            const int64_t Q = lin(g.n, gq);
+            const T D = ldv<T>(A.piv, Q);
+            T acc = ldv<T>(A.in, Q);
+            if (A.scale_by_piv) acc *= D;
+            // the upstream point across AX (inside the member's own tile, final)
+            {
+                int r[3] = {gq[0], gq[1], gq[2]};
+                r[a] -= dq[a];
+                const int64_t Ri = lin(g.n, r);
+                acc += ldv<T>(A.diag[dk(a, dq[a])], Ri) * ldv<T>(A.out, Ri);
+            }
+            // cross coupling to the block mate
+            T mx;
+            {
+                const int s2 = m ? -F.d[a] : F.d[a];
+                int q[3] = {gq[0], gq[1], gq[2]};
+                q[a] += s2;
+                mx = -ldv<T>(A.diag[dk(a, -s2)], lin(g.n, q)) / D;
+            }
+            T wb = T(0), wc = T(0);
+            if (l[b] > 0) {
+                int r[3] = {gq[0], gq[1], gq[2]};
+                r[b] -= dq[b];
+                wb = ldv<T>(A.diag[dk(b, dq[b])], lin(g.n, r)) / D;
+            }
+            if (l[c] > 0) {
+                int r[3] = {gq[0], gq[1], gq[2]};
+                r[c] -= dq[c];
+                wc = ldv<T>(A.diag[dk(c, dq[c])], lin(g.n, r)) / D;
+            }
+            rc[4 * m + 0] = acc / D;
+            rc[4 * m + 1] = wb;
+            rc[4 * m + 2] = wc;
+            rc[4 * m + 3] = mx;
+        }
+    }
+    __syncthreads();
+    const int nlev = nb + nc - 1;
+    for (int t = 0; t < nlev; ++t) {
+        for (int j = threadIdx.x; j < np; j += nth) {
+            const int lb = j % nb, lc = j / nb;
+            if (lb + lc != t) continue;
+            const T *rc = rec + 8 * j;
+            T R0 = rc[0], Rb = rc[4];
+            if (lb > 0) {
+                R0 += rc[1] * vP[j - 1];
+                Rb += rc[5] * vQ[j - 1];
+            }
+            if (lc > 0) {
+                R0 += rc[2] * vP[j - nb];
+                Rb += rc[6] * vQ[j - nb];
+            }
+            const T m0 = rc[3], mb = rc[7];
+            const T det = T(1) - m0 * mb;
+            const T x0 = (R0 - m0 * Rb) / det;
+            const T xb = (Rb - mb * R0) / det;
+            vP[j] = x0;
+            vQ[j] = xb;
+            int l[3];
+            l[a] = F.len[a] - 1;
+            l[b] = lb;
+            l[c] = lc;
+            int gp[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) gp[q] = F.base[q] + F.d[q] * l[q];
+            A.out[lin(g.n, gp)] = (TOUT)x0;
+            gp[a] += F.d[a];
+            A.out[lin(g.n, gp)] = (TOUT)xb;
+        }
+        lds_barrier(); // out is written, never read back, inside this kernel
+    }
+}
+
+template <typename T, typename S, typename TIN, typename TOUT>
+__global__ void __launch_bounds__(1024) k_end_faces3g(EndArgs<S, TIN, TOUT> A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tile = blockIdx.x / 3, a = blockIdx.x % 3;
+    const TileFrame F = make_frame<3>(A.g, A.g.tiles[tile]);
+    if (!(F.d[a] > 0 && F.end_cpl[a])) return;
+    if (a == 0) end_face3g_body<0, T, S, TIN, TOUT>(A, F, smem);
+    else if (a == 1) end_face3g_body<1, T, S, TIN, TOUT>(A, F, smem);
+    else end_face3g_body<2, T, S, TIN, TOUT>(A, F, smem);
+}
+
+// Edges (3D) with the data gathered first: the edge along axis CX where the end
+// faces of a and b meet.  The four block points of each edge position (P and its
+// partners across a, b and both) get their right-hand sides with the upstream
+// values across a and b (final after the faces), their couplings along the edge
+// and their cross couplings, divided by the pivot, gathered by all threads; one
+// thread then runs the chain of 4x4 blocks along the edge from LDS.
+template <int CX, typename T, typename S, typename TIN, typename TOUT>
+__device__ __forceinline__ void end_edge3g_body(const EndArgs<S, TIN, TOUT> &A, const TileFrame &F,
+                                                unsigned char *smem) {
+    constexpr int c = CX, a = (CX + 1) % 3, b = (CX + 2) % 3;
+    const PassGeom &g = A.g;
+    const int nc = F.end_cpl[c] ? F.len[c] - 1 : F.len[c];
+    T *rec = reinterpret_cast<T *>(smem); // 16 values per position: member m = (flip a) | (flip b) << 1
+    for (int j = threadIdx.x; j < nc; j += blockDim.x) {
+        int l[3];
+        l[a] = F.len[a] - 1;
+        l[b] = F.len[b] - 1;
+        l[c] = j;
+        int gp[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) gp[q] = F.base[q] + F.d[q] * l[q];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            int gq[3] = {gp[0], gp[1], gp[2]}, dq[3] = {F.d[0], F.d[1], F.d[2]};
+            if (m & 1) {
+                gq[a] += F.d[a];
+                dq[a] = -F.d[a];
+            }
+            if (m & 2) {
+                gq[b] += F.d[b];
+                dq[b] = -F.d[b];
+            }
+            const int64_t Q = lin(g.n, gq);
+            const T D = ldv<T>(A.piv, Q);
+            T acc = ldv<T>(A.in, Q);
+            if (A.scale_by_piv) acc *= D;
+            T mcr[2];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int q = k == 0 ? a : b;
+                const bool fl = k == 0 ? (m & 1) : (m & 2);
+                const int s2 = fl ? -F.d[q] : F.d[q];
+                int qp[3] = {gq[0], gq[1], gq[2]};
+                qp[q] += s2;
+                mcr[k] = -ldv<T>(A.diag[dk(q, -s2)], lin(g.n, qp)) / D;
+                int r[3] = {gq[0], gq[1], gq[2]};
+                r[q] -= dq[q];
+                const int64_t Ri = lin(g.n, r);
+                acc += ldv<T>(A.diag[dk(q, dq[q])], Ri) * ldv<T>(A.out, Ri);
+            }
+            T wc = T(0);
+            if (l[c] > 0) {
+                int r[3] = {gq[0], gq[1], gq[2]};
+                r[c] -= dq[c];
+                wc = ldv<T>(A.diag[dk(c, dq[c])], lin(g.n, r)) / D;
+            }
+            T *rc = rec + 16 * j + 4 * m;
+            rc[0] = acc / D;
+            rc[1] = wc;
+            rc[2] = mcr[0];
+            rc[3] = mcr[1];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    T xp[4] = {T(0), T(0), T(0), T(0)};
+    for (int j = 0; j < nc; ++j) {
+        const T *rc = rec + 16 * j;
+        T M[4][4], R[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) M[m][k] = (m == k) ? T(1) : T(0);
+            R[m] = rc[4 * m] + rc[4 * m + 1] * xp[m];
+            M[m][m ^ 1] = rc[4 * m + 2];
+            M[m][m ^ 2] = rc[4 * m + 3];
+        }
+        ge_solve<T, 4>(M, R);
+        int l[3];
+        l[a] = F.len[a] - 1;
+        l[b] = F.len[b] - 1;
+        l[c] = j;
+        int gp[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) gp[q] = F.base[q] + F.d[q] * l[q];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            int gq[3] = {gp[0], gp[1], gp[2]};
+            if (m & 1) gq[a] += F.d[a];
+            if (m & 2) gq[b] += F.d[b];
+            A.out[lin(g.n, gq)] = (TOUT)R[m];
+            xp[m] = R[m];
+        }
+    }
+}
+
+template <typename T, typename S, typename TIN, typename TOUT>
+__global__ void __launch_bounds__(64) k_end_edges3g(EndArgs<S, TIN, TOUT> A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tile = blockIdx.x / 3, c = blockIdx.x % 3;
+    const int a = (c + 1) % 3, b = (c + 2) % 3;
+    const TileFrame F = make_frame<3>(A.g, A.g.tiles[tile]);
+    if (!(F.d[a] > 0 && F.end_cpl[a] && F.d[b] > 0 && F.end_cpl[b])) return;
+    if (c == 0) end_edge3g_body<0, T, S, TIN, TOUT>(A, F, smem);
+    else if (c == 1) end_edge3g_body<1, T, S, TIN, TOUT>(A, F, smem);
+    else end_edge3g_body<2, T, S, TIN, TOUT>(A, F, smem);
+}
+
 // Edges (3D): the edge along axis c where the end faces of a and b meet; owned
 // by the tile that sweeps towards both.  One thread walks the edge chain.
 template <typename T, typename S, typename TIN, typename TOUT>
@@ -668,7 +1069,8 @@ hipError_t launch_sweep_stationary(const PassGeom &g, const double *const *diag,
 
 template <typename T, typename S, typename TIN, typename TOUT>
 static hipError_t start_impl(const PassGeom &g, const void *const *diag, const void *piv, const void *in,
-                             bool scale_by_piv, void *out, double cscale, hipStream_t st, bool faces_only = false) {
+                             bool scale_by_piv, void *out, double cscale, hipStream_t st, bool faces_only = false,
+                             int len0max = 0, size_t lds_limit = 0) {
     StartArgs<S, TIN, TOUT> A{};
     A.faces_only = faces_only ? 1 : 0;
     A.g = g;
@@ -684,9 +1086,16 @@ static hipError_t start_impl(const PassGeom &g, const void *const *diag, const v
     dim3 grid(g.ntiles), blk(block_threads(g));
     if (g.dim == 2)
         hipLaunchKernelGGL((k_sweep_start<2, T, S, TIN, TOUT, false>), grid, blk, sm, st, A);
-    else if (faces_only && g.cmax <= 1024)
-        hipLaunchKernelGGL((k_start_faces3<T, S, TIN, TOUT>), grid, dim3(std::max(64, (g.cmax + 63) / 64 * 64)), sm,
-                           st, A);
+    else if (faces_only && g.cmax <= 1024) {
+        const int nth = std::max(64, (g.cmax + 63) / 64 * 64);
+        const int lmax = std::max(len0max, std::max(g.l1max, g.l2max));
+        const int fmax = faces3_rec_floats(len0max, g.l1max, g.l2max, lmax);
+        const size_t smg = faces3_lds_bytes(g, fmax, sizeof(T));
+        if (len0max > 0 && smg <= lds_limit)
+            hipLaunchKernelGGL((k_start_faces3g<T, S, TIN, TOUT>), grid, dim3(nth), smg, st, A, lmax);
+        else
+            hipLaunchKernelGGL((k_start_faces3<T, S, TIN, TOUT>), grid, dim3(nth), sm, st, A);
+    }
     else
         hipLaunchKernelGGL((k_sweep_start<3, T, S, TIN, TOUT, false>), grid, blk, sm, st, A);
     return hipGetLastError();
@@ -719,7 +1128,8 @@ static hipError_t end_impl(const PassGeom &g, const void *const *diag, const voi
 
 template <typename T, typename S, typename TIN, typename TOUT>
 static hipError_t end_part_impl(const PassGeom &g, const void *const *diag, const void *piv, const void *in,
-                                bool scale_by_piv, void *out, int part, hipStream_t st) {
+                                bool scale_by_piv, void *out, int part, hipStream_t st, int len0max = 0,
+                                size_t lds_limit = 0) {
     EndArgs<S, TIN, TOUT> A{};
     A.g = g;
     for (int k = 0; k < 2 * g.dim + 1; ++k) A.diag[k] = (const S *)diag[k];
@@ -739,29 +1149,41 @@ static hipError_t end_part_impl(const PassGeom &g, const void *const *diag, cons
             hipLaunchKernelGGL((k_end_corners<3, T, S, TIN, TOUT>), dim3((g.ntiles + 63) / 64), dim3(64), 0, st, A);
     } else {
         if (g.dim != 3) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_end_faces<3, T, S, TIN, TOUT>), dim3(g.ntiles * 3), dim3(64), 0, st, A);
-        hipLaunchKernelGGL((k_end_edges<T, S, TIN, TOUT>), dim3((g.ntiles * 3 + 63) / 64), dim3(64), 0, st, A);
+        // largest end face: every face has at most max(len_b len_c) points
+        const int fmax = std::max(g.l1max * g.l2max, len0max * std::max(g.l1max, g.l2max));
+        if (len0max > 0 && fmax <= 1024 && 10 * (size_t)fmax * sizeof(T) <= lds_limit)
+            hipLaunchKernelGGL((k_end_faces3g<T, S, TIN, TOUT>), dim3(g.ntiles * 3),
+                               dim3(std::max(64, (fmax + 63) / 64 * 64)), 10 * (size_t)fmax * sizeof(T), st, A);
+        else
+            hipLaunchKernelGGL((k_end_faces<3, T, S, TIN, TOUT>), dim3(g.ntiles * 3), dim3(64), 0, st, A);
+        const int lmax = std::max(len0max, std::max(g.l1max, g.l2max));
+        if (len0max > 0 && 16 * (size_t)lmax * sizeof(T) <= lds_limit)
+            hipLaunchKernelGGL((k_end_edges3g<T, S, TIN, TOUT>), dim3(g.ntiles * 3), dim3(64),
+                               16 * (size_t)lmax * sizeof(T), st, A);
+        else
+            hipLaunchKernelGGL((k_end_edges<T, S, TIN, TOUT>), dim3((g.ntiles * 3 + 63) / 64), dim3(64), 0, st, A);
         hipLaunchKernelGGL((k_end_corners<3, T, S, TIN, TOUT>), dim3((g.ntiles + 63) / 64), dim3(64), 0, st, A);
     }
     return hipGetLastError();
 }
 
 static hipError_t end_part(const PassGeom &g, Store s, const void *const *diag, const void *piv, const void *in,
-                           bool in_f64, bool scale_by_piv, void *out, bool out_f64, int part, hipStream_t st) {
+                           bool in_f64, bool scale_by_piv, void *out, bool out_f64, int part, hipStream_t st,
+                           int len0max = 0, size_t lds_limit = 0) {
     if (s == Store::F64) {
         if (!in_f64 || !out_f64) return hipErrorInvalidValue;
-        return end_part_impl<double, double, double, double>(g, diag, piv, in, scale_by_piv, out, part, st);
+        return end_part_impl<double, double, double, double>(g, diag, piv, in, scale_by_piv, out, part, st, len0max, lds_limit);
     }
     if (s == Store::F32) {
-        if (in_f64 && !out_f64) return end_part_impl<float, float, double, float>(g, diag, piv, in, scale_by_piv, out, part, st);
-        if (!in_f64 && !out_f64) return end_part_impl<float, float, float, float>(g, diag, piv, in, scale_by_piv, out, part, st);
-        if (in_f64 && out_f64) return end_part_impl<float, float, double, double>(g, diag, piv, in, scale_by_piv, out, part, st);
-        return end_part_impl<float, float, float, double>(g, diag, piv, in, scale_by_piv, out, part, st);
+        if (in_f64 && !out_f64) return end_part_impl<float, float, double, float>(g, diag, piv, in, scale_by_piv, out, part, st, len0max, lds_limit);
+        if (!in_f64 && !out_f64) return end_part_impl<float, float, float, float>(g, diag, piv, in, scale_by_piv, out, part, st, len0max, lds_limit);
+        if (in_f64 && out_f64) return end_part_impl<float, float, double, double>(g, diag, piv, in, scale_by_piv, out, part, st, len0max, lds_limit);
+        return end_part_impl<float, float, float, double>(g, diag, piv, in, scale_by_piv, out, part, st, len0max, lds_limit);
     }
-    if (in_f64 && !out_f64) return end_part_impl<float, uint16_t, double, float>(g, diag, piv, in, scale_by_piv, out, part, st);
-    if (!in_f64 && !out_f64) return end_part_impl<float, uint16_t, float, float>(g, diag, piv, in, scale_by_piv, out, part, st);
-    if (in_f64 && out_f64) return end_part_impl<float, uint16_t, double, double>(g, diag, piv, in, scale_by_piv, out, part, st);
-    return end_part_impl<float, uint16_t, float, double>(g, diag, piv, in, scale_by_piv, out, part, st);
+    if (in_f64 && !out_f64) return end_part_impl<float, uint16_t, double, float>(g, diag, piv, in, scale_by_piv, out, part, st, len0max, lds_limit);
+    if (!in_f64 && !out_f64) return end_part_impl<float, uint16_t, float, float>(g, diag, piv, in, scale_by_piv, out, part, st, len0max, lds_limit);
+    if (in_f64 && out_f64) return end_part_impl<float, uint16_t, double, double>(g, diag, piv, in, scale_by_piv, out, part, st, len0max, lds_limit);
+    return end_part_impl<float, uint16_t, float, double>(g, diag, piv, in, scale_by_piv, out, part, st, len0max, lds_limit);
 }
 
 hipError_t launch_end_corners(const PassGeom &g, Store s, const void *const *diag, const void *piv, const void *in,
@@ -1591,6 +2013,10 @@ template <typename S, typename TIN, typename TOUT>
 static hipError_t tile3_impl(const PassGeom &g, bool start, const void *const *diag, const void *piv, const void *pk,
                              const int64_t *poff, int len0max, const void *in, bool scale_by_piv, void *out,
                              double cscale, hipStream_t st) {
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        lds = 0;
     Tile3Args<S, TIN, TOUT> A{};
     A.g = g;
     for (int k = 0; k < 7; ++k) A.diag[k] = (const S *)diag[k];
@@ -1607,7 +2033,8 @@ static hipError_t tile3_impl(const PassGeom &g, bool start, const void *const *d
     const size_t sm = tile3_lds_bytes(g, len0max, sizeof(float));
     if (start) {
         // the coupled start faces first (level kernel, faces only, unscaled into out)
-        hipError_t e = start_impl<float, S, TIN, TOUT>(g, diag, piv, in, scale_by_piv, out, 1.0, st, true);
+        hipError_t e =
+            start_impl<float, S, TIN, TOUT>(g, diag, piv, in, scale_by_piv, out, 1.0, st, true, len0max, (size_t)lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_tile3<float, S, TIN, TOUT, true>), dim3(g.ntiles), dim3(nth), sm, st, A);
     }
@@ -1637,8 +2064,12 @@ hipError_t launch_tile3(const PassGeom &g, Store s, bool start, const void *cons
 
 // the coupled end faces, edges and corners of an end-coupled 3D pass (after its interior)
 hipError_t launch_end_fixups3(const PassGeom &g, Store s, const void *const *diag, const void *piv, const void *in,
-                              bool in_f64, bool scale_by_piv, void *out, bool out_f64, hipStream_t st) {
-    return end_part(g, s, diag, piv, in, in_f64, scale_by_piv, out, out_f64, 2, st);
+                              bool in_f64, bool scale_by_piv, void *out, bool out_f64, int len0max, hipStream_t st) {
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        lds = 0;
+    return end_part(g, s, diag, piv, in, in_f64, scale_by_piv, out, out_f64, 2, st, len0max, (size_t)lds);
 }
 
 } // namespace psw
