@@ -463,7 +463,7 @@ def bench_poisson3d(args):
     achieved = N * bpp / (ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
                 "frac": round(achieved / 8000.0, 4), "traffic": None,
-                "kernel": "3D forward start-coupled half-sweep: k_sweep_start (start faces only) + k_tile3 (interior)",
+                "kernel": "3D forward start-coupled half-sweep: k_start_faces3g (coupled start faces) + k_tile3 (interior)",
                 "kernel_ms": round(ms, 4), "timed_launches": reps,
                 "timing": "HIP events on the launching stream around standalone pass-0 applications after the timed solves",
                 "bytes_per_point": bpp, "algorithmic_bytes": N * bpp}
