@@ -97,6 +97,10 @@ def main():
     torch.cuda.synchronize()
     if args.roofline_only:
         roofline = measure_roofline(g, N, args, stream)
+        # a few CG iterations, so that counter runs also see the fused CG step
+        u.zero_()
+        g.solve("cg", args.precond, f, u, rtol=args.rtol, maxit=40, check=False)
+        torch.cuda.synchronize()
         # reference for byte counters: one plain device copy of 512 MiB
         src = torch.ones(64 << 20, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -112,8 +116,10 @@ def main():
     for _ in range(args.warmup):
         one_solve()
     torch.cuda.synchronize()
-    # the dominant kernel (pass 0) is timed with HIP events on its own stream inside the timed solves
+    # the fused CG step (the largest share of kernel time) and the forward half-sweep (the method's
+    # decomposed sweep) are timed with HIP events on their stream inside the timed solves
     g.pass_timing_enable(0, True)
+    g.pass_timing_enable(4, True)
     lat = []
     infos = []
     t0 = time.perf_counter()
@@ -130,9 +136,12 @@ def main():
     half_sweeps = sum(4 * (it + 1) for it in iters)
     value = N * half_sweeps / elapsed / 1e9
 
-    k_ms, k_n = g.pass_timing()
+    k_ms, k_n = g.pass_timing(0)
+    c_ms, c_n = g.pass_timing(4)
     g.pass_timing_enable(0, False)
-    roofline = measure_roofline(g, N, args, stream, k_ms=k_ms, k_n=k_n)
+    g.pass_timing_enable(4, False)
+    roofline_sweep = measure_roofline(g, N, args, stream, k_ms=k_ms, k_n=k_n)
+    roofline = cg_step_roofline(N, args, c_ms, c_n)
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(w, n, p, args.precond, args.cpu_sample_s)
@@ -159,9 +168,29 @@ def main():
         "iterations": iters,
         "relres": [i["relres"] for i in infos],
         "roofline": roofline,
+        "roofline_sweep": roofline_sweep,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
+
+
+def cg_step_roofline(N, args, c_ms, c_n):
+    """The fused 2D CG step (k_cg_pq2d), the kernel with the largest share of the solve's kernel
+    time: p = z + beta p with z formed from its two pieces, the deferred x update, q = A p and the
+    p.q partials.  Algorithmic bytes per point: z1, z2, old p, five diagonals and x read (72), new p,
+    q and x written (24)."""
+    bpp = 96
+    alg = bpp * N
+    achieved = alg / (c_ms * 1e-3) / 1e9
+    traffic = None
+    if args.prec == "f64" and args.n == 2048 and args.p == 16:
+        traffic = measured_traffic(CG_TRAFFIC_FILE, CG_KERNEL_SRC)
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "k_cg_pq2d<true,2> (fused CG step: p update, x update, q = A p, p.q partials)",
+            "kernel_ms": round(c_ms, 4), "timed_launches": c_n,
+            "timing": "HIP events on the launching stream around every 8th fused step inside the timed solves",
+            "bytes_per_point": bpp, "algorithmic_bytes": alg}
 
 
 def bench_batch(args):
@@ -362,15 +391,19 @@ def bench_serve(args):
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_fast2d_fwd_varcoef2048.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1008_3699_amd", "csrc", "psw_fast2d.hip")
+CG_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_cg_pq2d_varcoef2048.json")
+CG_KERNEL_SRC = os.path.join(ROOT, "paper_1008_3699_amd", "csrc", "psw_kernels.hip")
 
 
-def measured_traffic():
+def measured_traffic(traffic_file=None, kernel_src=None):
     """HBM bytes per launch of the timed kernel from the committed counter runs, or None when the
     kernel source has changed since they were taken."""
     import hashlib
+    traffic_file = traffic_file or TRAFFIC_FILE
+    kernel_src = kernel_src or KERNEL_SRC
     try:
-        rec = json.load(open(TRAFFIC_FILE))
-        h = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        rec = json.load(open(traffic_file))
+        h = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
     if rec.get("source_sha256") != h:

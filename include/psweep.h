@@ -191,11 +191,15 @@ psw_status psw_autotune(int dim, const int64_t n[3], psw_prec prec, psw_precond 
 /* Measurement aid: while enabled, the library records HIP events on the
  * launching stream around every 8th launch (at most 1024) of pipelined pass
  * `which` (0..3; the 2D pipelined path only) of this problem, inside solves
- * and preconditioner calls alike.  psw_pass_timing returns the mean duration
+ * and preconditioner calls alike; which = 4 selects the fused step of 2D CG
+ * (p update, q = A p and the p.q partials).  psw_pass_timing returns the mean duration
  * of the recorded launches in ms and their number since the last enable
- * (it waits for them to complete).  Enabling resets the record. */
+ * (it waits for them to complete) for the pass enabled last.  Enabling resets that pass's record. */
 psw_status psw_pass_timing_enable(psw_problem *prob, int which, int enable);
 psw_status psw_pass_timing(psw_problem *prob, double *mean_ms, int64_t *count);
+/* The same for pass `which` (0..4); each pass keeps its own record, so several
+ * can be timed in the same solves. */
+psw_status psw_pass_timing_of(psw_problem *prob, int which, double *mean_ms, int64_t *count);
 
 /* ---------------------------------------------------------------- serving
  * A server solves a stream of independent problems A u = f with

@@ -72,6 +72,7 @@ def lib():
             "psw_batch_solve": [ci, pp, pp, pp, ci, ci, dbl, i64, ctypes.POINTER(Info), vp],
             "psw_pass_timing_enable": [vp, ci, ci],
             "psw_pass_timing": [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)],
+            "psw_pass_timing_of": [vp, ci, ctypes.POINTER(dbl), ctypes.POINTER(i64)],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -197,10 +198,15 @@ class Problem:
     def pass_timing_enable(self, which, enable=True):
         _check(lib().psw_pass_timing_enable(self._h, int(which), int(bool(enable))), "psw_pass_timing_enable")
 
-    def pass_timing(self):
-        """(mean ms, number of timed launches) of the pass selected by pass_timing_enable."""
+    def pass_timing(self, which=None):
+        """(mean ms, number of timed launches) of pass `which` (default: the one enabled last);
+        which 0..3 are the pipelined 2D passes, 4 the fused 2D CG step."""
         ms, n = ctypes.c_double(), ctypes.c_int64()
-        _check(lib().psw_pass_timing(self._h, ctypes.byref(ms), ctypes.byref(n)), "psw_pass_timing")
+        if which is None:
+            _check(lib().psw_pass_timing(self._h, ctypes.byref(ms), ctypes.byref(n)), "psw_pass_timing")
+        else:
+            _check(lib().psw_pass_timing_of(self._h, int(which), ctypes.byref(ms), ctypes.byref(n)),
+                   "psw_pass_timing_of")
         return ms.value, n.value
 
     def solve(self, method, precond, f, u, rtol=1e-8, maxit=100000, restart=30, stream=None, check=True):

@@ -161,7 +161,8 @@ struct psw_problem {
     size_t lds_limit = 65536;
     SideStream side;
     HostScalars hs;
-    PassTiming timing;
+    PassTiming timing[5]; // per pass 0..3, and 4: the fused 2D CG step
+    int timing_last = 0;
 };
 
 namespace {
@@ -420,8 +421,8 @@ psw_status fast_pass(psw_problem *P, psw_precond kind, int which, const void *in
                      void *out, bool out_f64, double cscale, const double *add, double cadd, hipStream_t st) {
     PrecState &S = P->pc[kind];
     const Fast2dPass fp = fast_pass_desc(P, S, which);
-    PassTiming &T = P->timing;
-    const bool timed = T.on && T.which == which && (T.calls++ % PassTiming::kStride) == 0 && T.used < PassTiming::kPool;
+    PassTiming &T = P->timing[which];
+    const bool timed = T.on && (T.calls++ % PassTiming::kStride) == 0 && T.used < PassTiming::kPool;
     if (timed) HIPCHK(hipEventRecord(T.ev[2 * T.used], st));
     HIPCHK(launch_fast2d(fp, store_of(P->prec), in, in_f64, scale_by_piv, out, out_f64, which <= 1 ? cscale : 1.0,
                          add, cadd, st));
@@ -639,9 +640,17 @@ psw_status cg2d_fused(psw_problem *P, psw_precond kind, bool split, double rtol,
     if ((ps = precond())) return ps;
     if (!P->hs.ensure()) return PSW_ENOMEM;
     double *h = P->hs.p;
+    PassTiming &T = P->timing[4];
     while (it < maxit) {
+        // measurement aid (which = 4): events around every kStride-th fused step
+        const bool timed = T.on && (T.calls++ % PassTiming::kStride) == 0 && T.used < PassTiming::kPool;
+        if (timed) HIPCHK(hipEventRecord(T.ev[2 * T.used], st));
         HIPCHK(launch_cg_pq2d(P->n[0], P->n[1], d, z1, z2, hc, pa, pb, q, x, part_rz, s_rz2, s_rz, out + 1, it == 0,
                               part_pq, &npq, st));
+        if (timed) {
+            HIPCHK(hipEventRecord(T.ev[2 * T.used + 1], st));
+            ++T.used;
+        }
         std::swap(pa, pb);
         std::swap(s_rz, s_rz2);
         HIPCHK(launch_cg_r(r, q, s_rz, part_pq, npq, out, N, st));
@@ -1645,9 +1654,10 @@ psw_status psw_server_destroy(psw_server *S) {
 }
 
 psw_status psw_pass_timing_enable(psw_problem *P, int which, int enable) {
-    if (!P || which < 0 || which > 3) return PSW_EINVAL;
+    if (!P || which < 0 || which > 4) return PSW_EINVAL;
     DeviceGuard dg(P->device);
-    PassTiming &T = P->timing;
+    PassTiming &T = P->timing[which];
+    P->timing_last = which;
     if (enable && T.ev.empty()) {
         T.ev.assign(2 * PassTiming::kPool, nullptr);
         for (auto &e : T.ev)
@@ -1660,10 +1670,10 @@ psw_status psw_pass_timing_enable(psw_problem *P, int which, int enable) {
     return PSW_OK;
 }
 
-psw_status psw_pass_timing(psw_problem *P, double *mean_ms, int64_t *count) {
-    if (!P || !mean_ms || !count) return PSW_EINVAL;
+psw_status psw_pass_timing_of(psw_problem *P, int which, double *mean_ms, int64_t *count) {
+    if (!P || !mean_ms || !count || which < 0 || which > 4) return PSW_EINVAL;
     DeviceGuard dg(P->device);
-    PassTiming &T = P->timing;
+    PassTiming &T = P->timing[which];
     double sum = 0.0;
     for (int64_t i = 0; i < T.used; ++i) {
         float ms = 0.f;
@@ -1674,6 +1684,11 @@ psw_status psw_pass_timing(psw_problem *P, double *mean_ms, int64_t *count) {
     *count = T.used;
     *mean_ms = T.used ? sum / (double)T.used : 0.0;
     return PSW_OK;
+}
+
+psw_status psw_pass_timing(psw_problem *P, double *mean_ms, int64_t *count) {
+    if (!P) return PSW_EINVAL;
+    return psw_pass_timing_of(P, P->timing_last, mean_ms, count);
 }
 
 psw_status psw_autotune(int dim, const int64_t n[3], psw_prec prec, psw_precond kind, int p_out[3],

@@ -1643,8 +1643,10 @@ __global__ void __launch_bounds__(256) k_cg_pq2d(int n0, int n1, int nbx, int nt
         load_in(ra, (int64_t)min(j0 + 1, n1 - 1) * n0 + ic);
         load_op(oa, (int64_t)j0 * n0 + ic);
         for (int j = j0; j < j1; ++j) {
-            load_in(rb, (int64_t)min(j + 2, n1 - 1) * n0 + ic);
-            load_op(ob, (int64_t)min(j + 1, n1 - 1) * n0 + ic);
+            // read ahead, but never past what the strip uses (the new p of row j1, the operator of row j1 - 1):
+            // the clamped loads re-read a row already in cache
+            load_in(rb, (int64_t)min(j + 2, min(j1, n1 - 1)) * n0 + ic);
+            load_op(ob, (int64_t)min(j + 1, j1 - 1) * n0 + ic);
             double pp[V];
             form(ra, pp);
             const double sl = from_lower_lane(pc[V - 1]), sr = from_upper_lane(pc[0]); // every lane takes part

@@ -314,3 +314,15 @@ def test_pass_timing_records_launches():
     ms, cnt = g.pass_timing()
     g.pass_timing_enable(0, False)
     assert cnt == 3 and ms > 0.0  # launches 0, 8 and 16 of pass 0
+    # pass 1 and the fused CG step keep records of their own, timed in the same solve
+    g.pass_timing_enable(1, True)
+    g.pass_timing_enable(4, True)
+    u = torch.zeros_like(r)
+    info = g.solve("cg", "ilu0", r, u, rtol=1e-30, maxit=20, check=False)
+    assert info["iters"] == 20
+    ms1, n1 = g.pass_timing(1)
+    ms4, n4 = g.pass_timing(4)
+    g.pass_timing_enable(1, False)
+    g.pass_timing_enable(4, False)
+    assert n4 == 3 and ms4 > 0.0  # CG steps 0, 8 and 16
+    assert n1 == 3 and ms1 > 0.0  # 21 backward passes (the first before the loop): 0, 8, 16
