@@ -639,7 +639,8 @@ psw_status cg2d_fused(psw_problem *P, psw_precond kind, bool split, double rtol,
     const double *z1 = (split || kind != PSW_NONE) ? z : r;
     if ((ps = precond())) return ps;
     if (!P->hs.ensure()) return PSW_ENOMEM;
-    double *h = P->hs.p;
+    double *h = P->hs.p, *hdev = nullptr;
+    HIPCHK(hipHostGetDevicePointer((void **)&hdev, h, 0));
     PassTiming &T = P->timing[4];
     while (it < maxit) {
         // measurement aid (which = 4): events around every kStride-th fused step
@@ -653,11 +654,11 @@ psw_status cg2d_fused(psw_problem *P, psw_precond kind, bool split, double rtol,
         }
         std::swap(pa, pb);
         std::swap(s_rz, s_rz2);
-        HIPCHK(launch_cg_r(r, q, s_rz, part_pq, npq, out, N, st));
+        // p.q and the r.r partials also go straight to pinned host memory, read behind an event;
+        // the next preconditioner is queued before the host waits for them, so the device stays
+        // busy during the test
+        HIPCHK(launch_cg_r(r, q, s_rz, part_pq, npq, out, N, hdev, st));
         ++it;
-        // p.q and the r.r partials go to the host behind an event; the next preconditioner is
-        // queued before the host waits for them, so the device stays busy during the test
-        HIPCHK(hipMemcpyAsync(h, out, (2 + kRedBlocks) * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(hipEventRecord(P->hs.ev, st));
         if ((ps = precond())) return ps;
         HIPCHK(hipEventSynchronize(P->hs.ev));

@@ -122,9 +122,9 @@ hipError_t launch_cg_pq2d(int n0, int n1, const double *const *diag, const doubl
                           double *rz_new, const double *rz_old, const double *alpha_prev, bool first,
                           double *pq_part, int *npq, hipStream_t st);
 // r -= alpha q, alpha = rz[0] / (sum of npq partials); out[0] = p.q, out[1] = alpha,
-// out[2 .. 2 + kRedBlocks) = partials of r.r
+// out[2 .. 2 + kRedBlocks) = partials of r.r; the same to hout (device-visible pinned host memory) if given
 hipError_t launch_cg_r(double *r, const double *q, const double *rz, const double *pq_part, int npq, double *out,
-                       int64_t N, hipStream_t st);
+                       int64_t N, double *hout, hipStream_t st);
 hipError_t launch_copy_scaled(double *y, const double *x, double a, int64_t N, hipStream_t st);
 hipError_t launch_residual(int dim, const int n[3], const double *const *diag, const double *f,
                            const double *x, double *r, hipStream_t st);

@@ -1718,15 +1718,21 @@ hipError_t launch_cg_pq2d(int n0, int n1, const double *const *diag, const doubl
 }
 
 // r -= alpha q with alpha = rz / (sum of npq p.q partials); out[0] = p.q, out[1] = alpha,
-// out[2 + b] = block b's partial of r.r (kRedBlocks of them)
+// out[2 + b] = block b's partial of r.r (kRedBlocks of them).  The same values go to hout
+// (pinned host memory, device-visible) when given, for the host's stopping test.
 __global__ void __launch_bounds__(kRedThreads) k_cg_r(double *r, const double *q, const double *rz,
-                                                     const double *pq_part, int npq, double *out, int64_t N) {
+                                                     const double *pq_part, int npq, double *out, int64_t N,
+                                                     double *hout) {
     __shared__ double sh[kRedThreads];
     const double pq = wave_sum_partials(pq_part, npq);
     const double alpha = rz[0] / pq;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         out[0] = pq;
         out[1] = alpha;
+        if (hout) {
+            hout[0] = pq;
+            hout[1] = alpha;
+        }
     }
     double acc = 0.0;
     const int64_t stride = (int64_t)kRedBlocks * kRedThreads;
@@ -1736,12 +1742,15 @@ __global__ void __launch_bounds__(kRedThreads) k_cg_r(double *r, const double *q
         acc += ri * ri;
     }
     const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) out[2 + blockIdx.x] = s;
+    if (threadIdx.x == 0) {
+        out[2 + blockIdx.x] = s;
+        if (hout) hout[2 + blockIdx.x] = s;
+    }
 }
 
 hipError_t launch_cg_r(double *r, const double *q, const double *rz, const double *pq_part, int npq, double *out,
-                       int64_t N, hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_r, dim3(kRedBlocks), dim3(kRedThreads), 0, st, r, q, rz, pq_part, npq, out, N);
+                       int64_t N, double *hout, hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_r, dim3(kRedBlocks), dim3(kRedThreads), 0, st, r, q, rz, pq_part, npq, out, N, hout);
     return hipGetLastError();
 }
 
