@@ -477,8 +477,10 @@ psw_status half(psw_problem *P, psw_precond kind, int which, const void *in, boo
 
 // The symmetric form in two pieces for the CG loop (pipelined 2D passes only):
 // z1 = c (backward pass) and z2 = the transposed pair with its end faces, so
-// that z = 0.5 z1 + 0.5 c z2.  Both end-face fixes run on the side stream,
-// beside the forward and the backward pass; st has joined both on return.
+// that z = 0.5 z1 + 0.5 c z2.  The two chains are independent: the forward and
+// backward passes run on st, the transposed passes with their end faces on the
+// side stream beside them, with one fork and one join per application (every
+// cross-stream dependency costs a queue bubble).  st has joined on return.
 psw_status precond_sym_split(psw_problem *P, psw_precond kind, const double *r, double *z1, double *z2,
                              hipStream_t st) {
     PrecState &S = P->pc[kind];
@@ -486,19 +488,16 @@ psw_status precond_sym_split(psw_problem *P, psw_precond kind, const double *r, 
     if (!P->side.ensure()) return PSW_EDEVICE;
     const bool f64 = P->prec == PSW_F64;
     void *y1 = P->w_y.p, *y2 = P->w_y2.p;
+    hipStream_t ss = P->side.s;
     psw_status ps;
-    if ((ps = fast_pass(P, kind, 2, r, true, false, y2, f64, 1.0, nullptr, 0.0, st))) return ps;
     HIPCHK(hipEventRecord(P->side.fork, st));
-    HIPCHK(hipStreamWaitEvent(P->side.s, P->side.fork, 0));
-    if ((ps = fast_end(P, kind, 2, r, true, false, y2, f64, P->side.s))) return ps;
-    HIPCHK(hipEventRecord(P->side.join, P->side.s));
+    HIPCHK(hipStreamWaitEvent(ss, P->side.fork, 0));
+    if ((ps = fast_pass(P, kind, 2, r, true, false, y2, f64, 1.0, nullptr, 0.0, ss))) return ps;
+    if ((ps = fast_end(P, kind, 2, r, true, false, y2, f64, ss))) return ps;
+    if ((ps = fast_pass(P, kind, 3, y2, f64, true, z2, true, 1.0, nullptr, 0.0, ss))) return ps;
+    if ((ps = fast_end(P, kind, 3, y2, f64, true, z2, true, ss))) return ps;
+    HIPCHK(hipEventRecord(P->side.join, ss));
     if ((ps = fast_pass(P, kind, 0, r, true, false, y1, f64, 1.0, nullptr, 0.0, st))) return ps;
-    HIPCHK(hipStreamWaitEvent(st, P->side.join, 0));
-    if ((ps = fast_pass(P, kind, 3, y2, f64, true, z2, true, 1.0, nullptr, 0.0, st))) return ps;
-    HIPCHK(hipEventRecord(P->side.fork, st));
-    HIPCHK(hipStreamWaitEvent(P->side.s, P->side.fork, 0));
-    if ((ps = fast_end(P, kind, 3, y2, f64, true, z2, true, P->side.s))) return ps;
-    HIPCHK(hipEventRecord(P->side.join, P->side.s));
     if ((ps = fast_pass(P, kind, 1, y1, f64, true, z1, true, S.c, nullptr, 0.0, st))) return ps;
     HIPCHK(hipStreamWaitEvent(st, P->side.join, 0));
     return PSW_OK;
