@@ -427,15 +427,32 @@ def measure_roofline(g, N, args, stream, k_ms=None, k_n=None):
         k_ms, k_n = g.pass_timing()
         g.pass_timing_enable(0, False)
         how = "HIP events around every 8th pass-0 launch, the four passes running in turn"
+    else:
+        # inside CG the transposed passes run on a second stream beside this one and share the
+        # chip with it; the same kernel is also timed alone, back to back, after the timed solves
+        r = torch.randn(N, dtype=torch.float64, device=stream.device)
+        y = torch.empty_like(r)
+        for _ in range(4):
+            g.precond_half(args.precond, 0, r, y)
+        g.pass_timing_enable(0, True)
+        for k in range(8 * args.kernel_reps):
+            g.precond_half(args.precond, 0, r, y)
+        a_ms, a_n = g.pass_timing()
+        g.pass_timing_enable(0, False)
     bpp = {"f64": 40, "f32": 28, "bf16": 20}[args.prec]  # r(8) + Piv + 2 upstream couplings + y
     alg_bytes = bpp * N
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
     traffic = measured_traffic() if (args.prec == "f64" and args.n == 2048 and args.p == 16) else None
+    alone = {}
+    if how.endswith("inside the timed solves"):
+        alone = {"kernel_ms_alone": round(a_ms, 4), "timed_launches_alone": a_n,
+                 "frac_alone": round(alg_bytes / (a_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                 "timing_alone": "the same events around every 8th of back-to-back pass-0 launches after the timed solves"}
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "k_fast2d<2,double,...,SC=false,CPL=true> (forward start-coupled half-sweep)",
             "kernel_ms": round(k_ms, 4), "timed_launches": k_n, "timing": how, "bytes_per_point": bpp,
-            "algorithmic_bytes": alg_bytes}
+            "algorithmic_bytes": alg_bytes, **alone}
 
 
 def bench_poisson3d(args):

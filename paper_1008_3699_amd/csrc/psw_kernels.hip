@@ -94,6 +94,15 @@ __device__ __forceinline__ void ge_solve(T (&M)[NB][NB], T (&R)[NB]) {
     }
 }
 
+constexpr int kWave = 64;
+
+// Compiler-only ordering point between the levels of a loop run by one wave:
+// the wave's own LDS accesses take effect in issue order, so no wait is needed.
+__device__ __forceinline__ void wave_order() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // Workgroup barrier that orders LDS only: the waves wait for their own LDS
 // accesses, not for global stores in flight.  For level loops whose global
 // writes no thread of the workgroup reads back.
@@ -466,23 +475,48 @@ __global__ void __launch_bounds__(1024) k_start_faces3g(StartArgs<S, TIN, TOUT> 
 #pragma unroll
     for (int a = 0; a < 3; ++a)
         if (F.start_cpl[a]) nlev = max(nlev, len[0] + len[1] + len[2] - len[a] - 1);
+    // the points of level t on face a are (u, t - u) in the face's own (b, c) axes (b < c):
+    // thread k takes face k / Lm and u = k % Lm at every level, so no level scans the face.
+    // Only the waves that hold such threads stay; a barrier waits for surviving waves only,
+    // and with one wave left the LDS accesses take effect in issue order with no barrier.
+    const int Lm = max(len[0], max(len[1], len[2]));
+    const int nlt = min(nth, (3 * Lm + kWave - 1) / kWave * kWave);
+    if ((int)threadIdx.x >= nlt) return;
+    // ring slot of member B at (q1, q2), B varying over the lanes: the address by selects
+    auto rslot = [&](int B, int buf, int q1, int q2) -> T * {
+        T *base = B == 0 ? rg.own : B == 1 ? rg.xp : B == 2 ? rg.yp : B == 4 ? rg.zp : B == 3 ? rg.xyp : B == 5 ? rg.xzp : rg.yzp;
+        const int off = B <= 1 ? buf * rg.cmax + q1 + L1 * q2
+                      : (B == 2 || B == 3) ? buf * rg.l2max + q2 : (B == 4 || B == 5) ? buf * rg.l1max + q1 : buf;
+        return base + off;
+    };
+    const int scm = (F.start_cpl[0] ? 1 : 0) | (F.start_cpl[1] ? 2 : 0) | (F.start_cpl[2] ? 4 : 0);
+    const int scm0 = scm & 1, scm1 = (scm >> 1) & 1, scm2 = (scm >> 2) & 1;
     for (int t = 0; t < nlev; ++t) {
         const int cur = t & 1, prv = cur ^ 1;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            if (!F.start_cpl[a]) continue;
-            for (int j = threadIdx.x; j < nf[a]; j += nth) {
-                int l0, l1, l2, Am;
-                if (!point(a, j, l0, l1, l2, Am)) continue;
-                if (l0 + l1 + l2 != t) continue;
+        for (int k = threadIdx.x; k < 3 * Lm; k += nlt) {
+            {
+                const int a = k / Lm, u = k - a * Lm;
+                if (!((scm >> a) & 1)) continue;
+                const int lenb = a == 0 ? len[1] : len[0], lenc = a == 2 ? len[1] : len[2];
+                const int v = t - u;
+                if (u >= lenb || v < 0 || v >= lenc) continue;
+                const int l0 = a == 0 ? 0 : u, l1 = a == 1 ? 0 : (a == 0 ? u : v), l2 = a == 2 ? 0 : v;
+                const int j = u + v * lenb;
+                const int Am = (l0 == 0 ? scm0 : 0) | (l1 == 0 ? scm1 << 1 : 0) | (l2 == 0 ? scm2 << 2 : 0);
+                if (Am & ((1 << a) - 1)) continue; // owned by the lowest coupled face
                 const T *rc = rec_of(a, j, l0, l1, l2, Am);
                 // right-hand side of member B with the upstream values outside the block
+                // (the three slots are read whatever the weights: a slot is always finite, and a zero
+                // weight, in the block's own directions or where the upstream point does not exist,
+                // adds nothing; no branch keeps the reads apart)
                 auto rhs = [&](int B, const T *r4) -> T {
+                    const T v0 = *rslot(B, prv, l1, l2), v1 = *rslot(B, prv, max(l1 - 1, 0), l2),
+                            v2 = *rslot(B, prv, l1, max(l2 - 1, 0));
+                    const T w0 = (Am & 1) ? T(0) : r4[1], w1 = (Am & 2) ? T(0) : r4[2], w2 = (Am & 4) ? T(0) : r4[3];
                     T x = r4[0];
-                    // zero weight where the upstream point does not exist (the ring slot is finite)
-                    if (!(Am & 1)) x += r4[1] * *rg.slot(B, prv, l1, l2, L1);
-                    if (!(Am & 2)) x += r4[2] * *rg.slot(B, prv, max(l1 - 1, 0), l2, L1);
-                    if (!(Am & 4)) x += r4[3] * *rg.slot(B, prv, l1, max(l2 - 1, 0), L1);
+                    x += w0 * v0;
+                    x += w1 * v1;
+                    x += w2 * v2;
                     return x;
                 };
                 T x0;
@@ -493,7 +527,28 @@ __global__ void __launch_bounds__(1024) k_start_faces3g(StartArgs<S, TIN, TOUT> 
                     const T det = T(1) - m0 * mb;
                     x0 = (R0 - m0 * Rb) / det;
                     const T xb = (Rb - mb * R0) / det;
-                    *rg.slot(Am, cur, l1, l2, L1) = xb;
+                    *rslot(Am, cur, l1, l2) = xb;
+                } else if (Am != 7) {
+                    // edge: a 4x4 block over the two coupled axes qa < qb; member m is the point
+                    // shifted across qa if m & 1 and across qb if m & 2 (same elimination order
+                    // as the 8x8 form, whose other rows and columns are identity)
+                    const int qa = (Am & 1) ? 0 : 1, qb = (Am & 4) ? 2 : 1;
+                    T M[4][4], R[4];
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const int B = ((m & 1) << qa) | ((m >> 1) << qb);
+                        const T *r4 = rc + 4 * B;
+                        R[m] = rhs(B, r4);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) M[m][q] = (m == q) ? T(1) : T(0);
+                        M[m][m ^ 1] = -r4[1 + qa];
+                        M[m][m ^ 2] = -r4[1 + qb];
+                    }
+                    ge_solve<T, 4>(M, R);
+                    x0 = R[0];
+#pragma unroll
+                    for (int m = 1; m < 4; ++m)
+                        *rslot(((m & 1) << qa) | ((m >> 1) << qb), cur, l1, l2) = R[m];
                 } else {
                     T M[8][8], R[8];
 #pragma unroll
@@ -522,7 +577,8 @@ __global__ void __launch_bounds__(1024) k_start_faces3g(StartArgs<S, TIN, TOUT> 
                 A.out[lin(g.n, gp)] = (TOUT)((T)A.cscale * x0);
             }
         }
-        lds_barrier(); // out is written, never read back, inside the sweep
+        if (nlt > kWave) lds_barrier(); // out is written, never read back, inside the sweep
+        else wave_order();
     }
 }
 
@@ -790,11 +846,14 @@ __device__ __forceinline__ void end_face3g_body(const EndArgs<S, TIN, TOUT> &A, 
         }
     }
     __syncthreads();
+    if (threadIdx.x >= kWave) return; // level loop in wave 0 alone, as for the start faces
     const int nlev = nb + nc - 1;
     for (int t = 0; t < nlev; ++t) {
-        for (int j = threadIdx.x; j < np; j += nth) {
-            const int lb = j % nb, lc = j / nb;
-            if (lb + lc != t) continue;
+        // the points of level t: (lb, t - lb)
+        for (int lb = threadIdx.x; lb < nb; lb += kWave) {
+            const int lc = t - lb;
+            if (lc < 0 || lc >= nc) continue;
+            const int j = lb + lc * nb;
             const T *rc = rec + 8 * j;
             T R0 = rc[0], Rb = rc[4];
             if (lb > 0) {
@@ -822,7 +881,7 @@ __device__ __forceinline__ void end_face3g_body(const EndArgs<S, TIN, TOUT> &A, 
             gp[a] += F.d[a];
             A.out[lin(g.n, gp)] = (TOUT)xb;
         }
-        lds_barrier(); // out is written, never read back, inside this kernel
+        wave_order();
     }
 }
 
