@@ -475,13 +475,9 @@ __global__ void __launch_bounds__(1024) k_start_faces3g(StartArgs<S, TIN, TOUT> 
 #pragma unroll
     for (int a = 0; a < 3; ++a)
         if (F.start_cpl[a]) nlev = max(nlev, len[0] + len[1] + len[2] - len[a] - 1);
-    // the points of level t on face a are (u, t - u) in the face's own (b, c) axes (b < c):
-    // thread k takes face k / Lm and u = k % Lm at every level, so no level scans the face.
-    // Only the waves that hold such threads stay; a barrier waits for surviving waves only,
-    // and with one wave left the LDS accesses take effect in issue order with no barrier.
+    // The points of level t on face a are (u, t - u) in the face's own (b, c) axes (b < c).
+    // A barrier waits for the surviving waves only.
     const int Lm = max(len[0], max(len[1], len[2]));
-    const int nlt = min(nth, (3 * Lm + kWave - 1) / kWave * kWave);
-    if ((int)threadIdx.x >= nlt) return;
     // ring slot of member B at (q1, q2), B varying over the lanes: the address by selects
     auto rslot = [&](int B, int buf, int q1, int q2) -> T * {
         T *base = B == 0 ? rg.own : B == 1 ? rg.xp : B == 2 ? rg.yp : B == 4 ? rg.zp : B == 3 ? rg.xyp : B == 5 ? rg.xzp : rg.yzp;
@@ -491,91 +487,134 @@ __global__ void __launch_bounds__(1024) k_start_faces3g(StartArgs<S, TIN, TOUT> 
     };
     const int scm = (F.start_cpl[0] ? 1 : 0) | (F.start_cpl[1] ? 2 : 0) | (F.start_cpl[2] ? 4 : 0);
     const int scm0 = scm & 1, scm1 = (scm >> 1) & 1, scm2 = (scm >> 2) & 1;
+    // face a, position (u, v) -> local point, record index j and coupled-face mask Am
+    auto locate = [&](int a, int u, int v, int &l0, int &l1, int &l2, int &j) -> int {
+        const int lenb = a == 0 ? len[1] : len[0];
+        l0 = a == 0 ? 0 : u;
+        l1 = a == 1 ? 0 : (a == 0 ? u : v);
+        l2 = a == 2 ? 0 : v;
+        j = u + v * lenb;
+        return (l0 == 0 ? scm0 : 0) | (l1 == 0 ? scm1 << 1 : 0) | (l2 == 0 ? scm2 << 2 : 0);
+    };
+    // solve the block at one point of level t, write its ring slots and its output
+    auto solve_point = [&](int a, int j, int l0, int l1, int l2, int Am, int cur, int prv) {
+        const T *rc = rec_of(a, j, l0, l1, l2, Am);
+        // right-hand side of member B with the upstream values outside the block
+        // (the three slots are read whatever the weights: a slot is always finite, and a zero
+        // weight, in the block's own directions or where the upstream point does not exist,
+        // adds nothing; no branch keeps the reads apart)
+        auto rhs = [&](int B, const T *r4) -> T {
+            const T v0 = *rslot(B, prv, l1, l2), v1 = *rslot(B, prv, max(l1 - 1, 0), l2),
+                    v2 = *rslot(B, prv, l1, max(l2 - 1, 0));
+            const T w0 = (Am & 1) ? T(0) : r4[1], w1 = (Am & 2) ? T(0) : r4[2], w2 = (Am & 4) ? T(0) : r4[3];
+            T x = r4[0];
+            x += w0 * v0;
+            x += w1 * v1;
+            x += w2 * v2;
+            return x;
+        };
+        T x0;
+        if ((Am & (Am - 1)) == 0) {
+            const int bit = Am == 1 ? 0 : (Am == 2 ? 1 : 2);
+            const T R0 = rhs(0, rc), Rb = rhs(Am, rc + 4);
+            const T m0 = -rc[1 + bit], mb = -rc[4 + 1 + bit];
+            const T det = T(1) - m0 * mb;
+            x0 = (R0 - m0 * Rb) / det;
+            const T xb = (Rb - mb * R0) / det;
+            *rslot(Am, cur, l1, l2) = xb;
+        } else if (Am != 7) {
+            // edge: a 4x4 block over the two coupled axes qa < qb; member m is the point
+            // shifted across qa if m & 1 and across qb if m & 2 (same elimination order
+            // as the 8x8 form, whose other rows and columns are identity)
+            const int qa = (Am & 1) ? 0 : 1, qb = (Am & 4) ? 2 : 1;
+            T M[4][4], R[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int B = ((m & 1) << qa) | ((m >> 1) << qb);
+                const T *r4 = rc + 4 * B;
+                R[m] = rhs(B, r4);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) M[m][q] = (m == q) ? T(1) : T(0);
+                M[m][m ^ 1] = -r4[1 + qa];
+                M[m][m ^ 2] = -r4[1 + qb];
+            }
+            ge_solve<T, 4>(M, R);
+            x0 = R[0];
+#pragma unroll
+            for (int m = 1; m < 4; ++m)
+                *rslot(((m & 1) << qa) | ((m >> 1) << qb), cur, l1, l2) = R[m];
+        } else {
+            T M[8][8], R[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                R[i] = T(0);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) M[i][k] = (i == k) ? T(1) : T(0);
+            }
+#pragma unroll
+            for (int B = 0; B < 8; ++B) {
+                if (B & ~Am) continue;
+                const T *r4 = rc + 4 * B;
+                R[B] = rhs(B, r4);
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+                    if ((Am >> q) & 1) M[B][B ^ (1 << q)] = -r4[1 + q];
+            }
+            ge_solve<T, 8>(M, R);
+            x0 = R[0];
+#pragma unroll
+            for (int B = 1; B < 7; ++B)
+                if (!(B & ~Am)) *rg.slot(B, cur, l1, l2, L1) = R[B];
+        }
+        *rg.slot(0, cur, l1, l2, L1) = x0;
+        const int gp[3] = {F.base[0] + F.d[0] * l0, F.base[1] + F.d[1] * l1, F.base[2] + F.d[2] * l2};
+        A.out[lin(g.n, gp)] = (TOUT)((T)A.cscale * x0);
+    };
+
+    if (Lm <= kWave && nth >= 4 * kWave) {
+        // Waves 0-2 take the 2x2 blocks of faces 0-2 (lane u), wave 3 the 4x4 edge blocks (lane 0:
+        // the edge (0, 0, t), 1: (0, t, 0), 2: (t, 0, 0)) and the corner at level 0: every wave runs
+        // one block type, so a level costs the longest of them, not their sum.
+        const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+        if (w >= 4) return;
+        for (int t = 0; t < nlev; ++t) {
+            const int cur = t & 1, prv = cur ^ 1;
+            int l0, l1, l2, j;
+            if (w < 3) {
+                const int lenb = w == 0 ? len[1] : len[0], lenc = w == 2 ? len[1] : len[2];
+                const int v = t - lane;
+                if (((scm >> w) & 1) && lane < lenb && v >= 0 && v < lenc) {
+                    const int Am = locate(w, lane, v, l0, l1, l2, j);
+                    if ((Am & (Am - 1)) == 0) solve_point(w, j, l0, l1, l2, Am, cur, prv);
+                }
+            } else if (lane < 3 && (t > 0 || lane == 0)) {
+                const int a = lane == 2 ? 1 : 0, u = lane == 0 ? 0 : t, v = lane == 0 ? t : 0;
+                const int lim = lane == 0 ? len[2] : (lane == 1 ? len[1] : len[0]);
+                if (t < lim) {
+                    const int Am = locate(a, u, v, l0, l1, l2, j);
+                    if (Am & (Am - 1)) solve_point(a, j, l0, l1, l2, Am, cur, prv);
+                }
+            }
+            lds_barrier(); // out is written, never read back, inside the sweep
+        }
+        return;
+    }
+    // Any tile: thread k takes face k / Lm and u = k % Lm at every level.  Only the waves that
+    // hold such threads stay; with one wave left its LDS accesses take effect in issue order.
+    const int nlt = min(nth, (3 * Lm + kWave - 1) / kWave * kWave);
+    if ((int)threadIdx.x >= nlt) return;
     for (int t = 0; t < nlev; ++t) {
         const int cur = t & 1, prv = cur ^ 1;
         for (int k = threadIdx.x; k < 3 * Lm; k += nlt) {
-            {
-                const int a = k / Lm, u = k - a * Lm;
-                if (!((scm >> a) & 1)) continue;
-                const int lenb = a == 0 ? len[1] : len[0], lenc = a == 2 ? len[1] : len[2];
-                const int v = t - u;
-                if (u >= lenb || v < 0 || v >= lenc) continue;
-                const int l0 = a == 0 ? 0 : u, l1 = a == 1 ? 0 : (a == 0 ? u : v), l2 = a == 2 ? 0 : v;
-                const int j = u + v * lenb;
-                const int Am = (l0 == 0 ? scm0 : 0) | (l1 == 0 ? scm1 << 1 : 0) | (l2 == 0 ? scm2 << 2 : 0);
-                if (Am & ((1 << a) - 1)) continue; // owned by the lowest coupled face
-                const T *rc = rec_of(a, j, l0, l1, l2, Am);
-                // right-hand side of member B with the upstream values outside the block
-                // (the three slots are read whatever the weights: a slot is always finite, and a zero
-                // weight, in the block's own directions or where the upstream point does not exist,
-                // adds nothing; no branch keeps the reads apart)
-                auto rhs = [&](int B, const T *r4) -> T {
-                    const T v0 = *rslot(B, prv, l1, l2), v1 = *rslot(B, prv, max(l1 - 1, 0), l2),
-                            v2 = *rslot(B, prv, l1, max(l2 - 1, 0));
-                    const T w0 = (Am & 1) ? T(0) : r4[1], w1 = (Am & 2) ? T(0) : r4[2], w2 = (Am & 4) ? T(0) : r4[3];
-                    T x = r4[0];
-                    x += w0 * v0;
-                    x += w1 * v1;
-                    x += w2 * v2;
-                    return x;
-                };
-                T x0;
-                if ((Am & (Am - 1)) == 0) {
-                    const int bit = Am == 1 ? 0 : (Am == 2 ? 1 : 2);
-                    const T R0 = rhs(0, rc), Rb = rhs(Am, rc + 4);
-                    const T m0 = -rc[1 + bit], mb = -rc[4 + 1 + bit];
-                    const T det = T(1) - m0 * mb;
-                    x0 = (R0 - m0 * Rb) / det;
-                    const T xb = (Rb - mb * R0) / det;
-                    *rslot(Am, cur, l1, l2) = xb;
-                } else if (Am != 7) {
-                    // edge: a 4x4 block over the two coupled axes qa < qb; member m is the point
-                    // shifted across qa if m & 1 and across qb if m & 2 (same elimination order
-                    // as the 8x8 form, whose other rows and columns are identity)
-                    const int qa = (Am & 1) ? 0 : 1, qb = (Am & 4) ? 2 : 1;
-                    T M[4][4], R[4];
-#pragma unroll
-                    for (int m = 0; m < 4; ++m) {
-                        const int B = ((m & 1) << qa) | ((m >> 1) << qb);
-                        const T *r4 = rc + 4 * B;
-                        R[m] = rhs(B, r4);
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) M[m][q] = (m == q) ? T(1) : T(0);
-                        M[m][m ^ 1] = -r4[1 + qa];
-                        M[m][m ^ 2] = -r4[1 + qb];
-                    }
-                    ge_solve<T, 4>(M, R);
-                    x0 = R[0];
-#pragma unroll
-                    for (int m = 1; m < 4; ++m)
-                        *rslot(((m & 1) << qa) | ((m >> 1) << qb), cur, l1, l2) = R[m];
-                } else {
-                    T M[8][8], R[8];
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) {
-                        R[i] = T(0);
-#pragma unroll
-                        for (int k = 0; k < 8; ++k) M[i][k] = (i == k) ? T(1) : T(0);
-                    }
-#pragma unroll
-                    for (int B = 0; B < 8; ++B) {
-                        if (B & ~Am) continue;
-                        const T *r4 = rc + 4 * B;
-                        R[B] = rhs(B, r4);
-#pragma unroll
-                        for (int q = 0; q < 3; ++q)
-                            if ((Am >> q) & 1) M[B][B ^ (1 << q)] = -r4[1 + q];
-                    }
-                    ge_solve<T, 8>(M, R);
-                    x0 = R[0];
-#pragma unroll
-                    for (int B = 1; B < 7; ++B)
-                        if (!(B & ~Am)) *rg.slot(B, cur, l1, l2, L1) = R[B];
-                }
-                *rg.slot(0, cur, l1, l2, L1) = x0;
-                const int gp[3] = {F.base[0] + F.d[0] * l0, F.base[1] + F.d[1] * l1, F.base[2] + F.d[2] * l2};
-                A.out[lin(g.n, gp)] = (TOUT)((T)A.cscale * x0);
-            }
+            const int a = k / Lm, u = k - a * Lm;
+            if (!((scm >> a) & 1)) continue;
+            const int lenb = a == 0 ? len[1] : len[0], lenc = a == 2 ? len[1] : len[2];
+            const int v = t - u;
+            if (u >= lenb || v < 0 || v >= lenc) continue;
+            int l0, l1, l2, j;
+            const int Am = locate(a, u, v, l0, l1, l2, j);
+            if (Am & ((1 << a) - 1)) continue; // owned by the lowest coupled face
+            solve_point(a, j, l0, l1, l2, Am, cur, prv);
         }
         if (nlt > kWave) lds_barrier(); // out is written, never read back, inside the sweep
         else wave_order();
