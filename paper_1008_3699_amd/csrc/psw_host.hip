@@ -135,6 +135,8 @@ struct PrecState {
     bool tile3 = false;
     int len0max = 1;
     DevBuf t3pk[4], t3off;
+    DevBuf f3img[2];        // coefficient images of the coupled start faces, passes 0 and 1
+    bool f3ok[2] = {false, false};
 };
 
 struct psw_problem {
@@ -318,6 +320,7 @@ psw_status fast_setup(psw_problem *P, PrecState &S, hipStream_t st) {
 // 3D problems swept in FP32 whose tiles fit in LDS: pack the four passes' coefficients
 psw_status tile3_setup(psw_problem *P, PrecState &S, hipStream_t st) {
     S.tile3 = false;
+    S.f3ok[0] = S.f3ok[1] = false;
     if (P->dim != 3 || P->prec == PSW_F64 || P->cmax > 1024) return PSW_OK;
     const char *e = std::getenv("PSW_FORCE_GENERIC");
     if (e && e[0] == '1') return PSW_OK;
@@ -462,8 +465,20 @@ psw_status half(psw_problem *P, psw_precond kind, int which, const void *in, boo
         return fast_end(P, kind, which, in, in_f64, scale_by_piv, out, out_f64, st);
     }
     if (S.tile3) {
+        // the coupled start faces read their coefficients from an image written on first use
+        void *fimg = nullptr;
+        if (which <= 1) {
+            if (!S.f3ok[which]) {
+                const int64_t ne = faces3_image_elems(g, S.len0max, P->lds_limit);
+                if (ne > 0 && S.f3img[which].ensure(sizeof(float) * (size_t)ne)) {
+                    HIPCHK(launch_faces3_image(g, s, d, S.piv.p, S.len0max, P->lds_limit, S.f3img[which].p, st));
+                    S.f3ok[which] = true;
+                }
+            }
+            if (S.f3ok[which]) fimg = S.f3img[which].p;
+        }
         HIPCHK(launch_tile3(g, s, which <= 1, d, S.piv.p, S.t3pk[which].p, S.t3off.as<int64_t>(), S.len0max, in,
-                            in_f64, scale_by_piv, out, out_f64, which <= 1 ? cscale : 1.0, st));
+                            in_f64, scale_by_piv, out, out_f64, which <= 1 ? cscale : 1.0, fimg, st));
         if (which >= 2)
             HIPCHK(launch_end_fixups3(g, s, d, S.piv.p, in, in_f64, scale_by_piv, out, out_f64, S.len0max, st));
         return PSW_OK;

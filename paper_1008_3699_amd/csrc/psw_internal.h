@@ -64,7 +64,13 @@ hipError_t launch_pack3(const PassGeom &g, Store s, bool transposed, const doubl
 // end-coupled pass, to be followed by launch_end_fixups3
 hipError_t launch_tile3(const PassGeom &g, Store s, bool start, const void *const *diag, const void *piv,
                         const void *pk, const int64_t *poff, int len0max, const void *in, bool in_f64,
-                        bool scale_by_piv, void *out, bool out_f64, double cscale, hipStream_t st);
+                        bool scale_by_piv, void *out, bool out_f64, double cscale, void *fimg, hipStream_t st);
+// Coefficient image of the coupled start faces of a start-coupled pass (fimg above, or null):
+// its size in FP32 elements (0 if the face kernel with gathered records does not apply), and
+// the kernel that writes it from the pass's diagonals and pivots.
+int64_t faces3_image_elems(const PassGeom &g, int len0max, size_t lds_limit);
+hipError_t launch_faces3_image(const PassGeom &g, Store s, const void *const *diag, const void *piv, int len0max,
+                               size_t lds_limit, void *img, hipStream_t st);
 hipError_t launch_end_fixups3(const PassGeom &g, Store s, const void *const *diag, const void *piv, const void *in,
                               bool in_f64, bool scale_by_piv, void *out, bool out_f64, int len0max, hipStream_t st);
 

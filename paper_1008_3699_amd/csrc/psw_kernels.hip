@@ -164,6 +164,12 @@ template <typename S, typename TIN, typename TOUT> struct StartArgs {
     TOUT *out;
     double cscale;
     int faces_only; // solve only the coupled blocks at the start faces (they involve no interior point)
+    // coupled start faces with gathered records: 0 gather everything; 1 write the records'
+    // coefficient part (pivot in place of the right-hand side) to img and stop; 2 take the
+    // coefficient part from img and gather the right-hand sides only
+    int img_mode;
+    void *img;
+    int64_t img_stride; // elements per tile
 };
 
 template <int DIM, typename T, typename S, typename TIN, typename TOUT, bool STAT>
@@ -426,7 +432,7 @@ __global__ void __launch_bounds__(1024) k_start_faces3g(StartArgs<S, TIN, TOUT> 
         return recm + 32 * (e * lmax + pos);
     };
     // member B of the block at local point (l0, l1, l2): r = rhs / Piv, w[a] = coupling along a / Piv
-    auto gather = [&](int l0, int l1, int l2, int B, T *r4) {
+    auto gather = [&](int l0, int l1, int l2, int B, T *r4, bool coef_only) {
         const int l[3] = {l0, l1, l2};
         int gq[3], dq[3];
 #pragma unroll
@@ -438,9 +444,13 @@ __global__ void __launch_bounds__(1024) k_start_faces3g(StartArgs<S, TIN, TOUT> 
         const int64_t Q = lin(g.n, gq);
         const T D = ldv<T>(A.piv, Q);
         const T sc = T(1) / D;
-        T acc = ldv<T>(A.in, Q);
-        if (scale) acc *= D;
-        r4[0] = sc * acc;
+        if (coef_only) {
+            r4[0] = D;
+        } else {
+            T acc = ldv<T>(A.in, Q);
+            if (scale) acc *= D;
+            r4[0] = sc * acc;
+        }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const int su = -dq[a];
@@ -450,22 +460,54 @@ __global__ void __launch_bounds__(1024) k_start_faces3g(StartArgs<S, TIN, TOUT> 
         }
     };
 
-    // ---- gather
+    // the right-hand side of member B from its pivot, left in r4[0] by the coefficient image
+    // (the same operations as in gather)
+    auto fill_rhs = [&](int l0, int l1, int l2, int B, T *r4) {
+        const int gq[3] = {F.base[0] + F.d[0] * l0 - (((B >> 0) & 1) ? F.d[0] : 0),
+                           F.base[1] + F.d[1] * l1 - (((B >> 1) & 1) ? F.d[1] : 0),
+                           F.base[2] + F.d[2] * l2 - (((B >> 2) & 1) ? F.d[2] : 0)};
+        const T D = r4[0];
+        const T sc = T(1) / D;
+        T acc = ldv<T>(A.in, lin(g.n, gq));
+        if (scale) acc *= D;
+        r4[0] = sc * acc;
+    };
+    // every member of every block owned by this tile's coupled start faces
+    auto members = [&](auto fn) {
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        if (!F.start_cpl[a]) continue;
-        for (int j = threadIdx.x; j < nf[a]; j += nth) {
-            int l0, l1, l2, Am;
-            if (!point(a, j, l0, l1, l2, Am)) continue;
-            T *rc = rec_of(a, j, l0, l1, l2, Am);
-            if ((Am & (Am - 1)) == 0) {
-                gather(l0, l1, l2, 0, rc);
-                gather(l0, l1, l2, Am, rc + 4);
-            } else {
+        for (int a = 0; a < 3; ++a) {
+            if (!F.start_cpl[a]) continue;
+            for (int j = threadIdx.x; j < nf[a]; j += nth) {
+                int l0, l1, l2, Am;
+                if (!point(a, j, l0, l1, l2, Am)) continue;
+                T *rc = rec_of(a, j, l0, l1, l2, Am);
+                if ((Am & (Am - 1)) == 0) {
+                    fn(l0, l1, l2, 0, rc);
+                    fn(l0, l1, l2, Am, rc + 4);
+                } else {
 #pragma unroll
-                for (int B = 0; B < 8; ++B)
-                    if (!(B & ~Am)) gather(l0, l1, l2, B, rc + 4 * B);
+                    for (int B = 0; B < 8; ++B)
+                        if (!(B & ~Am)) fn(l0, l1, l2, B, rc + 4 * B);
+                }
             }
+        }
+    };
+
+    // ---- gather
+    const int nrec = faces3_rec_floats(len[0], len[1], len[2], lmax);
+    T *img = A.img_mode ? reinterpret_cast<T *>(A.img) + (int64_t)blockIdx.x * A.img_stride : nullptr;
+    if (A.img_mode == 2) {
+        // the coefficients as stored (one contiguous read per tile), then the right-hand sides
+        for (int i = threadIdx.x; i < nrec; i += nth) rec1[i] = img[i];
+        __syncthreads();
+        members([&](int l0, int l1, int l2, int B, T *r4) { fill_rhs(l0, l1, l2, B, r4); });
+    } else {
+        const bool coef_only = A.img_mode == 1;
+        members([&](int l0, int l1, int l2, int B, T *r4) { gather(l0, l1, l2, B, r4, coef_only); });
+        if (coef_only) {
+            __syncthreads();
+            for (int i = threadIdx.x; i < nrec; i += nth) img[i] = rec1[i];
+            return;
         }
     }
     __syncthreads();
@@ -1168,7 +1210,7 @@ hipError_t launch_sweep_stationary(const PassGeom &g, const double *const *diag,
 template <typename T, typename S, typename TIN, typename TOUT>
 static hipError_t start_impl(const PassGeom &g, const void *const *diag, const void *piv, const void *in,
                              bool scale_by_piv, void *out, double cscale, hipStream_t st, bool faces_only = false,
-                             int len0max = 0, size_t lds_limit = 0) {
+                             int len0max = 0, size_t lds_limit = 0, void *img = nullptr, int img_mode = 0) {
     StartArgs<S, TIN, TOUT> A{};
     A.faces_only = faces_only ? 1 : 0;
     A.g = g;
@@ -1189,10 +1231,16 @@ static hipError_t start_impl(const PassGeom &g, const void *const *diag, const v
         const int lmax = std::max(len0max, std::max(g.l1max, g.l2max));
         const int fmax = faces3_rec_floats(len0max, g.l1max, g.l2max, lmax);
         const size_t smg = faces3_lds_bytes(g, fmax, sizeof(T));
-        if (len0max > 0 && smg <= lds_limit)
+        if (len0max > 0 && smg <= lds_limit) {
+            A.img_mode = img ? img_mode : 0;
+            A.img = img;
+            A.img_stride = fmax;
             hipLaunchKernelGGL((k_start_faces3g<T, S, TIN, TOUT>), grid, dim3(nth), smg, st, A, lmax);
-        else
+        } else if (img_mode == 1) {
+            return hipErrorNotSupported; // no gathered-record kernel for these tiles: no image
+        } else {
             hipLaunchKernelGGL((k_start_faces3<T, S, TIN, TOUT>), grid, dim3(nth), sm, st, A);
+        }
     }
     else
         hipLaunchKernelGGL((k_sweep_start<3, T, S, TIN, TOUT, false>), grid, blk, sm, st, A);
@@ -2121,7 +2169,7 @@ size_t pack3_slot_bytes(Store s) { return s == Store::F32 ? sizeof(Pk3<float>) :
 template <typename S, typename TIN, typename TOUT>
 static hipError_t tile3_impl(const PassGeom &g, bool start, const void *const *diag, const void *piv, const void *pk,
                              const int64_t *poff, int len0max, const void *in, bool scale_by_piv, void *out,
-                             double cscale, hipStream_t st) {
+                             double cscale, void *fimg, hipStream_t st) {
     int dev = 0, lds = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
@@ -2143,7 +2191,8 @@ static hipError_t tile3_impl(const PassGeom &g, bool start, const void *const *d
     if (start) {
         // the coupled start faces first (level kernel, faces only, unscaled into out)
         hipError_t e =
-            start_impl<float, S, TIN, TOUT>(g, diag, piv, in, scale_by_piv, out, 1.0, st, true, len0max, (size_t)lds);
+            start_impl<float, S, TIN, TOUT>(g, diag, piv, in, scale_by_piv, out, 1.0, st, true, len0max, (size_t)lds,
+                                            fimg, 2);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_tile3<float, S, TIN, TOUT, true>), dim3(g.ntiles), dim3(nth), sm, st, A);
     }
@@ -2154,10 +2203,10 @@ static hipError_t tile3_impl(const PassGeom &g, bool start, const void *const *d
 
 hipError_t launch_tile3(const PassGeom &g, Store s, bool start, const void *const *diag, const void *piv,
                         const void *pk, const int64_t *poff, int len0max, const void *in, bool in_f64,
-                        bool scale_by_piv, void *out, bool out_f64, double cscale, hipStream_t st) {
+                        bool scale_by_piv, void *out, bool out_f64, double cscale, void *fimg, hipStream_t st) {
     if (g.dim != 3 || s == Store::F64) return hipErrorInvalidValue;
 #define PSW_T3(S, TIN, TOUT) \
-    tile3_impl<S, TIN, TOUT>(g, start, diag, piv, pk, poff, len0max, in, scale_by_piv, out, cscale, st)
+    tile3_impl<S, TIN, TOUT>(g, start, diag, piv, pk, poff, len0max, in, scale_by_piv, out, cscale, fimg, st)
     if (s == Store::F32) {
         if (in_f64 && !out_f64) return PSW_T3(float, double, float);
         if (!in_f64 && out_f64) return PSW_T3(float, float, double);
@@ -2169,6 +2218,28 @@ hipError_t launch_tile3(const PassGeom &g, Store s, bool start, const void *cons
     if (in_f64 && out_f64) return PSW_T3(uint16_t, double, double);
     return PSW_T3(uint16_t, float, float);
 #undef PSW_T3
+}
+
+// Elements of the coefficient image of a start-coupled 3D pass (all tiles), 0 if the
+// gathered-record face kernel does not apply to these tiles.
+int64_t faces3_image_elems(const PassGeom &g, int len0max, size_t lds_limit) {
+    if (g.dim != 3 || g.cmax > 1024 || len0max <= 0) return 0;
+    const int lmax = std::max(len0max, std::max(g.l1max, g.l2max));
+    const int fmax = faces3_rec_floats(len0max, g.l1max, g.l2max, lmax);
+    if (faces3_lds_bytes(g, fmax, sizeof(float)) > lds_limit) return 0;
+    return (int64_t)fmax * g.ntiles;
+}
+
+// Write the coefficient image of a start-coupled 3D pass: per tile, the records of its
+// coupled start faces with the pivot where the right-hand side goes (FP32 sweeps).
+hipError_t launch_faces3_image(const PassGeom &g, Store s, const void *const *diag, const void *piv, int len0max,
+                               size_t lds_limit, void *img, hipStream_t st) {
+    if (g.dim != 3 || s == Store::F64 || !img) return hipErrorInvalidValue;
+    if (s == Store::F32)
+        return start_impl<float, float, double, double>(g, diag, piv, nullptr, false, nullptr, 1.0, st, true, len0max,
+                                                        lds_limit, img, 1);
+    return start_impl<float, uint16_t, double, double>(g, diag, piv, nullptr, false, nullptr, 1.0, st, true, len0max,
+                                                       lds_limit, img, 1);
 }
 
 // the coupled end faces, edges and corners of an end-coupled 3D pass (after its interior)
