@@ -137,6 +137,8 @@ struct PrecState {
     DevBuf t3pk[4], t3off;
     DevBuf f3img[2];        // coefficient images of the coupled start faces, passes 0 and 1
     bool f3ok[2] = {false, false};
+    DevBuf e3img[2];        // coefficient images of the coupled end faces, passes 2 and 3
+    bool e3ok[2] = {false, false};
 };
 
 struct psw_problem {
@@ -321,6 +323,7 @@ psw_status fast_setup(psw_problem *P, PrecState &S, hipStream_t st) {
 psw_status tile3_setup(psw_problem *P, PrecState &S, hipStream_t st) {
     S.tile3 = false;
     S.f3ok[0] = S.f3ok[1] = false;
+    S.e3ok[0] = S.e3ok[1] = false;
     if (P->dim != 3 || P->prec == PSW_F64 || P->cmax > 1024) return PSW_OK;
     const char *e = std::getenv("PSW_FORCE_GENERIC");
     if (e && e[0] == '1') return PSW_OK;
@@ -479,8 +482,18 @@ psw_status half(psw_problem *P, psw_precond kind, int which, const void *in, boo
         }
         HIPCHK(launch_tile3(g, s, which <= 1, d, S.piv.p, S.t3pk[which].p, S.t3off.as<int64_t>(), S.len0max, in,
                             in_f64, scale_by_piv, out, out_f64, which <= 1 ? cscale : 1.0, fimg, st));
-        if (which >= 2)
-            HIPCHK(launch_end_fixups3(g, s, d, S.piv.p, in, in_f64, scale_by_piv, out, out_f64, S.len0max, st));
+        if (which >= 2) {
+            const int e = which - 2;
+            if (!S.e3ok[e]) {
+                const int64_t ne = end_faces3_image_elems(g, S.len0max, P->lds_limit);
+                if (ne > 0 && S.e3img[e].ensure(sizeof(float) * (size_t)ne)) {
+                    HIPCHK(launch_end_faces3_image(g, s, d, S.piv.p, S.len0max, P->lds_limit, S.e3img[e].p, st));
+                    S.e3ok[e] = true;
+                }
+            }
+            HIPCHK(launch_end_fixups3(g, s, d, S.piv.p, in, in_f64, scale_by_piv, out, out_f64, S.len0max,
+                                      S.e3ok[e] ? S.e3img[e].p : nullptr, st));
+        }
         return PSW_OK;
     }
     if (which <= 1)

@@ -72,7 +72,12 @@ int64_t faces3_image_elems(const PassGeom &g, int len0max, size_t lds_limit);
 hipError_t launch_faces3_image(const PassGeom &g, Store s, const void *const *diag, const void *piv, int len0max,
                                size_t lds_limit, void *img, hipStream_t st);
 hipError_t launch_end_fixups3(const PassGeom &g, Store s, const void *const *diag, const void *piv, const void *in,
-                              bool in_f64, bool scale_by_piv, void *out, bool out_f64, int len0max, hipStream_t st);
+                              bool in_f64, bool scale_by_piv, void *out, bool out_f64, int len0max, void *eimg,
+                              hipStream_t st);
+// Coefficient image of the coupled end faces of an end-coupled pass (eimg above, or null).
+int64_t end_faces3_image_elems(const PassGeom &g, int len0max, size_t lds_limit);
+hipError_t launch_end_faces3_image(const PassGeom &g, Store s, const void *const *diag, const void *piv, int len0max,
+                                   size_t lds_limit, void *img, hipStream_t st);
 
 // ILU(0) pivots of the decomposed factorisation, FP64.
 hipError_t launch_ilu_pivots(const PassGeom &g, const double *const *diag, double *piv, int *bad,

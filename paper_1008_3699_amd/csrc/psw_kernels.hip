@@ -675,6 +675,12 @@ template <typename S, typename TIN, typename TOUT> struct EndArgs {
     const TIN *in;
     int scale_by_piv;
     TOUT *out;
+    // end faces with gathered records: 0 gather everything; 1 write the coefficient part of the
+    // records (pivot in place of the right-hand side, then each member's coupling to its
+    // upstream point across the face axis) to img and stop; 2 take it from img
+    int img_mode;
+    void *img;
+    int64_t img_stride; // elements per (tile, face)
 };
 
 // Interior phase: x_P = (b_P + sum_{R upstream of P in its tile} a_{R->P} x_R) / Piv_P,
@@ -874,6 +880,14 @@ __device__ __forceinline__ void end_face3g_body(const EndArgs<S, TIN, TOUT> &A, 
     T *rec = reinterpret_cast<T *>(smem); // 8 values per point
     T *vP = rec + 8 * np, *vQ = vP + np;   // solved values of the P and Q planes
     const int nth = blockDim.x;
+    T *img = A.img_mode ? reinterpret_cast<T *>(A.img) + (int64_t)blockIdx.x * A.img_stride : nullptr;
+    T *cup = img ? img + 8 * np : nullptr; // coupling to the upstream point across AX, 2 per point
+    if (A.img_mode == 2)
+        for (int i = threadIdx.x; i < 8 * np; i += nth) rec[i] = img[i];
+    // the records of point j: mode 0 gathers them into LDS, mode 1 writes their coefficient part to
+    // the image, mode 2 completes the right-hand sides of the records copied from it
+    T *const rdst = A.img_mode == 1 ? img : rec;
+    if (A.img_mode == 2) __syncthreads();
     for (int j = threadIdx.x; j < np; j += nth) {
         int l[3];
         l[a] = F.len[a] - 1;
@@ -882,7 +896,7 @@ __device__ __forceinline__ void end_face3g_body(const EndArgs<S, TIN, TOUT> &A, 
         int gp[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) gp[q] = F.base[q] + F.d[q] * l[q];
-        T *rc = rec + 8 * j;
+        T *rc = rdst + 8 * j;
 #pragma unroll
         for (int m = 0; m < 2; ++m) {
             int gq[3] = {gp[0], gp[1], gp[2]}, dq[3] = {F.d[0], F.d[1], F.d[2]};
@@ -891,15 +905,25 @@ __device__ __forceinline__ void end_face3g_body(const EndArgs<S, TIN, TOUT> &A, 
                 dq[a] = -F.d[a];
             }
             const int64_t Q = lin(g.n, gq);
+            int r[3] = {gq[0], gq[1], gq[2]};
+            r[a] -= dq[a];
+            const int64_t Ri = lin(g.n, r);
+            if (A.img_mode == 2) {
+                const T D = rc[4 * m + 0];
+                T acc = ldv<T>(A.in, Q);
+                if (A.scale_by_piv) acc *= D;
+                acc += cup[2 * j + m] * ldv<T>(A.out, Ri);
+                rc[4 * m + 0] = acc / D;
+                continue;
+            }
             const T D = ldv<T>(A.piv, Q);
-            T acc = ldv<T>(A.in, Q);
-            if (A.scale_by_piv) acc *= D;
             // the upstream point across AX (inside the member's own tile, final)
-            {
-                int r[3] = {gq[0], gq[1], gq[2]};
-                r[a] -= dq[a];
-                const int64_t Ri = lin(g.n, r);
-                acc += ldv<T>(A.diag[dk(a, dq[a])], Ri) * ldv<T>(A.out, Ri);
+            const T cu = ldv<T>(A.diag[dk(a, dq[a])], Ri);
+            T acc = T(0);
+            if (A.img_mode == 0) {
+                acc = ldv<T>(A.in, Q);
+                if (A.scale_by_piv) acc *= D;
+                acc += cu * ldv<T>(A.out, Ri);
             }
             // cross coupling to the block mate
             T mx;
@@ -920,12 +944,14 @@ __device__ __forceinline__ void end_face3g_body(const EndArgs<S, TIN, TOUT> &A, 
                 r[c] -= dq[c];
                 wc = ldv<T>(A.diag[dk(c, dq[c])], lin(g.n, r)) / D;
             }
-            rc[4 * m + 0] = acc / D;
+            rc[4 * m + 0] = A.img_mode == 1 ? D : acc / D;
             rc[4 * m + 1] = wb;
             rc[4 * m + 2] = wc;
             rc[4 * m + 3] = mx;
+            if (A.img_mode == 1) cup[2 * j + m] = cu;
         }
     }
+    if (A.img_mode == 1) return;
     __syncthreads();
     if (threadIdx.x >= kWave) return; // level loop in wave 0 alone, as for the start faces
     const int nlev = nb + nc - 1;
@@ -1275,7 +1301,7 @@ static hipError_t end_impl(const PassGeom &g, const void *const *diag, const voi
 template <typename T, typename S, typename TIN, typename TOUT>
 static hipError_t end_part_impl(const PassGeom &g, const void *const *diag, const void *piv, const void *in,
                                 bool scale_by_piv, void *out, int part, hipStream_t st, int len0max = 0,
-                                size_t lds_limit = 0) {
+                                size_t lds_limit = 0, void *img = nullptr, int img_mode = 0) {
     EndArgs<S, TIN, TOUT> A{};
     A.g = g;
     for (int k = 0; k < 2 * g.dim + 1; ++k) A.diag[k] = (const S *)diag[k];
@@ -1297,11 +1323,26 @@ static hipError_t end_part_impl(const PassGeom &g, const void *const *diag, cons
         if (g.dim != 3) return hipErrorInvalidValue;
         // largest end face: every face has at most max(len_b len_c) points
         const int fmax = std::max(g.l1max * g.l2max, len0max * std::max(g.l1max, g.l2max));
-        if (len0max > 0 && fmax <= 1024 && 10 * (size_t)fmax * sizeof(T) <= lds_limit)
+        const bool gathered = len0max > 0 && fmax <= 1024 && 10 * (size_t)fmax * sizeof(T) <= lds_limit;
+        if (img_mode == 1) {
+            // only the coefficient image of the gathered-record kernel
+            if (!gathered || !img) return hipErrorNotSupported;
+            A.img_mode = 1;
+            A.img = img;
+            A.img_stride = 10 * (int64_t)fmax;
             hipLaunchKernelGGL((k_end_faces3g<T, S, TIN, TOUT>), dim3(g.ntiles * 3),
                                dim3(std::max(64, (fmax + 63) / 64 * 64)), 10 * (size_t)fmax * sizeof(T), st, A);
-        else
+            return hipGetLastError();
+        }
+        if (gathered) {
+            A.img_mode = img ? 2 : 0;
+            A.img = img;
+            A.img_stride = 10 * (int64_t)fmax;
+            hipLaunchKernelGGL((k_end_faces3g<T, S, TIN, TOUT>), dim3(g.ntiles * 3),
+                               dim3(std::max(64, (fmax + 63) / 64 * 64)), 10 * (size_t)fmax * sizeof(T), st, A);
+        } else {
             hipLaunchKernelGGL((k_end_faces<3, T, S, TIN, TOUT>), dim3(g.ntiles * 3), dim3(64), 0, st, A);
+        }
         const int lmax = std::max(len0max, std::max(g.l1max, g.l2max));
         if (len0max > 0 && 16 * (size_t)lmax * sizeof(T) <= lds_limit)
             hipLaunchKernelGGL((k_end_edges3g<T, S, TIN, TOUT>), dim3(g.ntiles * 3), dim3(64),
@@ -1315,21 +1356,21 @@ static hipError_t end_part_impl(const PassGeom &g, const void *const *diag, cons
 
 static hipError_t end_part(const PassGeom &g, Store s, const void *const *diag, const void *piv, const void *in,
                            bool in_f64, bool scale_by_piv, void *out, bool out_f64, int part, hipStream_t st,
-                           int len0max = 0, size_t lds_limit = 0) {
+                           int len0max = 0, size_t lds_limit = 0, void *img = nullptr, int img_mode = 0) {
     if (s == Store::F64) {
         if (!in_f64 || !out_f64) return hipErrorInvalidValue;
-        return end_part_impl<double, double, double, double>(g, diag, piv, in, scale_by_piv, out, part, st, len0max, lds_limit);
+        return end_part_impl<double, double, double, double>(g, diag, piv, in, scale_by_piv, out, part, st, len0max, lds_limit, img, img_mode);
     }
     if (s == Store::F32) {
-        if (in_f64 && !out_f64) return end_part_impl<float, float, double, float>(g, diag, piv, in, scale_by_piv, out, part, st, len0max, lds_limit);
-        if (!in_f64 && !out_f64) return end_part_impl<float, float, float, float>(g, diag, piv, in, scale_by_piv, out, part, st, len0max, lds_limit);
-        if (in_f64 && out_f64) return end_part_impl<float, float, double, double>(g, diag, piv, in, scale_by_piv, out, part, st, len0max, lds_limit);
-        return end_part_impl<float, float, float, double>(g, diag, piv, in, scale_by_piv, out, part, st, len0max, lds_limit);
+        if (in_f64 && !out_f64) return end_part_impl<float, float, double, float>(g, diag, piv, in, scale_by_piv, out, part, st, len0max, lds_limit, img, img_mode);
+        if (!in_f64 && !out_f64) return end_part_impl<float, float, float, float>(g, diag, piv, in, scale_by_piv, out, part, st, len0max, lds_limit, img, img_mode);
+        if (in_f64 && out_f64) return end_part_impl<float, float, double, double>(g, diag, piv, in, scale_by_piv, out, part, st, len0max, lds_limit, img, img_mode);
+        return end_part_impl<float, float, float, double>(g, diag, piv, in, scale_by_piv, out, part, st, len0max, lds_limit, img, img_mode);
     }
-    if (in_f64 && !out_f64) return end_part_impl<float, uint16_t, double, float>(g, diag, piv, in, scale_by_piv, out, part, st, len0max, lds_limit);
-    if (!in_f64 && !out_f64) return end_part_impl<float, uint16_t, float, float>(g, diag, piv, in, scale_by_piv, out, part, st, len0max, lds_limit);
-    if (in_f64 && out_f64) return end_part_impl<float, uint16_t, double, double>(g, diag, piv, in, scale_by_piv, out, part, st, len0max, lds_limit);
-    return end_part_impl<float, uint16_t, float, double>(g, diag, piv, in, scale_by_piv, out, part, st, len0max, lds_limit);
+    if (in_f64 && !out_f64) return end_part_impl<float, uint16_t, double, float>(g, diag, piv, in, scale_by_piv, out, part, st, len0max, lds_limit, img, img_mode);
+    if (!in_f64 && !out_f64) return end_part_impl<float, uint16_t, float, float>(g, diag, piv, in, scale_by_piv, out, part, st, len0max, lds_limit, img, img_mode);
+    if (in_f64 && out_f64) return end_part_impl<float, uint16_t, double, double>(g, diag, piv, in, scale_by_piv, out, part, st, len0max, lds_limit, img, img_mode);
+    return end_part_impl<float, uint16_t, float, double>(g, diag, piv, in, scale_by_piv, out, part, st, len0max, lds_limit, img, img_mode);
 }
 
 hipError_t launch_end_corners(const PassGeom &g, Store s, const void *const *diag, const void *piv, const void *in,
@@ -2244,12 +2285,27 @@ hipError_t launch_faces3_image(const PassGeom &g, Store s, const void *const *di
 
 // the coupled end faces, edges and corners of an end-coupled 3D pass (after its interior)
 hipError_t launch_end_fixups3(const PassGeom &g, Store s, const void *const *diag, const void *piv, const void *in,
-                              bool in_f64, bool scale_by_piv, void *out, bool out_f64, int len0max, hipStream_t st) {
+                              bool in_f64, bool scale_by_piv, void *out, bool out_f64, int len0max, void *eimg,
+                              hipStream_t st) {
     int dev = 0, lds = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
         lds = 0;
-    return end_part(g, s, diag, piv, in, in_f64, scale_by_piv, out, out_f64, 2, st, len0max, (size_t)lds);
+    return end_part(g, s, diag, piv, in, in_f64, scale_by_piv, out, out_f64, 2, st, len0max, (size_t)lds, eimg,
+                    eimg ? 2 : 0);
+}
+
+int64_t end_faces3_image_elems(const PassGeom &g, int len0max, size_t lds_limit) {
+    if (g.dim != 3 || len0max <= 0) return 0;
+    const int fmax = std::max(g.l1max * g.l2max, len0max * std::max(g.l1max, g.l2max));
+    if (fmax > 1024 || 10 * (size_t)fmax * sizeof(float) > lds_limit) return 0;
+    return 10 * (int64_t)fmax * g.ntiles * 3;
+}
+
+hipError_t launch_end_faces3_image(const PassGeom &g, Store s, const void *const *diag, const void *piv, int len0max,
+                                   size_t lds_limit, void *img, hipStream_t st) {
+    if (g.dim != 3 || s == Store::F64 || !img) return hipErrorInvalidValue;
+    return end_part(g, s, diag, piv, nullptr, true, false, nullptr, true, 2, st, len0max, lds_limit, img, 1);
 }
 
 } // namespace psw
