@@ -355,6 +355,27 @@ psw_status tile3_setup(psw_problem *P, PrecState &S, hipStream_t st) {
         HIPCHK(launch_pack3(geom(P, sig), s, w >= 2, d, S.piv64.as<double>(), S.t3off.as<int64_t>(), S.t3pk[w].p,
                             st));
     }
+    // coefficient images of the coupled faces, from the sweep-precision diagonals and pivots:
+    // the start faces of passes 0 and 1, the end faces of passes 2 and 3 (none where the face
+    // kernels with gathered records do not apply; those passes gather everything)
+    const void *ds[7];
+    for (int k = 0; k < 7; ++k) ds[k] = S.diag[k].p;
+    for (int w = 0; w < 4; ++w) {
+        pass_sig(P, w, sig);
+        const PassGeom g = geom(P, sig);
+        const int e = w & 1;
+        DevBuf &img = w <= 1 ? S.f3img[e] : S.e3img[e];
+        bool &ok = w <= 1 ? S.f3ok[e] : S.e3ok[e];
+        const int64_t ne = w <= 1 ? faces3_image_elems(g, len0max, P->lds_limit)
+                                  : end_faces3_image_elems(g, len0max, P->lds_limit);
+        if (ne <= 0) continue;
+        if (!img.ensure(sizeof(float) * (size_t)ne)) return PSW_ENOMEM;
+        if (w <= 1)
+            HIPCHK(launch_faces3_image(g, s, ds, S.piv.p, len0max, P->lds_limit, img.p, st));
+        else
+            HIPCHK(launch_end_faces3_image(g, s, ds, S.piv.p, len0max, P->lds_limit, img.p, st));
+        ok = true;
+    }
     S.len0max = len0max;
     S.tile3 = true;
     return PSW_OK;
@@ -468,32 +489,13 @@ psw_status half(psw_problem *P, psw_precond kind, int which, const void *in, boo
         return fast_end(P, kind, which, in, in_f64, scale_by_piv, out, out_f64, st);
     }
     if (S.tile3) {
-        // the coupled start faces read their coefficients from an image written on first use
-        void *fimg = nullptr;
-        if (which <= 1) {
-            if (!S.f3ok[which]) {
-                const int64_t ne = faces3_image_elems(g, S.len0max, P->lds_limit);
-                if (ne > 0 && S.f3img[which].ensure(sizeof(float) * (size_t)ne)) {
-                    HIPCHK(launch_faces3_image(g, s, d, S.piv.p, S.len0max, P->lds_limit, S.f3img[which].p, st));
-                    S.f3ok[which] = true;
-                }
-            }
-            if (S.f3ok[which]) fimg = S.f3img[which].p;
-        }
+        // the coupled faces read the coefficient part of their records from the images of tile3_setup
+        void *fimg = which <= 1 && S.f3ok[which] ? S.f3img[which].p : nullptr;
         HIPCHK(launch_tile3(g, s, which <= 1, d, S.piv.p, S.t3pk[which].p, S.t3off.as<int64_t>(), S.len0max, in,
                             in_f64, scale_by_piv, out, out_f64, which <= 1 ? cscale : 1.0, fimg, st));
-        if (which >= 2) {
-            const int e = which - 2;
-            if (!S.e3ok[e]) {
-                const int64_t ne = end_faces3_image_elems(g, S.len0max, P->lds_limit);
-                if (ne > 0 && S.e3img[e].ensure(sizeof(float) * (size_t)ne)) {
-                    HIPCHK(launch_end_faces3_image(g, s, d, S.piv.p, S.len0max, P->lds_limit, S.e3img[e].p, st));
-                    S.e3ok[e] = true;
-                }
-            }
+        if (which >= 2)
             HIPCHK(launch_end_fixups3(g, s, d, S.piv.p, in, in_f64, scale_by_piv, out, out_f64, S.len0max,
-                                      S.e3ok[e] ? S.e3img[e].p : nullptr, st));
-        }
+                                      S.e3ok[which - 2] ? S.e3img[which - 2].p : nullptr, st));
         return PSW_OK;
     }
     if (which <= 1)

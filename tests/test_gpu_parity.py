@@ -212,6 +212,41 @@ def test_tile3_half_sweeps(prec, bound, n, p, monkeypatch):
             assert np.linalg.norm(a - b) / np.linalg.norm(ref) <= 2 * bound, (kind, which)
 
 
+def test_tile3_face_images_follow_updates():
+    """The 3D face kernels read the coefficient part of their records from per-pass images written when
+    the preconditioner is set up.  After a change of relaxation, decomposition or coefficients a reused
+    problem must give, bit for bit, what a fresh problem with the new settings gives.  Tiles of 20 x 32 x 32
+    and 10 x 32 x 32 points take the face kernels with gathered records (four waves per level)."""
+    import torch
+    dim, n = 3, (40, 32, 32)
+    pa, _ = _prob(dim, n, seed=5)
+    pb, _ = _prob(dim, n, seed=6)
+    f = to_dev(pa["f"])
+
+    def fresh(alphas, omega, p):
+        g = make_problem(dim, n, alphas, prec="f32")
+        g.set_relaxation([omega])
+        g.set_decomposition(p, overlap=2, phase=0)
+        return g
+
+    def apply(g, kind):
+        z = torch.empty_like(f)
+        g.precond_apply(kind, f, z, symmetric=True)
+        return to_np(z)
+
+    g = fresh(pa["alphas"], 1.2, (2, 1, 1))
+    for kind in ("ssor", "ilu0"):
+        assert np.array_equal(apply(g, kind), apply(fresh(pa["alphas"], 1.2, (2, 1, 1)), kind)), kind
+    g.set_relaxation([1.5])
+    assert np.array_equal(apply(g, "ssor"), apply(fresh(pa["alphas"], 1.5, (2, 1, 1)), "ssor"))
+    g.set_decomposition((4, 1, 1), overlap=2, phase=0)
+    for kind in ("ssor", "ilu0"):
+        assert np.array_equal(apply(g, kind), apply(fresh(pa["alphas"], 1.5, (4, 1, 1)), kind)), kind
+    g.assemble([to_dev(a) for a in pb["alphas"]], 0.0, "f32")
+    for kind in ("ssor", "ilu0"):
+        assert np.array_equal(apply(g, kind), apply(fresh(pb["alphas"], 1.5, (4, 1, 1)), kind)), kind
+
+
 def test_stationary_solve_poisson_64():
     """64x64 Poisson, 4x4 subdomains, omega = 2/(1+sin(pi/65)), relres 1e-8: sweeps within 1 of the oracle."""
     w = synth.poisson_2d_64()
