@@ -160,6 +160,7 @@ struct psw_problem {
     PrecState pc[2];
     // workspace
     DevBuf w_r, w_z, w_p, w_q, w_t, w_y, w_y2, w_z1;
+    DevBuf w_y3; // the transposed chain's output in sweep precision (3D LDS-tile passes)
     DevBuf partials, scal;
     DevBuf gm_V, gm_Z, gm_h;
     size_t lds_limit = 65536;
@@ -566,6 +567,25 @@ psw_status precond_apply(psw_problem *P, psw_precond kind, int symmetric, const 
         if ((ps = fast_pass(P, kind, 3, y2, f64, true, z1, true, 1.0, nullptr, 0.0, st))) return ps;
         if ((ps = fast_end(P, kind, 3, y2, f64, true, z1, true, st))) return ps;
         return fast_pass(P, kind, 1, y1, f64, true, z, true, S.c, z1, 0.5 * S.c, st);
+    }
+    if (S.tile3) {
+        // 3D LDS-tile passes: the two chains, z1 = c (backward)(forward) r and the transposed
+        // pair, are independent; the transposed pair runs on the side stream beside the other
+        // (same operations and intermediates as one after the other)
+        if (!P->side.ensure()) return PSW_EDEVICE;
+        if (!P->w_y3.ensure(sizeof(double) * (size_t)P->N)) return PSW_ENOMEM;
+        void *y2 = P->w_y2.p, *y3 = P->w_y3.p;
+        hipStream_t ss = P->side.s;
+        HIPCHK(hipEventRecord(P->side.fork, st));
+        HIPCHK(hipStreamWaitEvent(ss, P->side.fork, 0));
+        if ((ps = half(P, kind, 2, r, true, false, y2, f64, 1.0, ss))) return ps;
+        if ((ps = half(P, kind, 3, y2, f64, true, y3, f64, 1.0, ss))) return ps;
+        HIPCHK(hipEventRecord(P->side.join, ss));
+        if ((ps = half(P, kind, 0, r, true, false, y, f64, 1.0, st))) return ps;
+        if ((ps = half(P, kind, 1, y, f64, true, z1, true, S.c, st))) return ps;
+        HIPCHK(hipStreamWaitEvent(st, P->side.join, 0));
+        HIPCHK(launch_scale_add(z, z1, 0.5, y3, f64, 0.5 * S.c, P->N, st));
+        return PSW_OK;
     }
     if ((ps = half(P, kind, 0, r, true, false, y, f64, 1.0, st))) return ps;
     if ((ps = half(P, kind, 1, y, f64, true, z1, true, S.c, st))) return ps;
