@@ -24,6 +24,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+SEQ_ITERS_FILE = os.path.join(ROOT, "tests", "golden", "sequential_iterations.json")
+
+
+def sequential_iterations(key, iters):
+    """CG iterations of the sequential preconditioner (one subdomain) on the same input, from the CPU
+    oracle's stored run, and the decomposed solve's count relative to it."""
+    try:
+        rec = json.load(open(SEQ_ITERS_FILE))[key]
+    except (OSError, ValueError, KeyError):
+        return {"iterations_sequential": None}
+    seq = rec["iterations"]
+    return {"iterations_sequential": seq, "iterations_vs_sequential": round(max(iters) / seq, 4),
+            "sequential_source": "CPU FP64 oracle, one subdomain, same input (tests/golden/sequential_iterations.json)"}
 
 
 def parse():
@@ -167,6 +180,7 @@ def main():
         "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
         "iterations": iters,
         "relres": [i["relres"] for i in infos],
+        **(sequential_iterations("varcoef2048", iters) if n == 2048 else {}),
         "roofline": roofline,
         "roofline_sweep": roofline_sweep,
         "cpu_baseline": cpu,
@@ -554,6 +568,7 @@ def bench_poisson3d(args):
         "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
         "iterations": iters,
         "relres": [i["relres"] for i in infos],
+        **(sequential_iterations("poisson3d256", iters) if n == 256 else {}),
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -1,0 +1,54 @@
+"""Iteration counts of the sequential preconditioners (one subdomain, p = 1) on the measured workloads.
+
+With one subdomain the decomposed ILU(0) is lexicographic ILU(0), and its symmetric form is M^-1
+itself.  The counts are the CG iterations to a relative residual of 1e-8 from x0 = 0, computed by the
+FP64 CPU oracle on the same seeded inputs as the GPU measurements, and written to
+sequential_iterations.json beside this script.  Run: python tests/golden/make_sequential_iterations.py
+[2d|3d]  (the 2048^2 case takes tens of minutes on one core).
+"""
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+from oracle import oracle as O  # noqa: E402
+
+OUT = os.path.join(HERE, "sequential_iterations.json")
+
+
+def run(name, w, kind="ilu0", rtol=1e-8):
+    dim, n = w["dim"], w["n"]
+    diags = O.assemble(dim, n, w["alphas"], w["beta"])
+    pc = O.Precond(kind, dim, n, (1,) * dim, diags, omega=1.0)
+    calls = [0]
+    t0 = time.time()
+
+    def apply_m(r):
+        calls[0] += 1
+        if calls[0] % 200 == 0:
+            print(f"{name}: {calls[0]} preconditioner applications, {time.time() - t0:.0f} s", flush=True)
+        return pc.apply_sym(r)
+
+    _, iters, rel = O.cg(lambda x: O.spmv(dim, n, diags, x), apply_m, w["f"], rtol=rtol, maxit=100000)
+    rec = {"workload": name, "precond": kind, "subdomains": [1] * dim, "rtol": rtol, "iterations": int(iters),
+           "relres_true": float(rel), "cpu_s": round(time.time() - t0, 1)}
+    print(json.dumps(rec), flush=True)
+    return rec
+
+
+if __name__ == "__main__":
+    which = sys.argv[1] if len(sys.argv) > 1 else "all"
+    O.build(force=False)
+    new = {}
+    if which in ("3d", "all"):
+        new["poisson3d256"] = run("3D Poisson 7-point 256^3", synth.poisson_3d(n=256))
+    if which in ("2d", "all"):
+        new["varcoef2048"] = run("2D var-coef diffusion 2048x2048", synth.varcoef_2d(n=2048))
+    recs = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    recs.update(new)
+    json.dump(recs, open(OUT, "w"), indent=1, sort_keys=True)
