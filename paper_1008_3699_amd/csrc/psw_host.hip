@@ -1360,9 +1360,12 @@ size_t request_bytes(int dim, const int64_t n[3], psw_prec prec) {
         nodes *= n[a] + 2;
     }
     // FP64 operator, vectors and workspace (~16 arrays), packed passes (~4 x 3
-    // arrays with padding) and pivots in the sweep precision, node coefficients
+    // arrays with padding) and pivots in the sweep precision, node coefficients;
+    // 3D sweeps in FP32/BF16 add the face coefficient images (about 23 bytes per
+    // point with 32^3 tiles) and the transposed chain's output buffer (8)
     const size_t s = prec == PSW_F64 ? 8 : 4;
-    return (size_t)N * (16 * 8 + 20 * s + 16) + (size_t)nodes * 8 * dim;
+    const size_t extra3 = (dim == 3 && prec != PSW_F64) ? 32 : 0;
+    return (size_t)N * (16 * 8 + 20 * s + 16 + extra3) + (size_t)nodes * 8 * dim;
 }
 
 } // namespace
