@@ -4,9 +4,10 @@ With one subdomain the decomposed ILU(0) is lexicographic ILU(0), and its symmet
 itself.  The counts are the CG iterations to a relative residual of 1e-8 from x0 = 0, computed by the
 FP64 CPU oracle on the same seeded inputs as the GPU measurements, and written to
 sequential_iterations.json beside this script.  Run: python tests/golden/make_sequential_iterations.py
-[2d|3d]  (the 2048^2 case takes tens of minutes on one core).
+[sor64|2d|3d]  (the 2048^2 case takes tens of minutes on one core).
 """
 import json
+import math
 import os
 import sys
 import time
@@ -41,10 +42,26 @@ def run(name, w, kind="ilu0", rtol=1e-8):
     return rec
 
 
+def run_sor64():
+    """64^2 Poisson, SOR at omega = 2/(1+sin(pi/65)) to 1e-8: sweeps with one subdomain and with 4x4."""
+    w = synth.poisson_2d_64()
+    n = w["n"]
+    diags = O.assemble(2, n, w["alphas"], w["beta"])
+    omega = 2.0 / (1.0 + math.sin(math.pi / 65))
+    rec = {"workload": "2D Poisson 5-point 64x64, SOR", "omega": omega, "rtol": 1e-8}
+    for key, p in (("sweeps_sequential", (1, 1)), ("sweeps_4x4", (4, 4))):
+        _, sweeps, _ = O.stationary_solve(2, n, p, diags, omega, w["f"], rtol=1e-8, maxit=20000)
+        rec[key] = int(sweeps)
+    print(json.dumps(rec), flush=True)
+    return rec
+
+
 if __name__ == "__main__":
     which = sys.argv[1] if len(sys.argv) > 1 else "all"
     O.build(force=False)
     new = {}
+    if which in ("sor64", "all"):
+        new["poisson2d64_sor"] = run_sor64()
     if which in ("3d", "all"):
         new["poisson3d256"] = run("3D Poisson 7-point 256^3", synth.poisson_3d(n=256))
     if which in ("2d", "all"):
