@@ -534,6 +534,32 @@ psw_status precond_sym_split(psw_problem *P, psw_precond kind, const double *r, 
     return PSW_OK;
 }
 
+// The symmetric form in two pieces on the 3D LDS-tile passes: z1 = c (backward)(forward) r in
+// FP64 and z2 = the transposed pair in the sweep precision, so that z = 0.5 z1 + 0.5 c z2.  The two
+// chains are independent; the transposed pair runs on the side stream beside the other, with the
+// same operations and intermediates as one after the other.  st has joined on return.
+psw_status precond_sym_split3(psw_problem *P, psw_precond kind, const double *r, double *z1, const void **z2,
+                              hipStream_t st) {
+    PrecState &S = P->pc[kind];
+    if (!S.tile3) return PSW_ENOTSUP;
+    if (!P->side.ensure()) return PSW_EDEVICE;
+    if (!P->w_y3.ensure(sizeof(double) * (size_t)P->N)) return PSW_ENOMEM;
+    const bool f64 = P->prec == PSW_F64;
+    void *y = P->w_y.p, *y2 = P->w_y2.p, *y3 = P->w_y3.p;
+    hipStream_t ss = P->side.s;
+    psw_status ps;
+    HIPCHK(hipEventRecord(P->side.fork, st));
+    HIPCHK(hipStreamWaitEvent(ss, P->side.fork, 0));
+    if ((ps = half(P, kind, 2, r, true, false, y2, f64, 1.0, ss))) return ps;
+    if ((ps = half(P, kind, 3, y2, f64, true, y3, f64, 1.0, ss))) return ps;
+    HIPCHK(hipEventRecord(P->side.join, ss));
+    if ((ps = half(P, kind, 0, r, true, false, y, f64, 1.0, st))) return ps;
+    if ((ps = half(P, kind, 1, y, f64, true, z1, true, S.c, st))) return ps;
+    HIPCHK(hipStreamWaitEvent(st, P->side.join, 0));
+    *z2 = y3;
+    return PSW_OK;
+}
+
 psw_status precond_apply(psw_problem *P, psw_precond kind, int symmetric, const double *r, double *z,
                          hipStream_t st) {
     if (kind == PSW_NONE) {
@@ -569,21 +595,8 @@ psw_status precond_apply(psw_problem *P, psw_precond kind, int symmetric, const 
         return fast_pass(P, kind, 1, y1, f64, true, z, true, S.c, z1, 0.5 * S.c, st);
     }
     if (S.tile3) {
-        // 3D LDS-tile passes: the two chains, z1 = c (backward)(forward) r and the transposed
-        // pair, are independent; the transposed pair runs on the side stream beside the other
-        // (same operations and intermediates as one after the other)
-        if (!P->side.ensure()) return PSW_EDEVICE;
-        if (!P->w_y3.ensure(sizeof(double) * (size_t)P->N)) return PSW_ENOMEM;
-        void *y2 = P->w_y2.p, *y3 = P->w_y3.p;
-        hipStream_t ss = P->side.s;
-        HIPCHK(hipEventRecord(P->side.fork, st));
-        HIPCHK(hipStreamWaitEvent(ss, P->side.fork, 0));
-        if ((ps = half(P, kind, 2, r, true, false, y2, f64, 1.0, ss))) return ps;
-        if ((ps = half(P, kind, 3, y2, f64, true, y3, f64, 1.0, ss))) return ps;
-        HIPCHK(hipEventRecord(P->side.join, ss));
-        if ((ps = half(P, kind, 0, r, true, false, y, f64, 1.0, st))) return ps;
-        if ((ps = half(P, kind, 1, y, f64, true, z1, true, S.c, st))) return ps;
-        HIPCHK(hipStreamWaitEvent(st, P->side.join, 0));
+        const void *y3 = nullptr;
+        if ((ps = precond_sym_split3(P, kind, r, z1, &y3, st))) return ps;
         HIPCHK(launch_scale_add(z, z1, 0.5, y3, f64, 0.5 * S.c, P->N, st));
         return PSW_OK;
     }
@@ -759,7 +772,22 @@ psw_status solve_cg(psw_problem *P, psw_precond kind, double rtol, int64_t maxit
             if (ps) return ps;
             goto done;
         }
-        if (split) {
+        // 3D LDS-tile passes in FP32/BF16: z stays as z1 (FP64) and the FP32 output of the
+        // transposed pair, formed inside the r.z and p kernels
+        const bool split3 = kind != PSW_NONE && P->pc[kind].tile3 && P->prec != PSW_F64;
+        const float *z2f = nullptr;
+        auto apply3 = [&]() -> psw_status {
+            const void *zp = nullptr;
+            psw_status e = precond_sym_split3(P, kind, r, z, &zp, st);
+            z2f = (const float *)zp;
+            return e;
+        };
+        if (split3) {
+            if ((ps = apply3())) return ps;
+            HIPCHK(launch_dot_partial_zf(r, z, z2f, hc, N, part_rz, st));
+            HIPCHK(launch_dot_final(part_rz, s_rz, st));
+            HIPCHK(launch_zcomb_f(p, z, z2f, hc, N, st));
+        } else if (split) {
             if ((ps = precond_sym_split(P, kind, r, z, z2, st))) return ps;
             HIPCHK(launch_dot_partial_zz(r, z, z2, hc, N, part_rz, st));
             HIPCHK(launch_dot_final(part_rz, s_rz, st));
@@ -781,7 +809,11 @@ psw_status solve_cg(psw_problem *P, psw_precond kind, double rtol, int64_t maxit
             // device stays busy while the stopping test runs
             HIPCHK(hipMemcpyAsync(h, s_pq, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
             HIPCHK(hipEventRecord(P->hs.ev, st));
-            if (split) {
+            if (split3) {
+                if ((ps = apply3())) return ps;
+                HIPCHK(launch_dot_partial_zf(r, z, z2f, hc, N, part_rz, st));
+                HIPCHK(launch_cg_update_p_red_zf(p, z, z2f, hc, part_rz, s_rz2, s_rz, N, st));
+            } else if (split) {
                 if ((ps = precond_sym_split(P, kind, r, z, z2, st))) return ps;
                 HIPCHK(launch_dot_partial_zz(r, z, z2, hc, N, part_rz, st));
                 HIPCHK(launch_cg_update_p_red_zz(p, z, z2, hc, part_rz, s_rz2, s_rz, N, st));

@@ -115,6 +115,13 @@ hipError_t launch_cg_update_p_red_zz(double *p, const double *z1, const double *
                                      const double *num_partials, double *num, const double *den, int64_t N,
                                      hipStream_t st);
 hipError_t launch_zcomb(double *z, const double *z1, const double *z2, double b, int64_t N, hipStream_t st);
+// The same three with the second piece z2 in FP32 (the output of FP32/BF16 sweeps).
+hipError_t launch_dot_partial_zf(const double *r, const double *z1, const float *z2, double b, int64_t N,
+                                 double *partials, hipStream_t st);
+hipError_t launch_cg_update_p_red_zf(double *p, const double *z1, const float *z2, double b,
+                                     const double *num_partials, double *num, const double *den, int64_t N,
+                                     hipStream_t st);
+hipError_t launch_zcomb_f(double *z, const double *z1, const float *z2, double b, int64_t N, hipStream_t st);
 // p = z + beta p with beta = (sum of num_partials) / den[0]; stores the sum to num[0]
 hipError_t launch_cg_update_p_red(double *p, const double *z, const double *num_partials, double *num,
                                   const double *den, int64_t N, hipStream_t st);

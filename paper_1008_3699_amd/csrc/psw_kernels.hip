@@ -1664,24 +1664,33 @@ __global__ void __launch_bounds__(kRedThreads) k_cg_p_red(double *p, const doubl
 // z = 0.5 z1 + b z2, with one rounding after the exact halving (the symmetric preconditioner's combination)
 __device__ __forceinline__ double zcomb(double z1, double z2, double b) { return __fma_rn(b, z2, 0.5 * z1); }
 
-__global__ void __launch_bounds__(kRedThreads) k_dot_partial_zz(const double *r, const double *z1, const double *z2,
+template <typename Z2>
+__global__ void __launch_bounds__(kRedThreads) k_dot_partial_zz(const double *r, const double *z1, const Z2 *z2,
                                                                double b, int64_t N, double *partials) {
     __shared__ double sh[kRedThreads];
     double acc = 0.0;
     const int64_t stride = (int64_t)kRedBlocks * kRedThreads;
     for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < N; i += stride)
-        acc += r[i] * zcomb(z1[i], z2[i], b);
+        acc += r[i] * zcomb(z1[i], (double)z2[i], b);
     double s = block_sum(acc, sh);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
 hipError_t launch_dot_partial_zz(const double *r, const double *z1, const double *z2, double b, int64_t N,
                                  double *partials, hipStream_t st) {
-    hipLaunchKernelGGL(k_dot_partial_zz, dim3(kRedBlocks), dim3(kRedThreads), 0, st, r, z1, z2, b, N, partials);
+    hipLaunchKernelGGL(k_dot_partial_zz<double>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, r, z1, z2, b, N, partials);
     return hipGetLastError();
 }
 
-__global__ void __launch_bounds__(kRedThreads) k_cg_p_red_zz(double *p, const double *z1, const double *z2, double b,
+// the same with the second piece in FP32 (the output of FP32/BF16 sweeps)
+hipError_t launch_dot_partial_zf(const double *r, const double *z1, const float *z2, double b, int64_t N,
+                                 double *partials, hipStream_t st) {
+    hipLaunchKernelGGL(k_dot_partial_zz<float>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, r, z1, z2, b, N, partials);
+    return hipGetLastError();
+}
+
+template <typename Z2>
+__global__ void __launch_bounds__(kRedThreads) k_cg_p_red_zz(double *p, const double *z1, const Z2 *z2, double b,
                                                             const double *num_partials, double *num,
                                                             const double *den, int64_t N) {
     __shared__ double sh[kRedThreads];
@@ -1689,14 +1698,22 @@ __global__ void __launch_bounds__(kRedThreads) k_cg_p_red_zz(double *p, const do
     if (blockIdx.x == 0 && threadIdx.x == 0) num[0] = rz;
     const double beta = rz / den[0];
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = zcomb(z1[i], z2[i], b) + beta * p[i];
+        p[i] = zcomb(z1[i], (double)z2[i], b) + beta * p[i];
 }
 
 hipError_t launch_cg_update_p_red_zz(double *p, const double *z1, const double *z2, double b,
                                      const double *num_partials, double *num, const double *den, int64_t N,
                                      hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_p_red_zz, dim3(kRedBlocks), dim3(kRedThreads), 0, st, p, z1, z2, b, num_partials, num,
-                       den, N);
+    hipLaunchKernelGGL(k_cg_p_red_zz<double>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, p, z1, z2, b, num_partials,
+                       num, den, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_update_p_red_zf(double *p, const double *z1, const float *z2, double b,
+                                     const double *num_partials, double *num, const double *den, int64_t N,
+                                     hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_p_red_zz<float>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, p, z1, z2, b, num_partials,
+                       num, den, N);
     return hipGetLastError();
 }
 
@@ -1952,13 +1969,19 @@ hipError_t launch_axpy_dev(double *y, const double *a, const double *x, int64_t 
     return hipGetLastError();
 }
 
-__global__ void k_zcomb(double *z, const double *z1, const double *z2, double b, int64_t N) {
+template <typename Z2>
+__global__ void k_zcomb(double *z, const double *z1, const Z2 *z2, double b, int64_t N) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
-        z[i] = zcomb(z1[i], z2[i], b);
+        z[i] = zcomb(z1[i], (double)z2[i], b);
 }
 
 hipError_t launch_zcomb(double *z, const double *z1, const double *z2, double b, int64_t N, hipStream_t st) {
-    hipLaunchKernelGGL(k_zcomb, dim3(grid_for(N)), dim3(256), 0, st, z, z1, z2, b, N);
+    hipLaunchKernelGGL(k_zcomb<double>, dim3(grid_for(N)), dim3(256), 0, st, z, z1, z2, b, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_zcomb_f(double *z, const double *z1, const float *z2, double b, int64_t N, hipStream_t st) {
+    hipLaunchKernelGGL(k_zcomb<float>, dim3(grid_for(N)), dim3(256), 0, st, z, z1, z2, b, N);
     return hipGetLastError();
 }
 
