@@ -247,6 +247,25 @@ def test_tile3_face_images_follow_updates():
         assert np.array_equal(apply(g, kind), apply(fresh(pb["alphas"], 1.5, (4, 1, 1)), kind)), kind
 
 
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_cg_3d_tile_sweeps_two_pieces(prec):
+    """3D CG with FP32 arithmetic sweeps on the LDS-tile passes (16^3 tiles: face levels in four waves),
+    the transposed pair on the side stream and z kept in two pieces: converges to 1e-8 in the true
+    residual, with the iteration count of the oracle's FP64 CG within 10 %."""
+    import torch
+    dim, n, p = 3, (32, 32, 32), (2, 2, 2)
+    pr, diags = _prob(dim, n, seed=41)
+    pc = O.Precond("ilu0", dim, n, p, diags, omega=1.0)
+    _, it_ref, _ = O.cg(lambda v: O.spmv(dim, n, diags, v), pc.apply_sym, pr["f"], rtol=1e-8)
+    g = make_problem(dim, n, pr["alphas"], prec=prec)
+    g.set_relaxation([1.0])
+    g.set_decomposition(p, overlap=2, phase=0)
+    u = torch.zeros(int(np.prod(n)), dtype=torch.float64, device=dev())
+    info = g.solve("cg", "ilu0", to_dev(pr["f"]), u, rtol=1e-8, maxit=2000)
+    assert info["converged"] and info["relres"] <= 1.05e-8, info
+    assert abs(info["iters"] - it_ref) <= max(2, 0.1 * it_ref), (info, it_ref)
+
+
 def test_stationary_solve_poisson_64():
     """64x64 Poisson, 4x4 subdomains, omega = 2/(1+sin(pi/65)), relres 1e-8: sweeps within 1 of the oracle
     and within 10 % of sequential SOR."""
