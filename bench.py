@@ -180,7 +180,7 @@ def main():
         "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
         "iterations": iters,
         "relres": [i["relres"] for i in infos],
-        **(sequential_iterations("varcoef2048", iters) if n == 2048 else {}),
+        **(sequential_iterations("varcoef2048", iters) if n == 2048 and args.precond == "ilu0" else {}),
         "roofline": roofline,
         "roofline_sweep": roofline_sweep,
         "cpu_baseline": cpu,
@@ -568,7 +568,7 @@ def bench_poisson3d(args):
         "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
         "iterations": iters,
         "relres": [i["relres"] for i in infos],
-        **(sequential_iterations("poisson3d256", iters) if n == 256 else {}),
+        **(sequential_iterations("poisson3d256", iters) if n == 256 and args.precond == "ilu0" else {}),
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
