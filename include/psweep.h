@@ -104,11 +104,23 @@ psw_status psw_set_relaxation(psw_problem *prob, const double *omega, int count)
 
 /* Decomposition into p[0] x p[1] (x p[2]) subdomains: contiguous ranges per
  * axis, the first n mod p ranges one point longer (Sec. 3).  Every
- * subdomain must be at least 2 points long on every axis.  overlap is the
- * halo depth staged per subdomain (>= 2; a 5/7-point sweep reads 2 layers,
- * Sec. 3, Data structure) and does not change any result.  phase swaps the two members
- * of every direction pair of the schedule (Sec. 3, Sweeping directions). */
+ * subdomain must be at least 2 points long on every axis.  overlap (>= 2) is
+ * the depth of the layer beyond a subdomain's own box that its sweep may
+ * read.  The exact-coupling sweep, its preconditioners and solves read one
+ * layer (two across a coupled start face, Sec. 3, Data structure), so their
+ * results do not depend on overlap; it is stored and used only by the
+ * restricted-overlap sweep (psw_sweep_restricted).  phase swaps the two
+ * members of every direction pair of the schedule (Sec. 3, Sweeping
+ * directions). */
 psw_status psw_set_decomposition(psw_problem *prob, const int p[3], int overlap, int phase);
+
+/* Kernel path of the preconditioner passes: PSW_PATH_AUTO (the pipelined 2D
+ * passes and the 3D LDS-tile passes where a decomposition fits them) or
+ * PSW_PATH_GENERIC (the level-by-level kernels for every pass).  Both compute
+ * the same operator; the switch exists so that tests and measurements can
+ * compare the two.  Invalidates preconditioner state. */
+enum { PSW_PATH_AUTO = 0, PSW_PATH_GENERIC = 1 };
+psw_status psw_set_path(psw_problem *prob, int path);
 
 /* One decomposed SOR sweep, FP64 (Secs. 2-4).  Subdomain (r,s,t) sweeps at
  * iteration k in direction sigma_{k mod 2^dim} with the sign of axis a
@@ -146,6 +158,19 @@ psw_status psw_precond_apply(psw_problem *prob, psw_precond kind, int symmetric,
  * (D/w, 2-w) for SSOR and (D~, 1) for ILU0. */
 psw_status psw_precond_half(psw_problem *prob, psw_precond kind, int which, const double *in,
                             double *out, void *stream);
+
+/* The preconditioner's stored coefficients in the sweep precision, as the
+ * kernels read them: k = 0 the pivots (D/w for SSOR, D~ for ILU0), k = 1..2*dim
+ * the couplings of diagonal k (W,E,S,N,B,F).  out is a device array of N
+ * elements of the sweep precision (8, 4 or 2 bytes: FP64, FP32, or BF16, the
+ * upper 16 bits of an FP32), each the round-to-nearest-even conversion of the
+ * FP64 value of the Sec. 5 forms.  For tests of the conversion; sets the
+ * preconditioner up if needed. */
+psw_status psw_get_sweep_coefficients(psw_problem *prob, psw_precond kind, int k, void *out, void *stream);
+
+/* Device memory the handle holds now, in bytes (its own arrays; the caller's
+ * vectors are not counted). */
+psw_status psw_problem_device_bytes(psw_problem *prob, size_t *bytes);
 
 /* ILU(0) pivots D~ of the decomposed factorisation (FP64, N doubles):
  * D~_P = a^P_P - sum_{Q upstream of P in P's subdomain} a_{P->Q} a_{Q->P} / D~_Q. */
@@ -231,6 +256,12 @@ psw_status psw_server_create(size_t budget_bytes, const psw_server_opts *opts, p
  * budget.  *ticket identifies the request. */
 psw_status psw_server_submit(psw_server *srv, int dim, const int64_t n[3], const double *const alpha[], double beta,
                              const double *f, uint64_t *ticket);
+/* The device bytes admission reserves for a request of this shape: the
+ * footprint of its problem (diagonals, workspace, the preconditioner's
+ * packings for the largest of the decompositions the autotuner may choose),
+ * its right-hand side and solution, and its node coefficients during set-up. */
+psw_status psw_server_request_bytes(psw_server *srv, int dim, const int64_t n[3], size_t *bytes);
+
 /* *done = 1 once the request has finished (wait = 1 blocks until then).  On
  * completion info receives iterations, relres, status and t_total_ms =
  * submission to completion; t_queue_ms (may be NULL) the time spent waiting

@@ -73,6 +73,9 @@ def lib():
             "psw_pass_timing_enable": [vp, ci, ci],
             "psw_pass_timing": [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)],
             "psw_pass_timing_of": [vp, ci, ctypes.POINTER(dbl), ctypes.POINTER(i64)],
+            "psw_set_path": [vp, ci],
+            "psw_get_sweep_coefficients": [vp, ci, ci, vp, vp],
+            "psw_problem_device_bytes": [vp, ctypes.POINTER(ctypes.c_size_t)],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -144,6 +147,15 @@ class Problem:
 
     # ---- set-up
     def set_diagonals(self, diags, prec="f64", stream=None):
+        """Diagonals P,W,E,S,N(,B,F): CUDA float64 tensors (device copy) or numpy float64 arrays (host copy)."""
+        import numpy as np
+        if all(isinstance(d, np.ndarray) for d in diags):
+            host = [np.ascontiguousarray(d, dtype=np.float64).reshape(-1) for d in diags]
+            if any(h.size != self.N for h in host):
+                raise ValueError(f"each diagonal needs {self.N} values")
+            ptrs = (ctypes.c_void_p * 7)(*([h.ctypes.data for h in host] + [0] * (7 - len(host))))
+            _check(lib().psw_set_diagonals(self._h, ptrs, 0, _PREC[prec], _stream(stream)), "psw_set_diagonals")
+            return
         ptrs = (ctypes.c_void_p * 7)(*([_ptr(d, self.N, "diag").value for d in diags] + [0] * (7 - len(diags))))
         _check(lib().psw_set_diagonals(self._h, ptrs, 1, _PREC[prec], _stream(stream)), "psw_set_diagonals")
 
@@ -166,6 +178,24 @@ class Problem:
     def set_decomposition(self, p, overlap=2, phase=0):
         arr = (ctypes.c_int * 3)(*(list(p) + [1] * (3 - len(p))))
         _check(lib().psw_set_decomposition(self._h, arr, int(overlap), int(phase)), "psw_set_decomposition")
+
+    def set_path(self, path):
+        """'auto' (pipelined 2D / LDS-tile 3D passes where they apply) or 'generic' (level kernels)."""
+        _check(lib().psw_set_path(self._h, {"auto": 0, "generic": 1}[path]), "psw_set_path")
+
+    def sweep_coefficients(self, kind, k, out, stream=None):
+        """Stored sweep-precision coefficients (k = 0 pivots, 1..2*dim couplings) into the CUDA tensor
+        out (N elements of 8, 4 or 2 bytes: float64, float32, or int16 holding BF16 bits)."""
+        import torch
+        if not isinstance(out, torch.Tensor) or not out.is_cuda or not out.is_contiguous() or out.numel() != self.N:
+            raise ValueError(f"out must be a contiguous CUDA tensor of {self.N} elements")
+        _check(lib().psw_get_sweep_coefficients(self._h, _KIND[kind], int(k), ctypes.c_void_p(out.data_ptr()),
+                                                _stream(stream)), "psw_get_sweep_coefficients")
+
+    def device_bytes(self):
+        b = ctypes.c_size_t()
+        _check(lib().psw_problem_device_bytes(self._h, ctypes.byref(b)), "psw_problem_device_bytes")
+        return b.value
 
     # ---- operations
     def sweep(self, iteration, u_in, f, u_out, stream=None):
@@ -272,7 +302,10 @@ class Server:
         L.psw_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                       ctypes.POINTER(Info), vp, ctypes.POINTER(ctypes.c_double)]
         L.psw_server_destroy.argtypes = [vp]
-        for fn in (L.psw_server_create, L.psw_server_submit, L.psw_server_poll, L.psw_server_destroy):
+        L.psw_server_request_bytes.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                                               ctypes.POINTER(ctypes.c_size_t)]
+        for fn in (L.psw_server_create, L.psw_server_submit, L.psw_server_poll, L.psw_server_destroy,
+                   L.psw_server_request_bytes):
             fn.restype = ctypes.c_int
         opts = ServerOpts(_PREC[prec], _KIND[precond], float(rtol), int(maxit), int(epoch_iters), int(max_active),
                           int(lanes3d))
@@ -298,6 +331,13 @@ class Server:
                                        ctypes.byref(t)), "psw_server_submit")
         self._size[t.value] = N
         return t.value
+
+    def request_bytes(self, dim, n):
+        """Device bytes that admission reserves for a request of this shape."""
+        arr = (ctypes.c_int64 * 3)(*(list(n) + [1] * (3 - dim)))
+        b = ctypes.c_size_t()
+        _check(lib().psw_server_request_bytes(self._h, dim, arr, ctypes.byref(b)), "psw_server_request_bytes")
+        return b.value
 
     def poll(self, ticket, wait=False):
         """None while the request runs; else (solution u as numpy, info dict with t_queue_ms)."""

@@ -33,20 +33,12 @@ template <typename T> using GP = __attribute__((address_space(1))) T;
 
 namespace {
 
-__device__ __forceinline__ float bf16f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
-
-__device__ __forceinline__ uint16_t to_bf16(double x) {
-    float t = __double2float_rz(x);
-    uint32_t u = __float_as_uint(t);
-    if ((double)t != x && (u & 0x7f800000u) != 0x7f800000u) u |= 1u;
-    uint32_t r = u + 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(r >> 16);
-}
+__device__ __forceinline__ float bf16f(uint16_t b) { return bf16_to_f32(b); }
 
 template <typename S> __device__ __forceinline__ S from_f64(double v);
 template <> __device__ __forceinline__ double from_f64<double>(double v) { return v; }
 template <> __device__ __forceinline__ float from_f64<float>(double v) { return (float)v; }
-template <> __device__ __forceinline__ uint16_t from_f64<uint16_t>(double v) { return to_bf16(v); }
+template <> __device__ __forceinline__ uint16_t from_f64<uint16_t>(double v) { return f64_to_bf16(v); }
 
 template <typename T, typename S> __device__ __forceinline__ T cvt(S v);
 template <> __device__ __forceinline__ double cvt<double, double>(double v) { return v; }

@@ -154,6 +154,7 @@ struct psw_problem {
     int overlap = 2;
     int phase = 0;
     bool has_decomp = false;
+    bool force_generic = false; // psw_set_path(PSW_PATH_GENERIC): level kernels for every pass
     DevBuf tiles;
     int ntiles = 0;
     int cmax = 1, l1max = 1, l2max = 1;
@@ -254,19 +255,58 @@ void pass_sig(const psw_problem *P, int which, int sig[3]) {
         for (int a = 0; a < 3; ++a) sig[a] = -sig[a];
 }
 
-bool fast_eligible(const psw_problem *P, int &R, int &lxmax, int &lymax) {
-    if (P->dim != 2) return false;
-    const char *e = std::getenv("PSW_FORCE_GENERIC");
-    if (e && e[0] == '1') return false;
+// whether a 2D decomposition runs on the pipelined passes, with rows per lane and largest tile
+bool fast_shape(int dim, const int n[3], const int p[3], psw_prec prec, size_t lds_limit, int &R, int &lxmax,
+                int &lymax) {
+    if (dim != 2) return false;
     std::vector<int> lo, len;
-    partition(P->n[0], P->p[0], lo, len);
+    partition(n[0], p[0], lo, len);
     lxmax = *std::max_element(len.begin(), len.end());
-    partition(P->n[1], P->p[1], lo, len);
+    partition(n[1], p[1], lo, len);
     lymax = *std::max_element(len.begin(), len.end());
     R = (lymax + 63) / 64;
     if (R > 2) return false;
-    size_t elem = P->prec == PSW_F64 ? 8 : 4;
-    return fast2d_lds_bytes(lxmax, lymax, R, elem) <= P->lds_limit;
+    size_t elem = prec == PSW_F64 ? 8 : 4;
+    return fast2d_lds_bytes(lxmax, lymax, R, elem) <= lds_limit;
+}
+
+bool fast_eligible(const psw_problem *P, int &R, int &lxmax, int &lymax) {
+    if (P->force_generic) return false;
+    return fast_shape(P->dim, P->n, P->p, P->prec, P->lds_limit, R, lxmax, lymax);
+}
+
+// Sizes of the pipelined 2D packing: elements of one pass's packed coefficients (t) and face
+// records (f, before the 8 spare slots), and entries of the step-offset tables (otab); the
+// formulas fast_setup allocates with.
+struct Fast2dPlan {
+    int64_t t = 0, f = 0, otab = 0;
+};
+Fast2dPlan fast2d_plan(const int n[3], const int p[3], int R, size_t eb) {
+    std::vector<int> lo0, len0, lo1, len1;
+    partition(n[0], p[0], lo0, len0);
+    partition(n[1], p[1], lo1, len1);
+    Fast2dPlan pl;
+    for (int s1 = 0; s1 < p[1]; ++s1)
+        for (int s0 = 0; s0 < p[0]; ++s0) {
+            const int lx = len0[s0], ly = len1[s1];
+            pl.t += fast2d_tile_elems(lx, ly, R, eb);
+            pl.f += 4 * (int64_t)(lx + ly) + 3;
+            pl.f = (pl.f + 7) & ~(int64_t)7;
+            pl.otab += fast2d_tab_len(lx, ly, R);
+        }
+    return pl;
+}
+
+// slots of one 3D LDS-tile pass's level-major packing (tile3_setup)
+int64_t tile3_slots(const int n[3], const int p[3]) {
+    std::vector<int> lo[3], len[3];
+    for (int a = 0; a < 3; ++a) partition(n[a], p[a], lo[a], len[a]);
+    int64_t tot = 0;
+    for (int t = 0; t < p[2]; ++t)
+        for (int u = 0; u < p[1]; ++u)
+            for (int r = 0; r < p[0]; ++r)
+                tot += (int64_t)(len[0][r] + len[1][u] + len[2][t] - 2) * len[1][u] * len[2][t];
+    return tot;
 }
 
 psw_status fast_setup(psw_problem *P, PrecState &S, hipStream_t st) {
@@ -325,9 +365,7 @@ psw_status tile3_setup(psw_problem *P, PrecState &S, hipStream_t st) {
     S.tile3 = false;
     S.f3ok[0] = S.f3ok[1] = false;
     S.e3ok[0] = S.e3ok[1] = false;
-    if (P->dim != 3 || P->prec == PSW_F64 || P->cmax > 1024) return PSW_OK;
-    const char *e = std::getenv("PSW_FORCE_GENERIC");
-    if (e && e[0] == '1') return PSW_OK;
+    if (P->dim != 3 || P->prec == PSW_F64 || P->cmax > 1024 || P->force_generic) return PSW_OK;
     std::vector<int> lo[3], len[3];
     for (int a = 0; a < 3; ++a) partition(P->n[a], P->p[a], lo[a], len[a]);
     const int len0max = *std::max_element(len[0].begin(), len[0].end());
@@ -421,6 +459,80 @@ psw_status precond_setup(psw_problem *P, psw_precond kind, hipStream_t st) {
     if ((ps = tile3_setup(P, S, st))) return ps;
     S.ready = true;
     return PSW_OK;
+}
+
+// Device bytes that a problem holds after a CG solve with preconditioner kind (diagonals,
+// tile table, workspace, the preconditioner's sweep-precision state and packings, the 3D
+// transposed chain's buffer), from the size formulas its set-up allocates with.
+size_t problem_bytes(int dim, const int n_in[3], const int p_in[3], psw_prec prec, psw_precond kind,
+                     size_t lds_limit) {
+    int n[3] = {1, 1, 1}, p[3] = {1, 1, 1};
+    int64_t N = 1;
+    for (int a = 0; a < dim; ++a) {
+        n[a] = n_in[a];
+        p[a] = p_in[a];
+        N *= n[a];
+    }
+    const int ntiles = p[0] * p[1] * p[2];
+    size_t b = (size_t)(2 * dim + 1) * 8 * N + sizeof(TileDesc) * ntiles;        // diagonals, tiles
+    b += 8 * 8 * (size_t)N + sizeof(double) * kRedBlocks * 64 + sizeof(double) * 64; // ensure_work
+    if (kind != PSW_SSOR && kind != PSW_ILU0) return b;
+    const Store st = store_of(prec);
+    const size_t eb = store_bytes(st);
+    b += (size_t)(2 * dim) * eb * N + eb * N + 8 * (size_t)N; // couplings, pivots, FP64 pivots
+    int R, lxmax, lymax;
+    if (fast_shape(dim, n, p, prec, lds_limit, R, lxmax, lymax)) {
+        const Fast2dPlan pl = fast2d_plan(n, p, R, eb);
+        b += 3 * sizeof(int64_t) * ntiles + sizeof(int) * (size_t)pl.otab;
+        b += 4 * (3 * eb * (size_t)pl.t + eb * (size_t)(pl.f + 8));
+    }
+    if (dim == 3 && prec != PSW_F64) {
+        std::vector<int> lo[3], len[3];
+        PassGeom g{};
+        g.dim = 3;
+        g.ntiles = ntiles;
+        for (int a = 0; a < 3; ++a) {
+            g.n[a] = n[a];
+            g.sig[a] = 1;
+            partition(n[a], p[a], lo[a], len[a]);
+        }
+        const int l1max = *std::max_element(len[1].begin(), len[1].end());
+        const int l2max = *std::max_element(len[2].begin(), len[2].end());
+        g.cmax = l1max * l2max;
+        g.l1max = l1max;
+        g.l2max = l2max;
+        const int len0max = *std::max_element(len[0].begin(), len[0].end());
+        if (g.cmax <= 1024 && tile3_lds_bytes(g, len0max, sizeof(float)) <= lds_limit) {
+            b += sizeof(int64_t) * ntiles + 4 * pack3_slot_bytes(st) * (size_t)tile3_slots(n, p);
+            const int64_t fi = faces3_image_elems(g, len0max, lds_limit);
+            const int64_t ei = end_faces3_image_elems(g, len0max, lds_limit);
+            b += 2 * sizeof(float) * (size_t)std::max<int64_t>(fi, 0) + 2 * sizeof(float) * (size_t)std::max<int64_t>(ei, 0);
+            b += 8 * (size_t)N; // the transposed chain's output (CG on the LDS-tile passes)
+        }
+    }
+    return b;
+}
+
+size_t devbuf_bytes(const DevBuf &d) { return d.p ? d.bytes : 0; }
+
+// device bytes a problem holds now (its DevBufs)
+size_t problem_device_bytes(const psw_problem *P) {
+    size_t b = devbuf_bytes(P->tiles) + devbuf_bytes(P->partials) + devbuf_bytes(P->scal);
+    for (const DevBuf &d : P->diag) b += devbuf_bytes(d);
+    for (const DevBuf *d : {&P->w_r, &P->w_z, &P->w_p, &P->w_q, &P->w_t, &P->w_y, &P->w_y2, &P->w_z1, &P->w_y3,
+                            &P->gm_V, &P->gm_Z, &P->gm_h})
+        b += devbuf_bytes(*d);
+    for (const PrecState &S : P->pc) {
+        for (const DevBuf &d : S.diag) b += devbuf_bytes(d);
+        b += devbuf_bytes(S.piv) + devbuf_bytes(S.piv64) + devbuf_bytes(S.toff) + devbuf_bytes(S.foff) +
+             devbuf_bytes(S.otab) + devbuf_bytes(S.ooff) + devbuf_bytes(S.t3off);
+        for (const FastPassBuf &f : S.fp)
+            b += devbuf_bytes(f.inv) + devbuf_bytes(f.ax) + devbuf_bytes(f.ay) + devbuf_bytes(f.face);
+        for (const DevBuf &d : S.t3pk) b += devbuf_bytes(d);
+        for (const DevBuf &d : S.f3img) b += devbuf_bytes(d);
+        for (const DevBuf &d : S.e3img) b += devbuf_bytes(d);
+    }
+    return b;
 }
 
 // one half-sweep; which: 0 fwd (N1), 1 bwd (N2, scaled by c), 2 (Piv-N2)^-T, 3 (Piv-N1)^-T
@@ -1272,6 +1384,10 @@ psw_status batch_cg(int count, psw_problem *const *probs, const double *const *f
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int>, std::pair<int, int>> g_tune_cache;
 
+// candidate tile sides, and the subdomain count of an axis of n points for a side
+const int kTuneSides[] = {16, 24, 32, 48, 64, 96, 128};
+int tune_count(int n, int side) { return std::min(std::max(1, (n + side - 1) / side), std::max(1, n / 2)); }
+
 psw_status tune_candidate(int n0, int n1, psw_prec prec, psw_precond kind, int p0, int p1, double *us,
                           hipStream_t st) {
     const int64_t n[3] = {n0, n1, 1};
@@ -1335,13 +1451,10 @@ psw_status autotune2d(int n0, int n1, psw_prec prec, psw_precond kind, int p[2],
             return PSW_OK;
         }
     }
-    const int sides[] = {16, 24, 32, 48, 64, 96, 128};
     double best = 1e300;
     int bp0 = 0, bp1 = 0;
-    for (int side : sides) {
-        int p0 = std::max(1, (n0 + side - 1) / side), p1 = std::max(1, (n1 + side - 1) / side);
-        p0 = std::min(p0, std::max(1, n0 / 2));
-        p1 = std::min(p1, std::max(1, n1 / 2));
+    for (int side : kTuneSides) {
+        int p0 = tune_count(n0, side), p1 = tune_count(n1, side);
         double us = 0;
         psw_status ps = tune_candidate(n0, n1, prec, kind, p0, p1, &us, st);
         if (ps == PSW_ENOTSUP || ps == PSW_EINVAL) continue;
@@ -1385,19 +1498,51 @@ struct SrvReq {
     DevBuf dx, df, dal[3];
 };
 
-size_t request_bytes(int dim, const int64_t n[3], psw_prec prec) {
+// subdomain counts of a served problem: 2D from the tile side that the autotuner chose for the
+// size bucket (side <= 0: no answer, 128-point tiles), 3D with 32-point tiles
+void srv_decomp(int dim, const int64_t n[3], int side, int p[3]) {
+    p[0] = p[1] = p[2] = 1;
+    if (dim == 3) {
+        for (int a = 0; a < 3; ++a) p[a] = (int)std::max<int64_t>(1, std::min<int64_t>(n[a] / 2, (n[a] + 31) / 32));
+        return;
+    }
+    if (side <= 0) side = 128;
+    for (int a = 0; a < 2; ++a)
+        p[a] = (int)std::max<int64_t>(1, std::min<int64_t>(n[a] / 2, (n[a] + side - 1) / side));
+}
+
+// size bucket of a served 2D problem (the autotuner's cache key)
+int srv_bucket(const int64_t n[3]) { return (int)std::max<int64_t>(32, ((n[0] + 32) / 64) * 64); }
+
+// Admission estimate of a request: its problem's device bytes (problem_bytes, for the largest
+// footprint among the decompositions the autotuner can pick), the right-hand side and solution,
+// the node coefficients held during set-up, and its share of the batch tables.
+size_t request_bytes(int dim, const int64_t n[3], psw_prec prec, psw_precond kind, size_t lds_limit) {
     int64_t N = 1, nodes = 1;
+    int nn[3] = {1, 1, 1};
     for (int a = 0; a < dim; ++a) {
         N *= n[a];
         nodes *= n[a] + 2;
+        nn[a] = (int)n[a];
     }
-    // FP64 operator, vectors and workspace (~16 arrays), packed passes (~4 x 3
-    // arrays with padding) and pivots in the sweep precision, node coefficients;
-    // 3D sweeps in FP32/BF16 add the face coefficient images (about 23 bytes per
-    // point with 32^3 tiles) and the transposed chain's output buffer (8)
-    const size_t s = prec == PSW_F64 ? 8 : 4;
-    const size_t extra3 = (dim == 3 && prec != PSW_F64) ? 32 : 0;
-    return (size_t)N * (16 * 8 + 20 * s + 16 + extra3) + (size_t)nodes * 8 * dim;
+    size_t worst = 0;
+    int p[3];
+    if (dim == 3) {
+        srv_decomp(3, n, 0, p);
+        worst = problem_bytes(3, nn, p, prec, kind, lds_limit);
+    } else {
+        const int b = srv_bucket(n);
+        srv_decomp(2, n, 0, p);
+        worst = problem_bytes(2, nn, p, prec, kind, lds_limit);
+        for (int side : kTuneSides) {
+            srv_decomp(2, n, std::max(2, b / tune_count(b, side)), p);
+            worst = std::max(worst, problem_bytes(2, nn, p, prec, kind, lds_limit));
+        }
+    }
+    const int64_t chunks = (N + kBatchChunk - 1) / kBatchChunk;
+    const size_t tables = sizeof(BProb) + (size_t)chunks * (sizeof(BChunk) + sizeof(double)) +
+                          (size_t)p[0] * p[1] * p[2] * sizeof(BTile) + 3 * sizeof(int) + 5 * sizeof(double);
+    return worst + 2 * sizeof(double) * (size_t)N + (size_t)nodes * 8 * dim + tables;
 }
 
 } // namespace
@@ -1418,6 +1563,7 @@ struct psw_server {
     bool stop = false;
     uint64_t next_id = 1;
     int device = 0;
+    size_t lds_limit = 65536;
     int64_t n_done = 0;
     std::thread w2;
     std::vector<std::thread> w3;
@@ -1444,20 +1590,14 @@ psw_status srv_setup(psw_server *S, SrvReq *r, hipStream_t st) {
     const double w = 1.0;
     if ((ps = psw_set_relaxation(r->P, &w, 1))) return ps;
     int p[3] = {1, 1, 1};
+    int side = 0;
     if (r->dim == 2) {
         // autotuned tile side of the size bucket
-        const int b = (int)std::max<int64_t>(32, ((r->n[0] + 32) / 64) * 64);
+        const int b = srv_bucket(r->n);
         int pb[2];
-        if (autotune2d(b, b, S->prec, S->precond, pb, nullptr, st) == PSW_OK) {
-            const int side = std::max(2, b / pb[0]);
-            for (int a = 0; a < 2; ++a)
-                p[a] = (int)std::max<int64_t>(1, std::min<int64_t>(r->n[a] / 2, (r->n[a] + side - 1) / side));
-        } else {
-            for (int a = 0; a < 2; ++a) p[a] = (int)std::max<int64_t>(1, (r->n[a] + 127) / 128);
-        }
-    } else {
-        for (int a = 0; a < 3; ++a) p[a] = (int)std::max<int64_t>(1, std::min<int64_t>(r->n[a] / 2, (r->n[a] + 31) / 32));
+        if (autotune2d(b, b, S->prec, S->precond, pb, nullptr, st) == PSW_OK) side = std::max(2, b / pb[0]);
     }
+    srv_decomp(r->dim, r->n, side, p);
     if ((ps = psw_set_decomposition(r->P, p, 2, 0))) return ps;
     if ((ps = precond_setup(r->P, S->precond, st))) return ps;
     HIPCHK(hipStreamSynchronize(st));
@@ -1472,7 +1612,9 @@ void srv_finish(psw_server *S, SrvReq *r, psw_status st_code, hipStream_t st) {
     r->u.assign((size_t)r->N, 0.0);
     if (r->dx.p) (void)hipMemcpyAsync(r->u.data(), r->dx.p, sizeof(double) * r->N, hipMemcpyDeviceToHost, st);
     (void)hipStreamSynchronize(st);
-    if (r->P) psw_problem_destroy(r->P);
+    // every kernel of this request ran on st, which has drained: free without a device-wide
+    // synchronisation, so other lanes' solves keep running
+    delete r->P;
     r->P = nullptr;
     r->dx.release();
     r->df.release();
@@ -1655,6 +1797,9 @@ psw_status psw_server_create(size_t budget_bytes, const psw_server_opts *opts, p
         delete S;
         return PSW_EDEVICE;
     }
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, S->device) == hipSuccess && lds > 0)
+        S->lds_limit = (size_t)lds;
     S->budget = budget_bytes;
     if (opts) {
         if (opts->prec < PSW_F64 || opts->prec > PSW_BF16 || (opts->precond != PSW_SSOR && opts->precond != PSW_ILU0) ||
@@ -1690,7 +1835,7 @@ psw_status psw_server_submit(psw_server *S, int dim, const int64_t n[3], const d
         r->N *= n[a];
         nodes *= n[a] + 2;
     }
-    r->bytes = request_bytes(dim, r->n, S->prec);
+    r->bytes = request_bytes(dim, r->n, S->prec, S->precond, S->lds_limit);
     if (r->bytes > S->budget) return PSW_EBUSY;
     for (int a = 0; a < dim; ++a) r->alpha[a].assign(alpha[a], alpha[a] + nodes);
     r->f.assign(f, f + r->N);
@@ -1704,6 +1849,16 @@ psw_status psw_server_submit(psw_server *S, int dim, const int64_t n[3], const d
     (dim == 2 ? S->q2 : S->q3).push_back(raw);
     *ticket = raw->id;
     S->cv.notify_all();
+    return PSW_OK;
+}
+
+psw_status psw_server_request_bytes(psw_server *S, int dim, const int64_t n[3], size_t *bytes) {
+    if (!S || !n || !bytes || (dim != 2 && dim != 3)) return PSW_EINVAL;
+    for (int a = 0; a < dim; ++a)
+        if (n[a] < 4 || n[a] > (1 << 16)) return PSW_EINVAL;
+    int64_t nn[3] = {1, 1, 1};
+    for (int a = 0; a < dim; ++a) nn[a] = n[a];
+    *bytes = request_bytes(dim, nn, S->prec, S->precond, S->lds_limit);
     return PSW_OK;
 }
 
@@ -1944,6 +2099,32 @@ psw_status psw_set_decomposition(psw_problem *P, const int p[3], int overlap, in
     return PSW_OK;
 }
 
+psw_status psw_problem_device_bytes(psw_problem *P, size_t *bytes) {
+    if (!P || !bytes) return PSW_EINVAL;
+    *bytes = problem_device_bytes(P);
+    return PSW_OK;
+}
+
+psw_status psw_get_sweep_coefficients(psw_problem *P, psw_precond kind, int k, void *out, void *stream) {
+    if (!P || !out || (kind != PSW_SSOR && kind != PSW_ILU0) || k < 0 || k > 2 * P->dim) return PSW_EINVAL;
+    if (!P->has_diag || !P->has_decomp) return PSW_ESTATE;
+    DeviceGuard dg(P->device);
+    hipStream_t st = (hipStream_t)stream;
+    psw_status ps = precond_setup(P, kind, st);
+    if (ps) return ps;
+    const PrecState &S = P->pc[kind];
+    const DevBuf &src = k == 0 ? S.piv : S.diag[k];
+    HIPCHK(hipMemcpyAsync(out, src.p, store_bytes(store_of(P->prec)) * (size_t)P->N, hipMemcpyDeviceToDevice, st));
+    return PSW_OK;
+}
+
+psw_status psw_set_path(psw_problem *P, int path) {
+    if (!P || (path != PSW_PATH_AUTO && path != PSW_PATH_GENERIC)) return PSW_EINVAL;
+    P->force_generic = path == PSW_PATH_GENERIC;
+    invalidate(P);
+    return PSW_OK;
+}
+
 psw_status psw_sweep(psw_problem *P, int64_t iteration, const double *u_in, const double *f, double *u_out,
                      void *stream) {
     if (!P || !u_in || !f || !u_out || iteration < 0 || u_in == u_out) return PSW_EINVAL;
@@ -2043,15 +2224,8 @@ psw_status psw_solve(psw_problem *P, psw_method method, psw_precond precond, dou
     switch (method) {
     case PSW_SOR_STATIONARY: ps = solve_stationary(P, rtol, maxit, f, u, &loc, st); break;
     case PSW_CG:
-        // a single large problem runs faster on the host-driven loop; the
-        // graph-replayed batch path can be forced for testing
-        if (batch_eligible(P, precond) && std::getenv("PSW_BATCH_CG") && std::getenv("PSW_BATCH_CG")[0] == '1') {
-            psw_problem *pp[1] = {P};
-            const double *ff[1] = {f};
-            double *uu[1] = {u};
-            ps = batch_cg(1, pp, ff, uu, precond, rtol, maxit, &loc, st);
-            if (ps != PSW_ENOTSUP) break;
-        }
+        // a single problem runs on the host-driven loop (psw_batch_solve with count = 1 takes the
+        // graph-replayed batch path)
         ps = solve_cg(P, precond, rtol, maxit, f, u, &loc, st);
         break;
     case PSW_FGMRES: ps = solve_fgmres(P, precond, rtol, maxit, restart, f, u, &loc, st); break;

@@ -18,6 +18,20 @@ struct TileDesc {
 // Storage precisions of the diagonals used by the preconditioner sweeps.
 enum class Store { F64 = 0, F32 = 1, BF16 = 2 };
 
+// The one FP64 -> BF16 conversion of the library: round to nearest, ties to
+// even.  The value is first rounded to FP32 by truncation with a sticky bit
+// (round to odd), which keeps every bit below the BF16 rounding position that
+// decides the rounding, then rounded to nearest even at bit 16.  Used for the
+// stored coefficients of every BF16 path.
+__device__ __forceinline__ uint16_t f64_to_bf16(double x) {
+    const float t = __double2float_rz(x);
+    uint32_t u = __float_as_uint(t);
+    if ((double)t != x && (u & 0x7f800000u) != 0x7f800000u) u |= 1u;
+    const uint32_t r = u + 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(r >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
 // Geometry of one sweep pass: grid, tile table and the base direction of the
 // pass (the direction of tile (0,0,0); the sign on axis a flips for odd tile
 // coordinate a, so neighbouring tiles sweep in opposite directions).

@@ -28,8 +28,6 @@
 namespace psw {
 
 // ------------------------------------------------------------------ loads
-__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
-
 template <typename T, typename S> __device__ __forceinline__ T ldv(const S *p, int64_t i);
 template <> __device__ __forceinline__ double ldv<double, double>(const double *p, int64_t i) { return p[i]; }
 template <> __device__ __forceinline__ float ldv<float, float>(const float *p, int64_t i) { return p[i]; }
@@ -1528,16 +1526,7 @@ hipError_t launch_residual(int dim, const int n[3], const double *const *diag, c
     return hipGetLastError();
 }
 
-// FP64 -> storage precision.  BF16: round to odd into FP32 first, then to
-// nearest even into BF16, which equals direct round-to-nearest-even.
-__device__ __forceinline__ uint16_t f64_to_bf16(double x) {
-    float t = __double2float_rz(x);
-    uint32_t u = __float_as_uint(t);
-    if ((double)t != x && (u & 0x7f800000u) != 0x7f800000u) u |= 1u;
-    uint32_t r = u + 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(r >> 16);
-}
-
+// FP64 -> storage precision (FP32: the hardware's round to nearest even; BF16: f64_to_bf16)
 __global__ void k_convert(const double *src, void *dst, int kind, int64_t N, double scale) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
         double v = src[i] * scale;

@@ -1,11 +1,12 @@
-"""Iteration counts of the sequential preconditioners (one subdomain, p = 1) on the measured workloads.
+"""Iteration counts of the sequential and decomposed preconditioners on the measured workloads.
 
 With one subdomain the decomposed ILU(0) is lexicographic ILU(0), and its symmetric form is M^-1
 itself.  The counts are the CG iterations to a relative residual of 1e-8 from x0 = 0, computed by the
 FP64 CPU oracle on the same seeded inputs as the GPU measurements, and written to
 sequential_iterations.json beside this script.  Run: python tests/golden/make_sequential_iterations.py
-[sor64|2d|3d]  (the 2048^2 case takes tens of minutes on one core).
+[sor64|2d|2d16|2dssor|2dssor16|3d]  (each 2048^2 case takes one to two hours on one core).
 """
+import fcntl
 import json
 import math
 import os
@@ -22,10 +23,11 @@ from oracle import oracle as O  # noqa: E402
 OUT = os.path.join(HERE, "sequential_iterations.json")
 
 
-def run(name, w, kind="ilu0", rtol=1e-8):
+def run(name, w, kind="ilu0", rtol=1e-8, p=None):
     dim, n = w["dim"], w["n"]
+    p = (1,) * dim if p is None else tuple(p)
     diags = O.assemble(dim, n, w["alphas"], w["beta"])
-    pc = O.Precond(kind, dim, n, (1,) * dim, diags, omega=1.0)
+    pc = O.Precond(kind, dim, n, p, diags, omega=1.0)
     calls = [0]
     t0 = time.time()
 
@@ -36,7 +38,7 @@ def run(name, w, kind="ilu0", rtol=1e-8):
         return pc.apply_sym(r)
 
     _, iters, rel = O.cg(lambda x: O.spmv(dim, n, diags, x), apply_m, w["f"], rtol=rtol, maxit=100000)
-    rec = {"workload": name, "precond": kind, "subdomains": [1] * dim, "rtol": rtol, "iterations": int(iters),
+    rec = {"workload": name, "precond": kind, "subdomains": list(p), "rtol": rtol, "iterations": int(iters),
            "relres_true": float(rel), "cpu_s": round(time.time() - t0, 1)}
     print(json.dumps(rec), flush=True)
     return rec
@@ -64,8 +66,18 @@ if __name__ == "__main__":
         new["poisson2d64_sor"] = run_sor64()
     if which in ("3d", "all"):
         new["poisson3d256"] = run("3D Poisson 7-point 256^3", synth.poisson_3d(n=256))
+    name2 = "2D var-coef diffusion 2048x2048"
     if which in ("2d", "all"):
-        new["varcoef2048"] = run("2D var-coef diffusion 2048x2048", synth.varcoef_2d(n=2048))
-    recs = json.load(open(OUT)) if os.path.exists(OUT) else {}
-    recs.update(new)
-    json.dump(recs, open(OUT, "w"), indent=1, sort_keys=True)
+        new["varcoef2048"] = run(name2, synth.varcoef_2d(n=2048))
+    if which in ("2d16", "all"):
+        new["varcoef2048_p16"] = run(name2, synth.varcoef_2d(n=2048), p=(16, 16))
+    if which in ("2dssor", "all"):
+        new["varcoef2048_ssor"] = run(name2, synth.varcoef_2d(n=2048), kind="ssor")
+    if which in ("2dssor16", "all"):
+        new["varcoef2048_ssor_p16"] = run(name2, synth.varcoef_2d(n=2048), kind="ssor", p=(16, 16))
+    # several runs may finish at once: merge under an exclusive lock
+    with open(OUT + ".lock", "w") as lk:
+        fcntl.flock(lk, fcntl.LOCK_EX)
+        recs = json.load(open(OUT)) if os.path.exists(OUT) else {}
+        recs.update(new)
+        json.dump(recs, open(OUT, "w"), indent=1, sort_keys=True)

@@ -69,3 +69,36 @@ def test_batch_iterations_match_oracle(kind):
     infos = P.batch_solve(probs, fs, us, precond=kind, rtol=1e-8)
     for info, it in zip(infos, refs):
         assert info["converged"] and abs(info["iters"] - it) <= 1, (info, it)
+
+
+@pytest.mark.parametrize("kind", ["ssor", "ilu0"])
+def test_batch_solution_matches_oracle(kind):
+    """Batched FP64 CG against the oracle's FP64 CG: every solution within 1e-6 (relative 2-norm) of the
+    oracle's iterate, and a true residual, through the oracle's own product, within the tolerance."""
+    import paper_1008_3699_amd as P
+    import torch
+    specs = [(64, 0.05, (2, 2)), (90, 0.6, (3, 2)), (37, 1.0, (1, 1)), (120, 0.003, (4, 3))]
+    probs, fs, refs, ops = [], [], [], []
+    for i, (n, eps, p) in enumerate(specs):
+        al, f = _aniso(n, eps, 1300 + i)
+        diags = O.assemble(2, (n, n), al)
+        pc = O.Precond(kind, 2, (n, n), p, diags, omega=1.0)
+        x, it, _ = O.cg(lambda v, d=diags, m=n: O.spmv(2, (m, m), d, v), pc.apply_sym, f, rtol=1e-8)
+        refs.append((x, it))
+        ops.append((diags, f))
+        g = make_problem(2, (n, n), al)
+        g.set_relaxation([1.0])
+        g.set_decomposition(p, overlap=2)
+        probs.append(g)
+        fs.append(to_dev(f))
+    us = [torch.zeros_like(f) for f in fs]
+    infos = P.batch_solve(probs, fs, us, precond=kind, rtol=1e-8)
+    for (n, _, _), info, u, (x, it), (diags, f) in zip(specs, infos, us, refs, ops):
+        got = to_np(u)
+        err = np.linalg.norm(got - x) / np.linalg.norm(x)
+        rel = np.linalg.norm(f - O.spmv(2, (n, n), diags, got)) / np.linalg.norm(f)
+        print(f"n={n}: iters {info['iters']} (oracle {it}), error vs oracle {err:.2e}, true relres {rel:.2e}",
+              flush=True)
+        assert info["converged"] and abs(info["iters"] - it) <= 1
+        assert err <= 1e-6
+        assert rel <= 1.05e-8

@@ -78,23 +78,19 @@ def test_overlap_changes_no_result(dim, n, p):
     assert relmax(outs[0], ref) <= 1e-12
 
 
-@pytest.fixture(params=["pipelined", "generic"])
-def path(request, monkeypatch):
-    """2D problems run the wavefront-pipelined kernels unless PSW_FORCE_GENERIC=1."""
-    if request.param == "generic":
-        monkeypatch.setenv("PSW_FORCE_GENERIC", "1")
-    else:
-        monkeypatch.delenv("PSW_FORCE_GENERIC", raising=False)
+@pytest.fixture(params=["auto", "generic"])
+def path(request):
+    """Kernel path of the preconditioner passes (psw_set_path): 'auto' takes the wavefront-pipelined
+    2D passes and the 3D LDS-tile passes where they apply, 'generic' the level kernels."""
     return request.param
 
 
 @pytest.mark.parametrize("kind", ["ssor", "ilu0"])
 @pytest.mark.parametrize("dim,n,p", PRECOND_CASES)
 def test_precond_half_sweeps_f64(kind, dim, n, p, path):
-    if dim == 3 and path == "pipelined":
-        pytest.skip("3D problems use the generic kernels only")
     pr, diags = _prob(dim, n, seed=5)
     g = make_problem(dim, n, pr["alphas"])
+    g.set_path(path)  # FP64 3D passes run the level kernels on either path
     w = 1.3
     g.set_relaxation([w])
     g.set_decomposition(p, overlap=2, phase=0)
@@ -151,6 +147,7 @@ def test_spmv_and_dot(dim, n):
 def test_precond_mixed_precision_error(prec, bound, dim, n, p, path):
     pr, diags = _prob(dim, n, seed=17)
     g = make_problem(dim, n, pr["alphas"], prec=prec)
+    g.set_path(path)
     g.set_relaxation([1.0])
     g.set_decomposition(p, overlap=2, phase=0)
     import torch
@@ -170,7 +167,7 @@ TILE3_CASES = [((12, 10, 9), (2, 2, 3)), ((9, 9, 9), (1, 1, 1)), ((17, 13, 11), 
 
 @pytest.mark.parametrize("prec,bound", [("f32", 2e-6), ("bf16", 2e-2)])
 @pytest.mark.parametrize("n,p", TILE3_CASES)
-def test_tile3_half_sweeps(prec, bound, n, p, monkeypatch):
+def test_tile3_half_sweeps(prec, bound, n, p):
     """3D passes with the whole tile in LDS (FP32 arithmetic): every pass against the FP64 oracle, and
     against the generic level kernels in the same precision.  Ragged tiles, a single tile, and tiles of
     20 x 32 x 32 points (the largest cross-section, 1024 pencils, that one workgroup holds)."""
@@ -179,11 +176,8 @@ def test_tile3_half_sweeps(prec, bound, n, p, monkeypatch):
     pr, diags = _prob(dim, n, seed=31)
     outs = {}
     for mode in ("tile", "generic"):
-        if mode == "generic":
-            monkeypatch.setenv("PSW_FORCE_GENERIC", "1")
-        else:
-            monkeypatch.delenv("PSW_FORCE_GENERIC", raising=False)
         g = make_problem(dim, n, pr["alphas"], prec=prec)
+        g.set_path("auto" if mode == "tile" else "generic")
         g.set_relaxation([1.2])
         g.set_decomposition(p, overlap=2, phase=0)
         for kind in ("ssor", "ilu0"):
@@ -355,6 +349,14 @@ def test_full_size_varcoef_2048_half_sweeps(kind):
     g.precond_half(kind, 2, r, out)
     yt = O.dsolve_t(2, n, p, pc.dirs_b, diags, pc.piv, w["f"])
     assert relmax(to_np(out), yt) <= 1e-12
+    # the two passes that take the intermediate (start-coupled backward, end-coupled second transposed)
+    g.precond_half(kind, 1, to_dev(y), out)
+    assert relmax(to_np(out), pc.backward(y)) <= 1e-12
+    g.precond_half(kind, 3, to_dev(yt), out)
+    assert relmax(to_np(out), pc.c * O.dsolve_t(2, n, p, pc.dirs_f, diags, pc.piv, pc.piv * yt)) <= 1e-12
+    # the symmetric form the CG measurement applies
+    g.precond_apply(kind, r, out, symmetric=True)
+    assert relmax(to_np(out), pc.apply_sym(w["f"])) <= 1e-12
 
 
 def test_pass_timing_records_launches():

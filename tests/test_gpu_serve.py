@@ -33,15 +33,16 @@ def _serve(srv, reqs):
 
 @pytest.fixture(scope="module")
 def mix():
+    # the 40^3 request has 2x2x2 subdomains: coupled 3D faces and the two-stream 3D split in the mix
     specs = [(2, 96, 11), (2, 64, 12), (3, 20, 13), (2, 150, 14), (2, 72, 15), (3, 16, 16), (2, 130, 17),
-             (2, 64, 18), (2, 200, 19)]
+             (2, 64, 18), (2, 200, 19), (3, 40, 20)]
     return [_req(*s) for s in specs]
 
 
 @pytest.mark.parametrize("prec,precond", [("f32", "ilu0"), ("f64", "ssor")])
 def test_alone_equals_in_mix(mix, prec, precond):
     import paper_1008_3699_amd as P
-    probe = [0, 2, 3]  # two 2D requests and one 3D request, each served alone first
+    probe = [0, 2, 3, 9]  # two 2D requests and two 3D requests (one of 2x2x2 tiles), each served alone first
     with P.Server(2 << 30, prec=prec, precond=precond, rtol=RTOL) as srv:
         alone = {i: _serve(srv, [mix[i]])[0] for i in probe}
         together = _serve(srv, mix)
@@ -60,13 +61,14 @@ def test_alone_equals_in_mix(mix, prec, precond):
 
 def test_admission_by_budget_serialises_without_changing_results(mix):
     import paper_1008_3699_amd as P
-    L = P.lib()
-    del L  # loaded: the byte estimate is internal; a budget just above one request admits one at a time
     sub = [mix[1], mix[4], mix[7]]  # 64^2, 72^2, 64^2
     with P.Server(2 << 30, prec="f32", precond="ilu0", rtol=RTOL) as srv:
         ref = _serve(srv, sub)
-    # 72^2 needs about 72*72*(16*8+20*4+16) bytes plus nodes: ~1.25 MB; 1.5 MB admits one request at a time
-    with P.Server(1_500_000, prec="f32", precond="ilu0", rtol=RTOL) as srv:
+        need = [srv.request_bytes(2, r["n"]) for r in sub]
+    # a budget that holds the largest request but no two of them admits one request at a time
+    budget = max(need) + min(need) // 2
+    assert budget < need[0] + need[1] and budget < need[1] + need[2]
+    with P.Server(budget, prec="f32", precond="ilu0", rtol=RTOL) as srv:
         got = _serve(srv, sub)
         with pytest.raises(P.PswError) as e:
             srv.submit(2, (200, 200), mix[8]["alphas"], mix[8]["f"])
@@ -100,3 +102,39 @@ def test_served_matches_plain_solver(mix):
     print(f"served iters={info['iters']} plain iters={pinfo['iters']} rel diff={err:.2e}", flush=True)
     # both solutions satisfy ||f - A u|| <= 1e-8 ||f||; the coefficient contrast (1e4) bounds their distance
     assert err < 1e-4
+
+
+@pytest.mark.parametrize("dim,n,prec", [(2, 200, "f32"), (2, 333, "bf16"), (3, 64, "f32"), (3, 64, "bf16"),
+                                        (3, 40, "f32")])
+def test_admission_estimate_covers_the_allocation(dim, n, prec):
+    """The admission estimate of a request against what its problem really holds after a CG solve with
+    the server's decomposition (3D: 32-point tiles, so 64^3 has the 32^3 tiles with their face images;
+    2D: the autotuned tile side), plus its right-hand side, solution and node coefficients."""
+    import torch
+    import paper_1008_3699_amd as P
+    from gpu_util import dev
+    req = _req(dim, n, 77)
+    N = n ** dim
+    nodes = (n + 2) ** dim
+    with P.Server(1 << 34, prec=prec, precond="ilu0", rtol=RTOL) as srv:
+        est = srv.request_bytes(dim, req["n"])
+    if dim == 3:
+        p = tuple(max(1, min(n // 2, (n + 31) // 32)) for _ in range(3))
+    else:
+        b = max(32, ((n + 32) // 64) * 64)
+        pb, _ = P.autotune(2, (b, b), prec=prec, precond="ilu0")
+        side = max(2, b // pb[0])
+        p = tuple(max(1, min(n // 2, (n + side - 1) // side)) for _ in range(2))
+    pr = P.Problem(dim, req["n"])
+    pr.assemble([torch.tensor(a.reshape(-1), dtype=torch.float64, device=dev()) for a in req["alphas"]], 0.0, prec)
+    pr.set_relaxation(1.0)
+    pr.set_decomposition(p, 2)
+    f = torch.tensor(req["f"], dtype=torch.float64, device=dev())
+    u = torch.zeros_like(f)
+    info = pr.solve("cg", "ilu0", f, u, rtol=RTOL)
+    assert info["converged"]
+    held = pr.device_bytes() + 16 * N + 8 * dim * nodes
+    print(f"dim={dim} n={n} {prec} p={p}: estimate {est} B, held {held} B ({est / held:.3f}x)", flush=True)
+    assert held <= est
+    # 3D has one decomposition; 2D reserves for the largest footprint among the tile sides the tuner may pick
+    assert est <= 1.001 * held if dim == 3 else est <= 1.25 * held
