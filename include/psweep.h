@@ -152,6 +152,21 @@ psw_status psw_precond_setup(psw_problem *prob, psw_precond kind, void *stream);
 psw_status psw_precond_apply(psw_problem *prob, psw_precond kind, int symmetric, const double *r,
                              double *z, void *stream);
 
+/* z = M^-1 r (the pair form of psw_precond_apply, symmetric = 0) without
+ * allocating: for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid it).  The
+ * intermediate vector of the forward pass lives in a fixed 64 MiB device
+ * array of the library, one per GPU, held until the process ends; N times
+ * the intermediate's element size (8 bytes for FP64 sweeps, 4 for FP32 and
+ * BF16) must fit in it, else PSW_EINVAL.  The preconditioner must already be
+ * set up (psw_precond_setup or an earlier apply or solve), else PSW_ESTATE.
+ * Every call on a GPU uses that GPU's one array: calls that overlap in time on
+ * one GPU (other streams, other threads, other handles) race and give wrong
+ * results; calls ordered on one stream are safe.  Results are identical to
+ * psw_precond_apply with symmetric = 0. */
+psw_status psw_precond_apply_noalloc(psw_problem *prob, psw_precond kind, const double *r, double *z,
+                                     void *stream);
+
 /* One half-sweep of the preconditioner, FP64 in and out (for measurement and
  * tests): which = 0: y = (Piv - N1)^-1 r;  1: z = c (Piv - N2)^-1 Piv y;
  * 2: y = (Piv - N2)^-T r;  3: z = c (Piv - N1)^-T Piv y.  (Piv, c) =

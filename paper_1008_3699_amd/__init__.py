@@ -76,6 +76,7 @@ def lib():
             "psw_set_path": [vp, ci],
             "psw_get_sweep_coefficients": [vp, ci, ci, vp, vp],
             "psw_problem_device_bytes": [vp, ctypes.POINTER(ctypes.c_size_t)],
+            "psw_precond_apply_noalloc": [vp, ci, vp, vp, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -208,6 +209,11 @@ class Problem:
     def precond_apply(self, kind, r, z, symmetric=False, stream=None):
         _check(lib().psw_precond_apply(self._h, _KIND[kind], int(bool(symmetric)), _ptr(r, self.N, "r"),
                                        _ptr(z, self.N, "z"), _stream(stream)), "psw_precond_apply")
+
+    def precond_apply_noalloc(self, kind, r, z, stream=None):
+        """z = M^-1 r (pair form) with the library's fixed scratch array; no device allocation."""
+        _check(lib().psw_precond_apply_noalloc(self._h, _KIND[kind], _ptr(r, self.N, "r"), _ptr(z, self.N, "z"),
+                                               _stream(stream)), "psw_precond_apply_noalloc")
 
     def precond_half(self, kind, which, inp, out, stream=None):
         _check(lib().psw_precond_half(self._h, _KIND[kind], int(which), _ptr(inp, self.N, "in"),

@@ -1785,6 +1785,30 @@ void srv_lane3d(psw_server *S) {
 
 } // namespace
 
+// ------------------------------------------------ preconditioner without allocation
+// The intermediate vector of the pair form lives in a fixed device array.  Host code never passes
+// the array's name to a kernel: it takes the array's device address once per device with
+// hipGetSymbolAddress and uses that pointer.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64] = {};
+
+// device address of `scratch` on device dev (dev current); nullptr on failure
+void *scratch_ptr(int dev) {
+    if (dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+} // namespace
+
 // ====================================================================== C ABI
 extern "C" {
 
@@ -2097,6 +2121,21 @@ psw_status psw_set_decomposition(psw_problem *P, const int p[3], int overlap, in
     P->has_decomp = true;
     invalidate(P);
     return PSW_OK;
+}
+
+psw_status psw_precond_apply_noalloc(psw_problem *P, psw_precond kind, const double *r, double *z, void *stream) {
+    if (!P || !r || !z || r == z || (kind != PSW_SSOR && kind != PSW_ILU0)) return PSW_EINVAL;
+    if ((size_t)P->N * (P->prec == PSW_F64 ? 8 : 4) > kNoAllocScratchBytes) return PSW_EINVAL;
+    if (!P->has_diag || !P->has_decomp || !P->pc[kind].ready) return PSW_ESTATE;
+    DeviceGuard dg(P->device);
+    void *y = scratch_ptr(P->device);
+    if (!y) return PSW_EDEVICE;
+    hipStream_t st = (hipStream_t)stream;
+    const bool f64 = P->prec == PSW_F64;
+    // the forward pass writes every point of y before the backward pass reads it
+    psw_status ps = half(P, kind, 0, r, true, false, y, f64, 1.0, st);
+    if (ps) return ps;
+    return half(P, kind, 1, y, f64, true, z, true, P->pc[kind].c, st);
 }
 
 psw_status psw_problem_device_bytes(psw_problem *P, size_t *bytes) {
