@@ -750,28 +750,37 @@ __device__ __forceinline__ EndFrame2 end_frame2(const int sig[2], int n0, int n1
     return f;
 }
 
-// The coupled end face on axis a owned by this tile (the tile sweeps towards
+// The coupled end face on axis A owned by this tile (the tile sweeps towards
 // it): all data of the 2x2 chain that does not depend on the chain itself is
 // gathered into LDS by the workgroup; one thread then runs the recurrence.
-template <typename T, typename S, typename TIN, typename TOUT>
-__device__ void end_face2d_body(const EndFrame2 &E, int a, int n0, const GP<S> *const *diag, const GP<S> *piv,
+// The axis is a template argument and the diagonals are picked by selects, so
+// that no frame array is indexed at run time (that would put it in scratch
+// memory, one memory round trip per access).
+template <int A, typename T, typename S, typename TIN, typename TOUT>
+__device__ void end_face2d_body(const EndFrame2 &E, int n0, const GP<S> *const *diag, const GP<S> *piv,
                                 const GP<TIN> *in, bool scale_by_piv, GP<TOUT> *out, unsigned char *smem) {
-    const int b = 1 - a;
-    if (!(E.d[a] > 0 && E.endc[a])) return;
-    const int *d = E.d, *len = E.len, *lo = E.lo;
-    const int nb = E.endc[b] ? len[b] - 1 : len[b];
+    constexpr int B = 1 - A;
+    const int da = A ? E.d[1] : E.d[0], db = A ? E.d[0] : E.d[1];
+    const int lena = A ? E.len[1] : E.len[0], lenb = A ? E.len[0] : E.len[1];
+    const int loa = A ? E.lo[1] : E.lo[0], lob = A ? E.lo[0] : E.lo[1];
+    const bool endca = A ? E.endc[1] : E.endc[0], endcb = A ? E.endc[0] : E.endc[1];
+    if (!(da > 0 && endca)) return;
+    const int nb = endcb ? lenb - 1 : lenb;
     T *mPQ = reinterpret_cast<T *>(smem);
     T *mQP = mPQ + nb, *cP = mQP + nb, *cQ = cP + nb, *bP = cQ + nb, *bQ = bP + nb;
     auto gidx = [&](int la, int lb) -> int64_t {
-        int c[2];
-        c[a] = d[a] > 0 ? lo[a] + la : lo[a] + len[a] - 1 - la;
-        c[b] = d[b] > 0 ? lo[b] + lb : lo[b] + len[b] - 1 - lb;
-        return (int64_t)c[0] + (int64_t)n0 * c[1];
+        const int ca = da > 0 ? loa + la : loa + lena - 1 - la;
+        const int cb = db > 0 ? lob + lb : lob + lenb - 1 - lb;
+        return A == 0 ? (int64_t)ca + (int64_t)n0 * cb : (int64_t)cb + (int64_t)n0 * ca;
     };
+    // couplings along axis A towards +da / -da, and along B towards +db (diagonal k = 1 + 2 axis + side)
+    const GP<S> *dAp = da > 0 ? diag[2 + 2 * A] : diag[1 + 2 * A];
+    const GP<S> *dAm = da > 0 ? diag[1 + 2 * A] : diag[2 + 2 * A];
+    const GP<S> *dBp = db > 0 ? diag[2 + 2 * B] : diag[1 + 2 * B];
     // P at local (la = len_a-1, lb), Q at la = len_a (across), inward neighbours at len_a-2 and len_a+1
     for (int k = threadIdx.x; k < nb; k += blockDim.x) {
-        const int64_t P = gidx(len[a] - 1, k), Q = gidx(len[a], k);
-        const int64_t Pin = gidx(len[a] - 2, k), Qin = gidx(len[a] + 1, k);
+        const int64_t P = gidx(lena - 1, k), Q = gidx(lena, k);
+        const int64_t Pin = gidx(lena - 2, k), Qin = gidx(lena + 1, k);
         const T DP = ldS<T>(piv, P), DQ = ldS<T>(piv, Q);
         T rp = cvt<T>(in[P]), rq = cvt<T>(in[Q]);
         if (scale_by_piv) {
@@ -779,18 +788,17 @@ __device__ void end_face2d_body(const EndFrame2 &E, int a, int n0, const GP<S> *
             rq *= DQ;
         }
         // couplings of the neighbours towards P / Q (transposed rows)
-        const int sa = d[a], sb = d[b];
-        rp += ldS<T>(diag[dkk(a, +sa)], Pin) * cvt<T>(out[Pin]);
-        rq += ldS<T>(diag[dkk(a, -sa)], Qin) * cvt<T>(out[Qin]);
+        rp += ldS<T>(dAp, Pin) * cvt<T>(out[Pin]);
+        rq += ldS<T>(dAm, Qin) * cvt<T>(out[Qin]);
         const T iP = T(1) / DP, iQ = T(1) / DQ;
-        const T m1 = ldS<T>(diag[dkk(a, -sa)], Q) * iP; // Q's coupling towards P
-        const T m2 = ldS<T>(diag[dkk(a, +sa)], P) * iQ; // P's coupling towards Q
-        mPQ[k] = m1 / (T(1) - m1 * m2);                  // pre-divided by the 2x2 determinant
+        const T m1 = ldS<T>(dAm, Q) * iP; // Q's coupling towards P
+        const T m2 = ldS<T>(dAp, P) * iQ; // P's coupling towards Q
+        mPQ[k] = m1 / (T(1) - m1 * m2);   // pre-divided by the 2x2 determinant
         mQP[k] = m2;
         if (k > 0) {
-            const int64_t Pp = gidx(len[a] - 1, k - 1), Qp = gidx(len[a], k - 1);
-            cP[k] = ldS<T>(diag[dkk(b, +sb)], Pp) * iP;
-            cQ[k] = ldS<T>(diag[dkk(b, +sb)], Qp) * iQ;
+            const int64_t Pp = gidx(lena - 1, k - 1), Qp = gidx(lena, k - 1);
+            cP[k] = ldS<T>(dBp, Pp) * iP;
+            cQ[k] = ldS<T>(dBp, Qp) * iQ;
         } else {
             cP[k] = T(0);
             cQ[k] = T(0);
@@ -853,8 +861,8 @@ __device__ void end_face2d_body(const EndFrame2 &E, int a, int n0, const GP<S> *
     }
     __syncthreads();
     for (int k = threadIdx.x; k < nb; k += blockDim.x) {
-        out[gidx(len[a] - 1, k)] = (TOUT)bP[k];
-        out[gidx(len[a], k)] = (TOUT)bQ[k];
+        out[gidx(lena - 1, k)] = (TOUT)bP[k];
+        out[gidx(lena, k)] = (TOUT)bQ[k];
     }
 }
 
@@ -933,8 +941,12 @@ __global__ void __launch_bounds__(64) k_end_faces2d_fast(EndFaceArgs<T, S, TIN, 
     const EndFrame2 E = end_frame2(A.g.sig, A.g.n[0], A.g.n[1], td);
     const GP<S> *dg[5] = {(const GP<S> *)A.diag[0], (const GP<S> *)A.diag[1], (const GP<S> *)A.diag[2],
                           (const GP<S> *)A.diag[3], (const GP<S> *)A.diag[4]};
-    end_face2d_body<T, S, TIN, TOUT>(E, blockIdx.x & 1, A.g.n[0], dg, (const GP<S> *)A.piv, (const GP<TIN> *)A.in,
-                                     A.scale_by_piv != 0, (GP<TOUT> *)A.out, smem);
+    if (blockIdx.x & 1)
+        end_face2d_body<1, T, S, TIN, TOUT>(E, A.g.n[0], dg, (const GP<S> *)A.piv, (const GP<TIN> *)A.in,
+                                            A.scale_by_piv != 0, (GP<TOUT> *)A.out, smem);
+    else
+        end_face2d_body<0, T, S, TIN, TOUT>(E, A.g.n[0], dg, (const GP<S> *)A.piv, (const GP<TIN> *)A.in,
+                                            A.scale_by_piv != 0, (GP<TOUT> *)A.out, smem);
 }
 
 template <typename T, typename S, typename TIN, typename TOUT>
@@ -1118,9 +1130,14 @@ __global__ void __launch_bounds__(64) k_b_end_faces2d(const BTile *__restrict__ 
     const GP<S> *dg[5] = {as_global<const S>(P.diagS[0]), as_global<const S>(P.diagS[1]),
                           as_global<const S>(P.diagS[2]), as_global<const S>(P.diagS[3]),
                           as_global<const S>(P.diagS[4])};
-    end_face2d_body<T, S, TIN, TOUT>(E, blockIdx.x & 1, P.n0, dg, as_global<const S>(P.pivS),
-                                     as_global<const TIN>(bslot(P, in_slot)), scale_by_piv != 0,
-                                     as_global<TOUT>(bslot(P, out_slot)), smem);
+    if (blockIdx.x & 1)
+        end_face2d_body<1, T, S, TIN, TOUT>(E, P.n0, dg, as_global<const S>(P.pivS),
+                                            as_global<const TIN>(bslot(P, in_slot)), scale_by_piv != 0,
+                                            as_global<TOUT>(bslot(P, out_slot)), smem);
+    else
+        end_face2d_body<0, T, S, TIN, TOUT>(E, P.n0, dg, as_global<const S>(P.pivS),
+                                            as_global<const TIN>(bslot(P, in_slot)), scale_by_piv != 0,
+                                            as_global<TOUT>(bslot(P, out_slot)), smem);
 }
 
 template <typename T, typename S, typename TIN, typename TOUT>

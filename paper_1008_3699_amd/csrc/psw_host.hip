@@ -620,30 +620,25 @@ psw_status half(psw_problem *P, psw_precond kind, int which, const void *in, boo
 
 // The symmetric form in two pieces for the CG loop (pipelined 2D passes only):
 // z1 = c (backward pass) and z2 = the transposed pair with its end faces, so
-// that z = 0.5 z1 + 0.5 c z2.  The two chains are independent: the forward and
-// backward passes run on st, the transposed passes with their end faces on the
-// side stream beside them, with one fork and one join per application (every
-// cross-stream dependency costs a queue bubble).  st has joined on return.
+// that z = 0.5 z1 + 0.5 c z2, formed later inside the kernels that read z.
+// Each pass has one workgroup per tile that holds the tile in LDS, so a pass
+// fills the chip by itself and two passes side by side only time-share it;
+// all passes therefore run on st, ordered so that consecutive passes share
+// their input (the forward and first transposed passes both read r; the
+// backward pass reads the forward pass's output right after it is written).
 psw_status precond_sym_split(psw_problem *P, psw_precond kind, const double *r, double *z1, double *z2,
                              hipStream_t st) {
     PrecState &S = P->pc[kind];
     if (!S.fast) return PSW_ENOTSUP;
-    if (!P->side.ensure()) return PSW_EDEVICE;
     const bool f64 = P->prec == PSW_F64;
     void *y1 = P->w_y.p, *y2 = P->w_y2.p;
-    hipStream_t ss = P->side.s;
     psw_status ps;
-    HIPCHK(hipEventRecord(P->side.fork, st));
-    HIPCHK(hipStreamWaitEvent(ss, P->side.fork, 0));
-    if ((ps = fast_pass(P, kind, 2, r, true, false, y2, f64, 1.0, nullptr, 0.0, ss))) return ps;
-    if ((ps = fast_end(P, kind, 2, r, true, false, y2, f64, ss))) return ps;
-    if ((ps = fast_pass(P, kind, 3, y2, f64, true, z2, true, 1.0, nullptr, 0.0, ss))) return ps;
-    if ((ps = fast_end(P, kind, 3, y2, f64, true, z2, true, ss))) return ps;
-    HIPCHK(hipEventRecord(P->side.join, ss));
+    if ((ps = fast_pass(P, kind, 2, r, true, false, y2, f64, 1.0, nullptr, 0.0, st))) return ps;
     if ((ps = fast_pass(P, kind, 0, r, true, false, y1, f64, 1.0, nullptr, 0.0, st))) return ps;
     if ((ps = fast_pass(P, kind, 1, y1, f64, true, z1, true, S.c, nullptr, 0.0, st))) return ps;
-    HIPCHK(hipStreamWaitEvent(st, P->side.join, 0));
-    return PSW_OK;
+    if ((ps = fast_end(P, kind, 2, r, true, false, y2, f64, st))) return ps;
+    if ((ps = fast_pass(P, kind, 3, y2, f64, true, z2, true, 1.0, nullptr, 0.0, st))) return ps;
+    return fast_end(P, kind, 3, y2, f64, true, z2, true, st);
 }
 
 // The symmetric form in two pieces on the 3D LDS-tile passes: z1 = c (backward)(forward) r in
