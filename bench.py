@@ -9,8 +9,11 @@ relative residual 1e-8, FP64.
 
 Printed: one JSON line.  `value` is sweep Gpoints/s over the whole job:
 interior points x half-sweeps executed / wall time of the timed steps.  The
-roofline object times the dominant kernel (the start-coupled forward
-half-sweep) with HIP events on the stream it runs on.
+roofline object is the decomposed sweep: the start-coupled forward
+half-sweep, the sweep kernel with the largest share of the solve's kernel
+time, timed with HIP events on the stream it runs on inside the timed
+solves; the other three half-sweeps and the fused CG step are reported
+beside it.
 """
 from __future__ import annotations
 
@@ -54,9 +57,13 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample-s", type=float, default=15.0)
-    ap.add_argument("--workload", default="varcoef2048", choices=["varcoef2048", "batch512", "serve", "poisson3d256"],
+    ap.add_argument("--workload", default="varcoef2048",
+                    choices=["varcoef2048", "batch512", "serve", "poisson3d256", "poisson64", "sor2048"],
                     help="varcoef2048: one 2048^2 solve per step (default); batch512: 512 anisotropic problems "
-                         "solved together per step; serve: a stream of Poisson arrivals through the server")
+                         "solved together per step; serve: a stream of Poisson arrivals through the server; "
+                         "poisson3d256: the 3D solve; poisson64: the 64^2 stationary SOR solve; sor2048: "
+                         "decomposed SOR sweeps on the 2048^2 operator")
+    ap.add_argument("--sweeps", type=int, default=200, help="sor2048: sweeps per step")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--n3", type=int, default=256, help="poisson3d256: grid points per axis")
     ap.add_argument("--p3", type=int, default=8, help="poisson3d256: subdomains per axis")
@@ -94,6 +101,10 @@ def main():
         return bench_serve(args)
     if args.workload == "poisson3d256":
         return bench_poisson3d(args)
+    if args.workload == "poisson64":
+        return bench_poisson64(args)
+    if args.workload == "sor2048":
+        return bench_sor2048(args)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     n, p = args.n, args.p
@@ -129,10 +140,10 @@ def main():
     for _ in range(args.warmup):
         one_solve()
     torch.cuda.synchronize()
-    # the fused CG step (the largest share of kernel time) and the forward half-sweep (the method's
-    # decomposed sweep) are timed with HIP events on their stream inside the timed solves
-    g.pass_timing_enable(0, True)
-    g.pass_timing_enable(4, True)
+    # the four half-sweeps and the fused CG step are timed with HIP events on their stream inside
+    # the timed solves (every 8th launch of each)
+    for which in range(5):
+        g.pass_timing_enable(which, True)
     lat = []
     infos = []
     t0 = time.perf_counter()
@@ -149,12 +160,13 @@ def main():
     half_sweeps = sum(4 * (it + 1) for it in iters)
     value = N * half_sweeps / elapsed / 1e9
 
-    k_ms, k_n = g.pass_timing(0)
-    c_ms, c_n = g.pass_timing(4)
-    g.pass_timing_enable(0, False)
-    g.pass_timing_enable(4, False)
-    roofline_sweep = measure_roofline(g, N, args, stream, k_ms=k_ms, k_n=k_n)
-    roofline = cg_step_roofline(N, args, c_ms, c_n)
+    live = {}
+    for which in range(5):
+        live[which] = g.pass_timing(which)
+        g.pass_timing_enable(which, False)
+    roofline = measure_roofline(g, N, args, stream, k_ms=live[0][0], k_n=live[0][1])
+    passes = pass_table(N, args, live)
+    roofline_cg = cg_step_roofline(N, args, *live[4])
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(w, n, p, args.precond, args.cpu_sample_s)
@@ -182,17 +194,45 @@ def main():
         "relres": [i["relres"] for i in infos],
         **(sequential_iterations("varcoef2048", iters) if n == 2048 and args.precond == "ilu0" else {}),
         "roofline": roofline,
-        "roofline_sweep": roofline_sweep,
+        "roofline_passes": passes,
+        "roofline_cg_step": roofline_cg,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
 
 
+def pass_bytes(prec):
+    """Algorithmic bytes per point of the four half-sweeps inside CG.  s = stored coefficient size,
+    y = intermediate (sweep precision, FP64 or FP32).  Passes 0 and 2 read r (8), 1/Piv and two
+    pre-divided couplings (3 s) and write y; passes 1 and 3 read y and two pre-scaled couplings (2 s)
+    and write the FP64 piece of z (8)."""
+    sz = {"f64": 8, "f32": 4, "bf16": 2}[prec]
+    y = 8 if prec == "f64" else 4
+    return {0: 8 + 3 * sz + y, 1: y + 2 * sz + 8, 2: 8 + 3 * sz + y, 3: y + 2 * sz + 8}
+
+
+PASS_NAMES = {0: "forward start-coupled (Piv - N1)^-1", 1: "backward start-coupled c (Piv - N2)^-1 Piv",
+              2: "first transposed (Piv - N2)^-T, interior", 3: "second transposed c (Piv - N1)^-T Piv, interior"}
+
+
+def pass_table(N, args, live):
+    """Live duration and fraction of HBM peak of each half-sweep inside the timed solves."""
+    bpp = pass_bytes(args.prec)
+    out = []
+    for which in range(4):
+        ms, cnt = live[which]
+        gbs = bpp[which] * N / (ms * 1e-3) / 1e9 if ms > 0 else None
+        out.append({"pass": which, "what": PASS_NAMES[which], "bytes_per_point": bpp[which],
+                    "kernel_ms": round(ms, 4), "timed_launches": cnt,
+                    "achieved": round(gbs, 1) if gbs else None,
+                    "frac": round(gbs / HBM_PEAK_GBS, 4) if gbs else None})
+    return out
+
+
 def cg_step_roofline(N, args, c_ms, c_n):
-    """The fused 2D CG step (k_cg_pq2d), the kernel with the largest share of the solve's kernel
-    time: p = z + beta p with z formed from its two pieces, the deferred x update, q = A p and the
-    p.q partials.  Algorithmic bytes per point: z1, z2, old p, five diagonals and x read (72), new p,
-    q and x written (24)."""
+    """The fused 2D CG step (k_cg_pq2d): p = z + beta p with z formed from its two pieces, the
+    deferred x update, q = A p and the p.q partials.  Algorithmic bytes per point: z1, z2, old p,
+    five diagonals and x read (72), new p, q and x written (24)."""
     bpp = 96
     alg = bpp * N
     achieved = alg / (c_ms * 1e-3) / 1e9
@@ -205,6 +245,177 @@ def cg_step_roofline(N, args, c_ms, c_n):
             "kernel_ms": round(c_ms, 4), "timed_launches": c_n,
             "timing": "HIP events on the launching stream around every 8th fused step inside the timed solves",
             "bytes_per_point": bpp, "algorithmic_bytes": alg}
+
+
+def bench_poisson64(args):
+    """64x64 Poisson, 5-point, 4x4 subdomains, overlap 2, decomposed SOR at w = 2/(1+sin(pi/65)) to a
+    relative residual of 1e-8 from u = 0 (residual tested after every sweep).  A launch-bound problem:
+    one sweep is a right-hand-side kernel and a pipelined pass over 16 tiles of 16^2 points."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import paper_1008_3699_amd as P
+    import synth
+
+    dev = torch.device("cuda:0")
+    w = synth.poisson_2d_64()
+    n = w["n"]
+    N = n[0] * n[1]
+    omega = 2.0 / (1.0 + math.sin(math.pi / 65))
+    g = P.Problem(2, n)
+    g.assemble([torch.from_numpy(a).to(dev) for a in w["alphas"]], 0.0, "f64")
+    g.set_relaxation([omega])
+    g.set_decomposition((4, 4), overlap=2, phase=0)
+    f = torch.from_numpy(w["f"]).to(dev)
+    u = torch.zeros(N, dtype=torch.float64, device=dev)
+
+    def one():
+        u.zero_()
+        return g.solve("sor", "none", f, u, rtol=args.rtol, maxit=20000)
+
+    for _ in range(args.warmup):
+        one()
+    torch.cuda.synchronize()
+    infos, lat = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        infos.append(one())
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - s0)
+    elapsed = time.perf_counter() - t0
+    sweeps = [i["iters"] for i in infos]
+    # one sweep alone, back to back, with events on this stream
+    x = torch.randn(N, dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for k in range(8):
+        g.sweep(k, x, f, y)
+    e0.record()
+    for k in range(400):
+        g.sweep(k, x, f, y)
+    e1.record()
+    torch.cuda.synchronize()
+    sweep_ms = e0.elapsed_time(e1) / 400
+    seq = {}
+    try:
+        seq = json.load(open(SEQ_ITERS_FILE))["poisson2d64_sor"]
+    except (OSError, ValueError, KeyError):
+        pass
+    cpu = None
+    if not args.no_cpu:
+        from oracle import oracle as O
+        diags = O.assemble(2, n, w["alphas"])
+        t1 = time.perf_counter()
+        _, s_or, _ = O.stationary_solve(2, n, (4, 4), diags, omega, w["f"], rtol=args.rtol, maxit=20000)
+        dt = time.perf_counter() - t1
+        cpu = {"value": round(N * s_or / dt / 1e9, 5), "unit": "Gpoints/s", "cores": 1, "kind": "oracle",
+               "sample": f"the whole stationary solve ({s_or} decomposed sweeps, residual after each), "
+                         "single-threaded C oracle", "sweeps": s_or, "solve_s": round(dt, 3)}
+    bpp = 64
+    rec = {
+        "metric": "sweep Gpoints/s (whole job, stationary SOR to 1e-8)",
+        "value": round(N * sum(sweeps) / elapsed / 1e9, 4), "unit": "Gpoints/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "2D Poisson 5-point 64x64, 4x4 subdomains, overlap 2, decomposed SOR at "
+                               f"w = 2/(1+sin(pi/65)) = {omega:.6f} to {args.rtol:g}", "n": 64, "subdomains": [4, 4],
+                   "overlap": 2},
+        "sweeps": sweeps,
+        "relres": [i["relres"] for i in infos],
+        "sweeps_sequential_fsor": seq.get("sweeps_sequential"), "sweeps_sequential_rsor": seq.get("sweeps_rsor"),
+        "sweeps_sequential_ssor": seq.get("sweeps_ssor"), "sweeps_oracle_4x4": seq.get("sweeps_4x4"),
+        "sequential_source": "CPU FP64 oracle on the same input (tests/golden/sequential_iterations.json): FSOR = "
+                             "one subdomain with the alternating schedule, RSOR = row-wise from the SW corner, "
+                             "SSOR = SW then NE",
+        "roofline": {"bound": "hbm", "achieved": round(N * bpp / (sweep_ms * 1e-3) / 1e9, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(N * bpp / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 6),
+                     "traffic": None, "kernel": "one decomposed sweep (k_sor_rhs2d + k_fast2d start-coupled pass)",
+                     "kernel_ms": round(sweep_ms, 5), "timed_launches": 400, "bytes_per_point": bpp,
+                     "timing": "events around 400 back-to-back sweeps after the timed solves; 4096 points, so the "
+                               "two launches, not HBM, set the time",
+                     "algorithmic_bytes": N * bpp},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+def bench_sor2048(args):
+    """Decomposed SOR sweeps (Gauss-Seidel, w = 1) on the 2048^2 variable-coefficient operator with 16x16
+    subdomains: u_out = sweep(u_in) at successive schedule steps, ping-pong buffers, on inputs resident in
+    HBM.  Algorithmic bytes per point: u_in, f, five diagonals, u_out = 64."""
+    import numpy as np
+    import torch
+
+    import paper_1008_3699_amd as P
+    import synth
+
+    dev = torch.device("cuda:0")
+    n, p = args.n, args.p
+    w = synth.varcoef_2d(n=n)
+    N = n * n
+    al = torch.from_numpy(w["alphas"][0]).to(dev)
+    g = P.Problem(2, (n, n))
+    g.assemble([al, al], 0.0, "f64")
+    g.set_relaxation([1.0])
+    g.set_decomposition((p, p), overlap=args.overlap, phase=0)
+    f = torch.from_numpy(w["f"]).to(dev)
+    ua = torch.zeros(N, dtype=torch.float64, device=dev)
+    ub = torch.empty_like(ua)
+    for k in range(8):
+        g.sweep(k, ua, f, ub)
+        ua, ub = ub, ua
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    it = 0
+    for a, b in ev:
+        a.record(stream)
+        for _ in range(args.sweeps):
+            g.sweep(it, ua, f, ub)
+            ua, ub = ub, ua
+            it += 1
+        b.record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms = float(np.mean([a.elapsed_time(b) for a, b in ev])) / args.sweeps
+    bpp = 64
+    achieved = N * bpp / (ms * 1e-3) / 1e9
+    cpu = None
+    if not args.no_cpu:
+        from oracle import oracle as O
+        diags = O.assemble(2, (n, n), w["alphas"])
+        u0 = np.zeros(N)
+        t1 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t1 < args.cpu_sample_s:
+            u0 = O.dsweep(2, (n, n), (p, p), O.schedule(2, (p, p), k, 0), diags, w["f"], uold=u0, omega=[1.0] * 4)
+            k += 1
+        dt = time.perf_counter() - t1
+        cpu = {"value": round(N * k / dt / 1e9, 5), "unit": "Gpoints/s", "cores": 1, "kind": "oracle",
+               "sample": f"{k} decomposed sweeps on the full {n}x{n} grid ({p}x{p} subdomains), single-threaded C oracle"}
+    rec = {
+        "metric": "decomposed SOR sweep Gpoints/s",
+        "value": round(N * args.sweeps * args.steps / elapsed / 1e9, 3), "unit": "Gpoints/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"2D var-coef diffusion {n}x{n}, {p}x{p} subdomains, overlap {args.overlap}, "
+                               f"{args.sweeps} decomposed SOR sweeps (w = 1) per step", "n": n, "subdomains": [p, p]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "one decomposed sweep: k_sor_rhs2d (f + (1/w-1) a^P u_old + N2 u_old, 48 B/pt moved) "
+                               "then the start-coupled pipelined pass k_fast2d (40 B/pt)",
+                     "kernel_ms": round(ms, 4), "timed_launches": args.sweeps * args.steps,
+                     "timing": "HIP events on the launching stream around each step's sweeps",
+                     "bytes_per_point": bpp, "algorithmic_bytes": N * bpp},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
 
 
 def bench_batch(args):
@@ -426,9 +637,10 @@ def measured_traffic(traffic_file=None, kernel_src=None):
 
 
 def measure_roofline(g, N, args, stream, k_ms=None, k_n=None):
-    """Dominant kernel: the forward start-coupled half-sweep (pass 0).  k_ms: its mean duration
-    from the library's HIP events around its launches inside the timed solves.  Without it (the
-    --roofline-only run) the four passes run in turn as inside CG and pass 0 is timed the same way."""
+    """The decomposed sweep: the forward start-coupled half-sweep (pass 0), the sweep kernel with the
+    largest share of the solve's kernel time.  k_ms: its mean duration from the library's HIP events
+    around its launches inside the timed solves.  Without it (the --roofline-only run) the four passes
+    run in turn as inside CG and pass 0 is timed the same way."""
     import torch
     how = "HIP events on the launching stream around every 8th pass-0 launch inside the timed solves"
     if k_ms is None:
@@ -442,8 +654,7 @@ def measure_roofline(g, N, args, stream, k_ms=None, k_n=None):
         g.pass_timing_enable(0, False)
         how = "HIP events around every 8th pass-0 launch, the four passes running in turn"
     else:
-        # inside CG the transposed passes run on a second stream beside this one and share the
-        # chip with it; the same kernel is also timed alone, back to back, after the timed solves
+        # the same kernel is also timed back to back after the timed solves
         r = torch.randn(N, dtype=torch.float64, device=stream.device)
         y = torch.empty_like(r)
         for _ in range(4):
@@ -453,7 +664,7 @@ def measure_roofline(g, N, args, stream, k_ms=None, k_n=None):
             g.precond_half(args.precond, 0, r, y)
         a_ms, a_n = g.pass_timing()
         g.pass_timing_enable(0, False)
-    bpp = {"f64": 40, "f32": 28, "bf16": 20}[args.prec]  # r(8) + Piv + 2 upstream couplings + y
+    bpp = pass_bytes(args.prec)[0]  # r + 1/Piv + 2 upstream couplings + y
     alg_bytes = bpp * N
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
     traffic = measured_traffic() if (args.prec == "f64" and args.n == 2048 and args.p == 16) else None

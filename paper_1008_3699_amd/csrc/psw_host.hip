@@ -141,6 +141,16 @@ struct PrecState {
     bool e3ok[2] = {false, false};
 };
 
+// The stationary 2D sweep on the pipelined passes: the four direction maps of the schedule cycle
+// (index c of the base cycle) packed as start-coupled passes with pivots a^P / w.
+struct StatState {
+    bool ready = false;
+    bool fast = false;
+    int R = 1, lxmax = 1, lymax = 1;
+    FastPassBuf fp[4];
+    DevBuf toff, foff, otab, ooff;
+};
+
 struct psw_problem {
     int device = 0;
     int dim = 2;
@@ -159,6 +169,7 @@ struct psw_problem {
     int ntiles = 0;
     int cmax = 1, l1max = 1, l2max = 1;
     PrecState pc[2];
+    StatState stat;
     // workspace
     DevBuf w_r, w_z, w_p, w_q, w_t, w_y, w_y2, w_z1;
     DevBuf w_y3; // the transposed chain's output in sweep precision (3D LDS-tile passes)
@@ -360,6 +371,66 @@ psw_status fast_setup(psw_problem *P, PrecState &S, hipStream_t st) {
     return PSW_OK;
 }
 
+// Stationary sweep state: step-offset tables as fast_setup, and per direction map of the cycle the
+// pivots a^P / w (w by each subdomain's start corner) packed with the upstream couplings.
+psw_status stat_setup(psw_problem *P, hipStream_t st) {
+    StatState &S = P->stat;
+    S.fast = false;
+    S.ready = true;
+    int R, lxmax, lymax;
+    if (P->dim != 2 || P->force_generic || !fast_shape(2, P->n, P->p, PSW_F64, P->lds_limit, R, lxmax, lymax))
+        return PSW_OK;
+    std::vector<int> lo0, len0, lo1, len1;
+    partition(P->n[0], P->p[0], lo0, len0);
+    partition(P->n[1], P->p[1], lo1, len1);
+    const size_t eb = 8;
+    std::vector<int64_t> toff, foff, ooff;
+    std::vector<int> otab;
+    int64_t t = 0, f = 0;
+    for (int s1 = 0; s1 < P->p[1]; ++s1)
+        for (int s0 = 0; s0 < P->p[0]; ++s0) {
+            const int lx = len0[s0], ly = len1[s1];
+            toff.push_back(t);
+            foff.push_back(f);
+            ooff.push_back((int64_t)otab.size());
+            t += fast2d_tile_elems(lx, ly, R, eb);
+            f += 4 * (int64_t)(lx + ly) + 3;
+            f = (f + 7) & ~(int64_t)7;
+            const size_t o = otab.size();
+            otab.resize(o + fast2d_tab_len(lx, ly, R));
+            fast2d_fill_tab(lx, ly, R, eb, otab.data() + o);
+        }
+    S.ready = false;
+    if (!S.toff.ensure(sizeof(int64_t) * toff.size()) || !S.foff.ensure(sizeof(int64_t) * foff.size()) ||
+        !S.ooff.ensure(sizeof(int64_t) * ooff.size()) || !S.otab.ensure(sizeof(int) * otab.size()))
+        return PSW_ENOMEM;
+    HIPCHK(hipMemcpy(S.toff.p, toff.data(), sizeof(int64_t) * toff.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(S.foff.p, foff.data(), sizeof(int64_t) * foff.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(S.ooff.p, ooff.data(), sizeof(int64_t) * ooff.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(S.otab.p, otab.data(), sizeof(int) * otab.size(), hipMemcpyHostToDevice));
+    psw_status ps = ensure_work(P);
+    if (ps) return ps;
+    double *piv = P->w_y.as<double>(); // pivots of one direction map at a time, consumed by the packing
+    const double *d[7];
+    diag64(P, d);
+    for (int c = 0; c < 4; ++c) {
+        FastPassBuf &B = S.fp[c];
+        if (!B.inv.ensure(eb * t) || !B.ax.ensure(eb * t) || !B.ay.ensure(eb * t) || !B.face.ensure(eb * (f + 8)))
+            return PSW_ENOMEM;
+        const int *sig = kCycle2[c];
+        HIPCHK(launch_sor_piv2d(P->n, P->p, sig, d[0], P->omega, piv, st));
+        const PassGeom g = geom(P, sig);
+        HIPCHK(launch_pack2d(g, Store::F64, R, false, d, piv, S.toff.as<int64_t>(), S.foff.as<int64_t>(), B.inv.p,
+                             B.ax.p, B.ay.p, B.face.p, st));
+    }
+    S.R = R;
+    S.lxmax = lxmax;
+    S.lymax = lymax;
+    S.fast = true;
+    S.ready = true;
+    return PSW_OK;
+}
+
 // 3D problems swept in FP32 whose tiles fit in LDS: pack the four passes' coefficients
 psw_status tile3_setup(psw_problem *P, PrecState &S, hipStream_t st) {
     S.tile3 = false;
@@ -532,6 +603,10 @@ size_t problem_device_bytes(const psw_problem *P) {
         for (const DevBuf &d : S.f3img) b += devbuf_bytes(d);
         for (const DevBuf &d : S.e3img) b += devbuf_bytes(d);
     }
+    const StatState &T = P->stat;
+    b += devbuf_bytes(T.toff) + devbuf_bytes(T.foff) + devbuf_bytes(T.otab) + devbuf_bytes(T.ooff);
+    for (const FastPassBuf &f : T.fp)
+        b += devbuf_bytes(f.inv) + devbuf_bytes(f.ax) + devbuf_bytes(f.ay) + devbuf_bytes(f.face);
     return b;
 }
 
@@ -730,6 +805,50 @@ psw_status host_norm(psw_problem *P, const double *x, double *out, hipStream_t s
     return PSW_OK;
 }
 
+// One decomposed SOR sweep u_out <- sweep(u_in) at schedule step `it`.  2D problems whose tiles fit
+// the pipelined pass: the right-hand side f + (1/w - 1) a^P u_in + N2 u_in into w_z, then the
+// start-coupled pass with pivots a^P / w of the step's direction map; else the level kernel.
+psw_status sweep_once(psw_problem *P, int64_t it, const double *u_in, const double *f, double *u_out,
+                      hipStream_t st) {
+    int sig[3];
+    sched_sig(P, it, sig);
+    const double *d[7];
+    diag64(P, d);
+    if (P->dim == 2 && !P->force_generic) {
+        if (!P->stat.ready) {
+            psw_status ps = stat_setup(P, st);
+            if (ps) return ps;
+        }
+        if (P->stat.fast) {
+            psw_status ps = ensure_work(P);
+            if (ps) return ps;
+            int c = (int)(it % 4);
+            if (P->phase) c ^= 1;
+            StatState &S = P->stat;
+            double *rhs = P->w_z.as<double>();
+            HIPCHK(launch_sor_rhs2d(P->n, P->p, sig, d, P->omega, f, u_in, rhs, st));
+            Fast2dPass fp{};
+            fp.g = geom(P, sig);
+            fp.R = S.R;
+            fp.coupled = true;
+            fp.lxmax = S.lxmax;
+            fp.lymax = S.lymax;
+            fp.s_inv = S.fp[c].inv.p;
+            fp.s_ax = S.fp[c].ax.p;
+            fp.s_ay = S.fp[c].ay.p;
+            fp.face = S.fp[c].face.p;
+            fp.toff = S.toff.as<int64_t>();
+            fp.foff = S.foff.as<int64_t>();
+            fp.otab = S.otab.as<int>();
+            fp.ooff = S.ooff.as<int64_t>();
+            HIPCHK(launch_fast2d(fp, Store::F64, rhs, true, false, u_out, true, 1.0, nullptr, 0.0, st));
+            return PSW_OK;
+        }
+    }
+    HIPCHK(launch_sweep_stationary(geom(P, sig), d, P->omega, u_in, f, u_out, st));
+    return PSW_OK;
+}
+
 psw_status solve_stationary(psw_problem *P, double rtol, int64_t maxit, const double *f, double *u, psw_info *info,
                             hipStream_t st) {
     psw_status ps = ensure_work(P);
@@ -745,10 +864,7 @@ psw_status solve_stationary(psw_problem *P, double rtol, int64_t maxit, const do
     int64_t it = 0;
     bool conv = false;
     for (it = 0; it < maxit;) {
-        int sig[3];
-        sched_sig(P, it, sig);
-        PassGeom g = geom(P, sig);
-        HIPCHK(launch_sweep_stationary(g, d, P->omega, u, f, tmp, st));
+        if ((ps = sweep_once(P, it, u, f, tmp, st))) return ps;
         HIPCHK(hipMemcpyAsync(u, tmp, sizeof(double) * P->N, hipMemcpyDeviceToDevice, st));
         ++it;
         HIPCHK(launch_residual(P->dim, P->n, d, f, u, res, st));
@@ -2018,6 +2134,7 @@ psw_status psw_problem_destroy(psw_problem *P) {
 static void invalidate(psw_problem *P) {
     P->pc[0].ready = false;
     P->pc[1].ready = false;
+    P->stat.ready = false;
 }
 
 psw_status psw_set_diagonals(psw_problem *P, const double *const diag[], int on_device, psw_prec prec, void *stream) {
@@ -2166,12 +2283,7 @@ psw_status psw_sweep(psw_problem *P, int64_t iteration, const double *u_in, cons
     psw_status ps = check_lds(P, 8);
     if (ps) return ps;
     DeviceGuard dg(P->device);
-    int sig[3];
-    sched_sig(P, iteration, sig);
-    PassGeom g = geom(P, sig);
-    const double *d[7];
-    HIPCHK(launch_sweep_stationary(g, diag64(P, d), P->omega, u_in, f, u_out, (hipStream_t)stream));
-    return PSW_OK;
+    return sweep_once(P, iteration, u_in, f, u_out, (hipStream_t)stream);
 }
 
 psw_status psw_precond_setup(psw_problem *P, psw_precond kind, void *stream) {

@@ -53,6 +53,14 @@ struct PassGeom {
 hipError_t launch_sweep_stationary(const PassGeom &g, const double *const *diag, const double *omega8,
                                    const double *uold, const double *f, double *out, hipStream_t st);
 
+// Stationary sweep as a start-coupled pass (2D): right-hand side f + (1/w - 1) a^P u_old + N2 u_old
+// and pivots a^P / w, with w per point from its subdomain's start corner under the direction map sig
+// (omega8: the 4 factors by start corner, host array, passed by value).
+hipError_t launch_sor_rhs2d(const int n[3], const int p[3], const int sig[3], const double *const *diag,
+                           const double *omega8, const double *f, const double *uold, double *out, hipStream_t st);
+hipError_t launch_sor_piv2d(const int n[3], const int p[3], const int sig[3], const double *aP, const double *omega8,
+                            double *piv, hipStream_t st);
+
 // Preconditioner half-sweep, start-coupled: out = cscale * (Piv - N)^-1 (in .* (scale_by_piv ? Piv : 1)).
 // in/out element types follow `in_f64`/`out_f64`; arithmetic in FP64 for Store::F64, else FP32.
 hipError_t launch_half_start(const PassGeom &g, Store s, const void *const *diag, const void *piv,

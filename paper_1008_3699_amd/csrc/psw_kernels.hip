@@ -1526,6 +1526,55 @@ hipError_t launch_residual(int dim, const int n[3], const double *const *diag, c
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- stationary sweep as a start-coupled pass
+// One decomposed SOR sweep in direction map g.sig (Secs. 2-4) multiplied by a^P/omega is
+//   (a^P/w - N1) u_new = f + (1/w - 1) a^P u_old + N2 u_old ,
+// w the factor of the point's own subdomain's start corner, N1 / N2 the couplings towards the
+// upstream / downstream neighbours (whatever subdomain owns them).  The right-hand side below and
+// the pivots a^P/w, per point, turn the sweep into a start-coupled half-sweep of the pipelined kind.
+
+// subdomain coordinate of global coordinate x on an axis of n points cut into p ranges, the first
+// n mod p of them one point longer
+__device__ __forceinline__ int part_of(int x, int n, int p) {
+    const int base = n / p, rem = n % p, big = rem * (base + 1);
+    return x < big ? x / (base + 1) : rem + (x - big) / base;
+}
+
+struct Omega8 {
+    double w[8];
+};
+
+__global__ void k_sor_rhs2d(int n0, int n1, int p0, int p1, int sig0, int sig1, DiagPtrs D, Omega8 om,
+                            const double *__restrict__ f, const double *__restrict__ uold, double *__restrict__ out) {
+    const int64_t N = (int64_t)n0 * n1;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % n0), y = (int)(i / n0);
+        const int d0 = (part_of(x, n0, p0) & 1) ? -sig0 : sig0;
+        const int d1 = (part_of(y, n1, p1) & 1) ? -sig1 : sig1;
+        const int c = (d0 < 0 ? 1 : 0) | (d1 < 0 ? 2 : 0);
+        const double w = c == 0 ? om.w[0] : c == 1 ? om.w[1] : c == 2 ? om.w[2] : om.w[3];
+        const double aP = D.d[0][i];
+        double acc = f[i] + (1.0 / w - 1.0) * aP * uold[i];
+        // downstream neighbours: the side the point's own sweep moves towards
+        const int xd = x + d0, yd = y + d1;
+        if (xd >= 0 && xd < n0) acc += D.d[d0 > 0 ? 2 : 1][i] * uold[i + d0];
+        if (yd >= 0 && yd < n1) acc += D.d[d1 > 0 ? 4 : 3][i] * uold[i + (int64_t)d1 * n0];
+        out[i] = acc;
+    }
+}
+
+__global__ void k_sor_piv2d(int n0, int n1, int p0, int p1, int sig0, int sig1, const double *__restrict__ aP,
+                            Omega8 om, double *__restrict__ piv) {
+    const int64_t N = (int64_t)n0 * n1;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % n0), y = (int)(i / n0);
+        const int d0 = (part_of(x, n0, p0) & 1) ? -sig0 : sig0;
+        const int d1 = (part_of(y, n1, p1) & 1) ? -sig1 : sig1;
+        const int c = (d0 < 0 ? 1 : 0) | (d1 < 0 ? 2 : 0);
+        piv[i] = aP[i] / (c == 0 ? om.w[0] : c == 1 ? om.w[1] : c == 2 ? om.w[2] : om.w[3]);
+    }
+}
+
 // FP64 -> storage precision (FP32: the hardware's round to nearest even; BF16: f64_to_bf16)
 __global__ void k_convert(const double *src, void *dst, int kind, int64_t N, double scale) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
@@ -1534,6 +1583,28 @@ __global__ void k_convert(const double *src, void *dst, int kind, int64_t N, dou
         else if (kind == 1) ((float *)dst)[i] = (float)v;
         else ((uint16_t *)dst)[i] = f64_to_bf16(v);
     }
+}
+
+hipError_t launch_sor_rhs2d(const int n[3], const int p[3], const int sig[3], const double *const *diag,
+                           const double *omega8, const double *f, const double *uold, double *out, hipStream_t st) {
+    DiagPtrs D{};
+    for (int k = 0; k < 5; ++k) D.d[k] = diag[k];
+    Omega8 om{};
+    for (int k = 0; k < 8; ++k) om.w[k] = omega8[k];
+    const int64_t N = (int64_t)n[0] * n[1];
+    hipLaunchKernelGGL(k_sor_rhs2d, dim3(grid_for(N)), dim3(256), 0, st, n[0], n[1], p[0], p[1], sig[0], sig[1], D,
+                       om, f, uold, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sor_piv2d(const int n[3], const int p[3], const int sig[3], const double *aP, const double *omega8,
+                            double *piv, hipStream_t st) {
+    Omega8 om{};
+    for (int k = 0; k < 8; ++k) om.w[k] = omega8[k];
+    const int64_t N = (int64_t)n[0] * n[1];
+    hipLaunchKernelGGL(k_sor_piv2d, dim3(grid_for(N)), dim3(256), 0, st, n[0], n[1], p[0], p[1], sig[0], sig[1], aP,
+                       om, piv);
+    return hipGetLastError();
 }
 
 hipError_t launch_convert(const double *src, void *dst, Store s, int64_t N, double scale, hipStream_t st) {

@@ -13,6 +13,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
@@ -44,8 +46,22 @@ def run(name, w, kind="ilu0", rtol=1e-8, p=None):
     return rec
 
 
+def lex_sweeps(n, diags, omega, f, directions, rtol=1e-8, maxit=20000):
+    """Sweeps of lexicographic SOR (one subdomain) cycling through the given directions until
+    ||f - A u|| / ||f|| <= rtol, from u = 0."""
+    u = np.zeros_like(f)
+    nf = np.linalg.norm(f)
+    for k in range(maxit):
+        u = O.sor_lex(2, n, diags, omega, directions[k % len(directions)], f, u)
+        if np.linalg.norm(f - O.spmv(2, n, diags, u)) / nf <= rtol:
+            return k + 1
+    return maxit
+
+
 def run_sor64():
-    """64^2 Poisson, SOR at omega = 2/(1+sin(pi/65)) to 1e-8: sweeps with one subdomain and with 4x4."""
+    """64^2 Poisson, SOR at omega = 2/(1+sin(pi/65)) to 1e-8: sweeps with one subdomain (the alternating
+    schedule, FSOR), with 4x4, and of row-wise SOR always sweeping from the SW corner (RSOR) and of
+    symmetric SOR (SW then NE, SSOR)."""
     w = synth.poisson_2d_64()
     n = w["n"]
     diags = O.assemble(2, n, w["alphas"], w["beta"])
@@ -54,6 +70,8 @@ def run_sor64():
     for key, p in (("sweeps_sequential", (1, 1)), ("sweeps_4x4", (4, 4))):
         _, sweeps, _ = O.stationary_solve(2, n, p, diags, omega, w["f"], rtol=1e-8, maxit=20000)
         rec[key] = int(sweeps)
+    rec["sweeps_rsor"] = lex_sweeps(n, diags, omega, w["f"], [(1, 1)])
+    rec["sweeps_ssor"] = lex_sweeps(n, diags, omega, w["f"], [(1, 1), (-1, -1)])
     print(json.dumps(rec), flush=True)
     return rec
 

@@ -37,6 +37,27 @@ def test_sor64_counts_reproduce_and_stay_within_ten_percent():
     assert got["sweeps_4x4"] <= 1.10 * got["sweeps_sequential"]
 
 
+def test_sor64_row_wise_and_symmetric_counts_reproduce():
+    """The two other sequential comparators of the 64^2 SOR case: row-wise SOR from the SW corner every
+    sweep (RSOR) and symmetric SOR (SSOR).  At the optimal factor the alternating schedule (FSOR, and the
+    decomposed sweep that follows it) needs about twice RSOR's sweeps; both comparators are reported."""
+    rec = _stored()["poisson2d64_sor"]
+    w = synth.poisson_2d_64()
+    diags = O.assemble(2, w["n"], w["alphas"], w["beta"])
+    omega = rec["omega"]
+    nf = np.linalg.norm(w["f"])
+    for key, dirs in (("sweeps_rsor", [(1, 1)]), ("sweeps_ssor", [(1, 1), (-1, -1)])):
+        u = np.zeros(4096)
+        k = 0
+        while True:
+            u = O.sor_lex(2, w["n"], diags, omega, dirs[k % len(dirs)], w["f"], u)
+            k += 1
+            if np.linalg.norm(w["f"] - O.spmv(2, w["n"], diags, u)) / nf <= 1e-8:
+                break
+        assert k == rec[key], (key, k, rec[key])
+    assert rec["sweeps_rsor"] < rec["sweeps_sequential"]
+
+
 def test_stored_3d_sequential_count_is_a_converged_run():
     rec = _stored()["poisson3d256"]
     assert rec["subdomains"] == [1, 1, 1] and rec["rtol"] == 1e-8
