@@ -56,7 +56,7 @@ typedef enum {
    residuals, dot products and updates are always FP64. */
 typedef enum { PSW_F64 = 0, PSW_F32 = 1, PSW_BF16 = 2 } psw_prec;
 typedef enum { PSW_SSOR = 0, PSW_ILU0 = 1, PSW_NONE = 2 } psw_precond;
-typedef enum { PSW_SOR_STATIONARY = 0, PSW_CG = 1, PSW_FGMRES = 2 } psw_method;
+typedef enum { PSW_SOR_STATIONARY = 0, PSW_CG = 1, PSW_FGMRES = 2, PSW_SOR_RESTRICTED = 3 } psw_method;
 
 typedef struct psw_problem psw_problem;
 
@@ -104,12 +104,12 @@ psw_status psw_set_relaxation(psw_problem *prob, const double *omega, int count)
 
 /* Decomposition into p[0] x p[1] (x p[2]) subdomains: contiguous ranges per
  * axis, the first n mod p ranges one point longer (Sec. 3).  Every
- * subdomain must be at least 2 points long on every axis.  overlap (>= 2) is
- * the depth of the layer beyond a subdomain's own box that its sweep may
- * read.  The exact-coupling sweep, its preconditioners and solves read one
- * layer (two across a coupled start face, Sec. 3, Data structure), so their
- * results do not depend on overlap; it is stored and used only by the
- * restricted-overlap sweep (psw_sweep_restricted).  phase swaps the two
+ * subdomain must be at least 2 points long on every axis.  overlap (>= 0) is
+ * the number of points by which the restricted-overlap sweep
+ * (psw_sweep_restricted) widens every subdomain's box.  The exact-coupling
+ * sweep, its preconditioners and solves read one layer beyond a subdomain
+ * (two across a coupled start face, Sec. 3, Data structure) whatever the
+ * overlap, so their results do not depend on it.  phase swaps the two
  * members of every direction pair of the schedule (Sec. 3, Sweeping
  * directions). */
 psw_status psw_set_decomposition(psw_problem *prob, const int p[3], int overlap, int phase);
@@ -134,6 +134,21 @@ psw_status psw_set_path(psw_problem *prob, int path);
  * arrays of N doubles; u_out must not alias u_in. */
 psw_status psw_sweep(psw_problem *prob, int64_t iteration, const double *u_in, const double *f,
                      double *u_out, void *stream);
+
+/* One restricted-overlap sweep, FP64: the reading of the paper's parallel
+ * experiments under which its PGS/PSOR iteration counts (Sec. 8, Tables
+ * 1d:1-3d:3) are reproduced, in place of the exact coupled blocks of
+ * psw_sweep.  Subdomain s, with the direction of psw_sweep's schedule at
+ * this iteration, widens its box by the decomposition's overlap on every
+ * side (clipped to the grid), sweeps the widened box lexicographically in its
+ * direction with the relaxation factor of its start corner, taking u_in
+ * outside the widened box, and writes only its own points to u_out.  With
+ * overlap 1 the paper's PGS/PSOR counts are matched within 2 %.  PSW_ENOTSUP
+ * when the widened box of the largest subdomain with a ring of one point
+ * (FP64) exceeds one workgroup's LDS.  Device arrays; u_out must not alias
+ * u_in.  psw_solve with PSW_SOR_RESTRICTED iterates it to a tolerance. */
+psw_status psw_sweep_restricted(psw_problem *prob, int64_t iteration, const double *u_in, const double *f,
+                                double *u_out, void *stream);
 
 /* Build the preconditioner state (pivots, packed diagonals) for kind.  Done
  * implicitly by the first psw_precond_apply / psw_solve; returns PSW_EPIVOT
@@ -199,7 +214,8 @@ psw_status psw_spmv(psw_problem *prob, const double *x, double *y, void *stream)
 psw_status psw_dot(psw_problem *prob, const double *x, const double *y, double *out, void *stream);
 
 /* Solve A u = f to ||f - A u||_2 / ||f||_2 <= rtol from the initial guess in
- * u.  method: stationary decomposed SOR (precond ignored), CG with the
+ * u.  method: stationary decomposed SOR (precond ignored; PSW_SOR_RESTRICTED
+ * iterates psw_sweep_restricted instead of psw_sweep), CG with the
  * symmetric form (M^-1 + M^-T)/2 of the preconditioner, or right-
  * preconditioned flexible GMRES(restart) with M^-1.  Returns PSW_ENOCONV when
  * maxit is reached.  info may be NULL.  Blocks until the solve ends. */

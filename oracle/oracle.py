@@ -76,6 +76,7 @@ def lib():
         L.or_dsweep.argtypes = [ctypes.c_int, i64p, ip, i8p, dpp, dp, dp, dp, dp, dp]
         L.or_dsolve_t.argtypes = [ctypes.c_int, i64p, ip, i8p, dpp, dp, dp, dp]
         L.or_ilu_pivots.argtypes = [ctypes.c_int, i64p, ip, i8p, dpp, dp]
+        L.or_ras_sweep.argtypes = [ctypes.c_int, i64p, ip, i8p, dpp, dp, ctypes.c_int, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -192,6 +193,26 @@ def dsweep(dim, n, p, dirs, diags, f, uold=None, piv=None, omega=None):
     return x
 
 
+def _omega_corners(dim, omega):
+    om = np.asarray(omega, np.float64).reshape(-1)
+    return np.ascontiguousarray(np.broadcast_to(om, (1 << dim,)) if om.size == 1 else om)
+
+
+def ras_sweep(dim, n, p, dirs, diags, f, uold, omega, overlap):
+    """One restricted-overlap sweep (see or_ras_sweep in psw_oracle.c): each subdomain sweeps its box
+    widened by `overlap` points, in its own direction, with old values outside; keeps its own points."""
+    pp, keep = _diag_pp(diags)
+    f = _flat(f)
+    uold = _flat(uold)
+    om = _omega_corners(dim, omega)
+    assert om.size == 1 << dim
+    dirs = np.ascontiguousarray(dirs, np.int8)
+    x = np.empty_like(f)
+    _check(lib().or_ras_sweep(dim, _n3(dim, n), _p3(dim, p), dirs.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
+                              pp, _dptr(om), int(overlap), _dptr(uold), _dptr(f), _dptr(x)))
+    return x
+
+
 def dsolve_t(dim, n, p, dirs, diags, piv, b):
     """Solve (Piv - N)^T x = b for the upstream couplings N of the direction map dirs."""
     pp, keep = _diag_pp(diags)
@@ -263,6 +284,21 @@ def stationary_solve(dim, n, p, diags, omega, f, rtol=1e-8, maxit=100000, phase=
     for k in range(maxit):
         dirs = schedule(dim, p, k, phase)
         u = dsweep(dim, n, p, dirs, diags, f, uold=u, omega=omega)
+        rel = np.linalg.norm(f - spmv(dim, n, diags, u)) / nf
+        if rel <= rtol:
+            return u, k + 1, rel
+    return u, maxit, rel
+
+
+def ras_solve(dim, n, p, diags, omega, f, overlap, rtol=1e-8, maxit=100000, phase=0):
+    """Repeat the restricted-overlap sweep with the schedule; stop when ||f-Au||/||f|| <= rtol.
+    Returns (u, sweeps, relres)."""
+    f = _flat(f)
+    u = np.zeros_like(f)
+    nf = np.linalg.norm(f)
+    rel = 1.0
+    for k in range(maxit):
+        u = ras_sweep(dim, n, p, schedule(dim, p, k, phase), diags, f, u, omega, overlap)
         rel = np.linalg.norm(f - spmv(dim, n, diags, u)) / nf
         if rel <= rtol:
             return u, k + 1, rel

@@ -21,7 +21,7 @@ SSOR, ILU0, NONE = 0, 1, 2
 STATIONARY, CG, FGMRES = 0, 1, 2
 _PREC = {"f64": 0, "f32": 1, "bf16": 2}
 _KIND = {"ssor": SSOR, "ilu0": ILU0, "none": NONE}
-_METHOD = {"sor": STATIONARY, "stationary": STATIONARY, "cg": CG, "fgmres": FGMRES}
+_METHOD = {"sor": STATIONARY, "stationary": STATIONARY, "cg": CG, "fgmres": FGMRES, "sor_restricted": 3}
 
 
 class PswError(RuntimeError):
@@ -77,6 +77,7 @@ def lib():
             "psw_get_sweep_coefficients": [vp, ci, ci, vp, vp],
             "psw_problem_device_bytes": [vp, ctypes.POINTER(ctypes.c_size_t)],
             "psw_precond_apply_noalloc": [vp, ci, vp, vp, vp],
+            "psw_sweep_restricted": [vp, i64, vp, vp, vp, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -202,6 +203,11 @@ class Problem:
     def sweep(self, iteration, u_in, f, u_out, stream=None):
         _check(lib().psw_sweep(self._h, int(iteration), _ptr(u_in, self.N, "u_in"), _ptr(f, self.N, "f"),
                                _ptr(u_out, self.N, "u_out"), _stream(stream)), "psw_sweep")
+
+    def sweep_restricted(self, iteration, u_in, f, u_out, stream=None):
+        """One restricted-overlap sweep (widened boxes of the decomposition's overlap)."""
+        _check(lib().psw_sweep_restricted(self._h, int(iteration), _ptr(u_in, self.N, "u_in"), _ptr(f, self.N, "f"),
+                                          _ptr(u_out, self.N, "u_out"), _stream(stream)), "psw_sweep_restricted")
 
     def precond_setup(self, kind, stream=None):
         _check(lib().psw_precond_setup(self._h, _KIND[kind], _stream(stream)), "psw_precond_setup")

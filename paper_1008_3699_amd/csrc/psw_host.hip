@@ -849,8 +849,28 @@ psw_status sweep_once(psw_problem *P, int64_t it, const double *u_in, const doub
     return PSW_OK;
 }
 
-psw_status solve_stationary(psw_problem *P, double rtol, int64_t maxit, const double *f, double *u, psw_info *info,
+// One restricted-overlap sweep (widened boxes of P->overlap points) at schedule step `it`.
+psw_status sweep_restricted(psw_problem *P, int64_t it, const double *u_in, const double *f, double *u_out,
                             hipStream_t st) {
+    int sig[3];
+    sched_sig(P, it, sig);
+    const PassGeom g = geom(P, sig);
+    int lenmax[3] = {1, 1, 1};
+    for (int a = 0; a < P->dim; ++a) {
+        std::vector<int> lo, len;
+        partition(P->n[a], P->p[a], lo, len);
+        lenmax[a] = *std::max_element(len.begin(), len.end());
+    }
+    const size_t lds = ras_lds_bytes(g, lenmax, P->overlap, P->lds_limit);
+    if (!lds) return PSW_ENOTSUP;
+    const double *d[7];
+    diag64(P, d);
+    HIPCHK(launch_ras(g, d, P->omega, P->overlap, lds, u_in, f, u_out, st));
+    return PSW_OK;
+}
+
+psw_status solve_stationary(psw_problem *P, double rtol, int64_t maxit, const double *f, double *u, psw_info *info,
+                            hipStream_t st, bool restricted = false) {
     psw_status ps = ensure_work(P);
     if (ps) return ps;
     if ((ps = check_lds(P, 8))) return ps;
@@ -864,7 +884,7 @@ psw_status solve_stationary(psw_problem *P, double rtol, int64_t maxit, const do
     int64_t it = 0;
     bool conv = false;
     for (it = 0; it < maxit;) {
-        if ((ps = sweep_once(P, it, u, f, tmp, st))) return ps;
+        if ((ps = restricted ? sweep_restricted(P, it, u, f, tmp, st) : sweep_once(P, it, u, f, tmp, st))) return ps;
         HIPCHK(hipMemcpyAsync(u, tmp, sizeof(double) * P->N, hipMemcpyDeviceToDevice, st));
         ++it;
         HIPCHK(launch_residual(P->dim, P->n, d, f, u, res, st));
@@ -2194,7 +2214,7 @@ psw_status psw_set_relaxation(psw_problem *P, const double *omega, int count) {
 }
 
 psw_status psw_set_decomposition(psw_problem *P, const int p[3], int overlap, int phase) {
-    if (!P || !p || overlap < 2 || (phase != 0 && phase != 1)) return PSW_EINVAL;
+    if (!P || !p || overlap < 0 || (phase != 0 && phase != 1)) return PSW_EINVAL;
     int pp[3] = {1, 1, 1};
     for (int a = 0; a < P->dim; ++a) {
         pp[a] = p[a];
@@ -2286,6 +2306,14 @@ psw_status psw_sweep(psw_problem *P, int64_t iteration, const double *u_in, cons
     return sweep_once(P, iteration, u_in, f, u_out, (hipStream_t)stream);
 }
 
+psw_status psw_sweep_restricted(psw_problem *P, int64_t iteration, const double *u_in, const double *f,
+                                double *u_out, void *stream) {
+    if (!P || !u_in || !f || !u_out || iteration < 0 || u_in == u_out) return PSW_EINVAL;
+    if (!P->has_diag || !P->has_decomp) return PSW_ESTATE;
+    DeviceGuard dg(P->device);
+    return sweep_restricted(P, iteration, u_in, f, u_out, (hipStream_t)stream);
+}
+
 psw_status psw_precond_setup(psw_problem *P, psw_precond kind, void *stream) {
     if (!P) return PSW_EINVAL;
     DeviceGuard dg(P->device);
@@ -2369,6 +2397,7 @@ psw_status psw_solve(psw_problem *P, psw_method method, psw_precond precond, dou
     psw_status ps;
     switch (method) {
     case PSW_SOR_STATIONARY: ps = solve_stationary(P, rtol, maxit, f, u, &loc, st); break;
+    case PSW_SOR_RESTRICTED: ps = solve_stationary(P, rtol, maxit, f, u, &loc, st, true); break;
     case PSW_CG:
         // a single problem runs on the host-driven loop (psw_batch_solve with count = 1 takes the
         // graph-replayed batch path)

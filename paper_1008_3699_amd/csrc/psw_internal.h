@@ -53,6 +53,12 @@ struct PassGeom {
 hipError_t launch_sweep_stationary(const PassGeom &g, const double *const *diag, const double *omega8,
                                    const double *uold, const double *f, double *out, hipStream_t st);
 
+// Restricted-overlap sweep (one workgroup per subdomain, widened box and a ring in LDS).
+// ras_lds_bytes: LDS bytes for the largest subdomain, 0 if it does not fit lds_limit.
+size_t ras_lds_bytes(const PassGeom &g, const int lenmax[3], int overlap, size_t lds_limit);
+hipError_t launch_ras(const PassGeom &g, const double *const *diag, const double *omega8, int overlap, size_t lds,
+                      const double *uold, const double *f, double *out, hipStream_t st);
+
 // Stationary sweep as a start-coupled pass (2D): right-hand side f + (1/w - 1) a^P u_old + N2 u_old
 // and pivots a^P / w, with w per point from its subdomain's start corner under the direction map sig
 // (omega8: the 4 factors by start corner, host array, passed by value).

@@ -25,6 +25,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 namespace psw {
 
 // ------------------------------------------------------------------ loads
@@ -1228,6 +1230,122 @@ hipError_t launch_sweep_stationary(const PassGeom &g, const double *const *diag,
         hipLaunchKernelGGL((k_sweep_start<2, double, double, double, double, true>), grid, blk, sm, st, A);
     else
         hipLaunchKernelGGL((k_sweep_start<3, double, double, double, double, true>), grid, blk, sm, st, A);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- restricted-overlap sweep
+// The reading of the parallel experiments under which the paper's PGS/PSOR rows (Sec. 8) are
+// reproduced: every subdomain sweeps its own box widened by `overlap` points on every side (clipped
+// to the grid), in its own direction and with the factor of its start corner, on a private copy of
+// u_old, with u_old outside the widened box; only its own points are written.  One workgroup per
+// subdomain holds the widened box and a ring of one point around it in LDS and sweeps it by
+// hyperplanes (a point's upstream neighbours lie on the previous hyperplane), in place.
+struct RasArgs {
+    PassGeom g;
+    const double *diag[7];
+    double omega[8];
+    int overlap;
+    const double *uold, *f;
+    double *out;
+};
+
+template <int DIM>
+__global__ void __launch_bounds__(256) k_ras(RasArgs A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *box = reinterpret_cast<double *>(smem);
+    const TileDesc td = A.g.tiles[blockIdx.x];
+    int d[3], elo[3], ext[3], rext[3];
+    int corner = 0;
+    for (int a = 0; a < 3; ++a) {
+        d[a] = A.g.sig[a] * (td.par[a] ? -1 : 1);
+        if (a < DIM && d[a] < 0) corner |= 1 << a;
+        const int lo = a < DIM ? max(0, td.lo[a] - A.overlap) : 0;
+        const int hi = a < DIM ? min(A.g.n[a] - 1, td.lo[a] + td.len[a] - 1 + A.overlap) : 0;
+        elo[a] = lo;
+        ext[a] = hi - lo + 1;
+        rext[a] = a < DIM ? ext[a] + 2 : 1; // with the ring
+    }
+    const double w = A.omega[corner];
+    const int n0 = A.g.n[0], n1 = A.g.n[1];
+    const int64_t nr = (int64_t)rext[0] * rext[1] * rext[2];
+    // ring coordinate r = box coordinate + 1 on the used axes
+    auto ridx = [&](int r0, int r1, int r2) -> int { return r0 + rext[0] * (r1 + rext[1] * r2); };
+    // stage u_old on the box and its ring (zero where the ring leaves the grid)
+    for (int64_t e = threadIdx.x; e < nr; e += blockDim.x) {
+        const int r0 = (int)(e % rext[0]), r1 = (int)((e / rext[0]) % rext[1]), r2 = (int)(e / ((int64_t)rext[0] * rext[1]));
+        const int g0 = elo[0] + r0 - 1, g1 = DIM >= 2 ? elo[1] + r1 - 1 : 0, g2 = DIM >= 3 ? elo[2] + r2 - 1 : 0;
+        const bool in = g0 >= 0 && g0 < n0 && (DIM < 2 || (g1 >= 0 && g1 < n1)) && (DIM < 3 || (g2 >= 0 && g2 < A.g.n[2]));
+        box[e] = in ? A.uold[(int64_t)g0 + (int64_t)n0 * (g1 + (int64_t)n1 * g2)] : 0.0;
+    }
+    __syncthreads();
+    // hyperplanes t = l0 + l1 + l2 of local coordinates in the sweep orientation
+    const int nlev = ext[0] + (DIM >= 2 ? ext[1] - 1 : 0) + (DIM >= 3 ? ext[2] - 1 : 0);
+    const int npen = (DIM >= 2 ? ext[1] : 1) * (DIM >= 3 ? ext[2] : 1);
+    for (int t = 0; t < nlev; ++t) {
+        for (int c = threadIdx.x; c < npen; c += blockDim.x) {
+            const int l1 = DIM >= 2 ? c % ext[1] : 0, l2 = DIM >= 3 ? c / ext[1] : 0;
+            const int l0 = t - l1 - l2;
+            if (l0 < 0 || l0 >= ext[0]) continue;
+            const int l[3] = {l0, l1, l2};
+            int b[3], gc[3];
+            for (int a = 0; a < 3; ++a) {
+                b[a] = a < DIM ? (d[a] > 0 ? l[a] : ext[a] - 1 - l[a]) : 0; // box coordinate
+                gc[a] = elo[a] + b[a];
+            }
+            const int64_t P = (int64_t)gc[0] + (int64_t)n0 * (gc[1] + (int64_t)n1 * gc[2]);
+            const int rp = ridx(b[0] + 1, DIM >= 2 ? b[1] + 1 : 0, DIM >= 3 ? b[2] + 1 : 0);
+            double acc = A.f[P];
+            // neighbours in the order W, E, S, N, B, F; a neighbour outside the grid reads the zero ring
+            acc += A.diag[1][P] * box[rp - 1];
+            acc += A.diag[2][P] * box[rp + 1];
+            if (DIM >= 2) {
+                acc += A.diag[3][P] * box[rp - rext[0]];
+                acc += A.diag[4][P] * box[rp + rext[0]];
+            }
+            if (DIM >= 3) {
+                acc += A.diag[5][P] * box[rp - rext[0] * rext[1]];
+                acc += A.diag[6][P] * box[rp + rext[0] * rext[1]];
+            }
+            box[rp] = (1.0 - w) * box[rp] + (w / A.diag[0][P]) * acc;
+        }
+        __syncthreads();
+    }
+    // own points back
+    const int64_t own = (int64_t)td.len[0] * (DIM >= 2 ? td.len[1] : 1) * (DIM >= 3 ? td.len[2] : 1);
+    for (int64_t e = threadIdx.x; e < own; e += blockDim.x) {
+        const int o0 = (int)(e % td.len[0]);
+        const int o1 = DIM >= 2 ? (int)((e / td.len[0]) % td.len[1]) : 0;
+        const int o2 = DIM >= 3 ? (int)(e / ((int64_t)td.len[0] * td.len[1])) : 0;
+        const int g0 = td.lo[0] + o0, g1 = DIM >= 2 ? td.lo[1] + o1 : 0, g2 = DIM >= 3 ? td.lo[2] + o2 : 0;
+        const int rp = ridx(g0 - elo[0] + 1, DIM >= 2 ? g1 - elo[1] + 1 : 0, DIM >= 3 ? g2 - elo[2] + 1 : 0);
+        A.out[(int64_t)g0 + (int64_t)n0 * (g1 + (int64_t)n1 * g2)] = box[rp];
+    }
+}
+
+// LDS bytes of the widened box with its ring for the largest subdomain (0: too large for one workgroup)
+size_t ras_lds_bytes(const PassGeom &g, const int lenmax[3], int overlap, size_t lds_limit) {
+    size_t e = 1;
+    for (int a = 0; a < g.dim; ++a) e *= (size_t)std::min(g.n[a], lenmax[a] + 2 * overlap) + 2;
+    e *= sizeof(double);
+    return e <= lds_limit ? e : 0;
+}
+
+hipError_t launch_ras(const PassGeom &g, const double *const *diag, const double *omega8, int overlap, size_t lds,
+                      const double *uold, const double *f, double *out, hipStream_t st) {
+    RasArgs A{};
+    A.g = g;
+    for (int k = 0; k < 2 * g.dim + 1; ++k) A.diag[k] = diag[k];
+    for (int k = 0; k < 8; ++k) A.omega[k] = omega8[k];
+    A.overlap = overlap;
+    A.uold = uold;
+    A.f = f;
+    A.out = out;
+    if (g.dim == 1)
+        hipLaunchKernelGGL(k_ras<1>, dim3(g.ntiles), dim3(64), lds, st, A);
+    else if (g.dim == 2)
+        hipLaunchKernelGGL(k_ras<2>, dim3(g.ntiles), dim3(256), lds, st, A);
+    else
+        hipLaunchKernelGGL(k_ras<3>, dim3(g.ntiles), dim3(256), lds, st, A);
     return hipGetLastError();
 }
 
