@@ -10,7 +10,7 @@
  * irreducibly diagonally dominant structured n-diagonal matrix on a
  * structured grid.
  *
- * Layout.  dim in {2,3}; n[a] interior points on axis a; point index
+ * Layout.  dim in {1,2,3}; n[a] interior points on axis a; point index
  * P = x + n0*(y + n1*z) (x fastest).  Boundary points are not stored:
  * Dirichlet data are folded into f (eq. 1d:mat, eq. d2d).  Diagonals come in
  * the order P, W, E, S, N, B, F (2*dim+1 arrays of N doubles; W/E = -x/+x,
@@ -70,7 +70,9 @@ typedef struct {
 } psw_info;
 
 /* Create a problem on a dim-dimensional grid with n[0..dim-1] interior
- * points; stencil must be 2*dim+1 (5 or 7).  Memory for the handle is owned
+ * points; stencil must be 2*dim+1 (3, 5 or 7).  A 1D (tridiagonal) problem
+ * (Sec. 2) runs on the 2D kernels as an n x 1 grid; its schedule is the 1D
+ * one (+ then -), its coupled blocks the 2x2 of eq. 1d:sorc.  Memory for the handle is owned
  * by the library; free it with psw_problem_destroy.  The current HIP device
  * at creation is used for every later call on the handle. */
 psw_status psw_problem_create(int dim, const int64_t n[3], int stencil, psw_problem **out);

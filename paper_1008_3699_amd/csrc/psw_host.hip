@@ -34,6 +34,7 @@ namespace {
 
 // Base direction cycle of tile (0,0,0) (Sec. 3, Sweeping directions; Sec. 4 for 3D):
 // consecutive pairs are mutually reversed and each pair uses a new diagonal.
+const int kCycle1[2][3] = {{+1, 1, 1}, {-1, 1, 1}};
 const int kCycle2[4][3] = {{-1, -1, 1}, {+1, +1, 1}, {+1, -1, 1}, {-1, +1, 1}};
 const int kCycle3[8][3] = {{-1, -1, -1}, {+1, +1, +1}, {+1, -1, -1}, {-1, +1, +1},
                            {-1, +1, -1}, {+1, -1, +1}, {+1, +1, -1}, {-1, -1, +1}};
@@ -141,8 +142,9 @@ struct PrecState {
     bool e3ok[2] = {false, false};
 };
 
-// The stationary 2D sweep on the pipelined passes: the four direction maps of the schedule cycle
-// (index c of the base cycle) packed as start-coupled passes with pivots a^P / w.
+// The stationary sweep on the pipelined 2D passes (2D problems, and 1D ones as n x 1 grids): the
+// direction maps of the schedule cycle (index c of the base cycle) packed as start-coupled passes
+// with pivots a^P / w.
 struct StatState {
     bool ready = false;
     bool fast = false;
@@ -153,7 +155,8 @@ struct StatState {
 
 struct psw_problem {
     int device = 0;
-    int dim = 2;
+    int dim = 2; // the problem's dimension (ABI)
+    int kd = 2;  // dimension the kernels see: a 1D problem runs as an n x 1 grid (zero S/N couplings)
     int n[3] = {1, 1, 1};
     int64_t N = 0;
     bool has_diag = false;
@@ -217,10 +220,10 @@ void partition(int n, int p, std::vector<int> &lo, std::vector<int> &len) {
 
 PassGeom geom(const psw_problem *P, const int sig[3]) {
     PassGeom g{};
-    g.dim = P->dim;
+    g.dim = P->kd;
     for (int a = 0; a < 3; ++a) {
         g.n[a] = P->n[a];
-        g.sig[a] = a < P->dim ? sig[a] : 1;
+        g.sig[a] = a < P->kd ? sig[a] : 1;
     }
     g.ntiles = P->ntiles;
     g.tiles = P->tiles.as<TileDesc>();
@@ -230,13 +233,19 @@ PassGeom geom(const psw_problem *P, const int sig[3]) {
     return g;
 }
 
-void sched_sig(const psw_problem *P, int64_t it, int sig[3]) {
-    int period = 1 << P->dim;
-    int k = (int)(it % period);
-    if (P->phase) k ^= 1;
-    const int *s = P->dim == 2 ? kCycle2[k] : kCycle3[k];
+// entry c of the base direction cycle of the problem's dimension
+void cycle_sig(const psw_problem *P, int c, int sig[3]) {
+    const int *s = P->dim == 1 ? kCycle1[c] : P->dim == 2 ? kCycle2[c] : kCycle3[c];
     for (int a = 0; a < 3; ++a) sig[a] = a < P->dim ? s[a] : 1;
 }
+
+// cycle entry of schedule step it (phase swaps the members of every pair)
+int sched_step(const psw_problem *P, int64_t it) {
+    int k = (int)(it % (1 << P->dim));
+    return P->phase ? k ^ 1 : k;
+}
+
+void sched_sig(const psw_problem *P, int64_t it, int sig[3]) { cycle_sig(P, sched_step(P, it), sig); }
 
 Store store_of(psw_prec p) { return p == PSW_F64 ? Store::F64 : (p == PSW_F32 ? Store::F32 : Store::BF16); }
 
@@ -283,7 +292,7 @@ bool fast_shape(int dim, const int n[3], const int p[3], psw_prec prec, size_t l
 
 bool fast_eligible(const psw_problem *P, int &R, int &lxmax, int &lymax) {
     if (P->force_generic) return false;
-    return fast_shape(P->dim, P->n, P->p, P->prec, P->lds_limit, R, lxmax, lymax);
+    return fast_shape(P->kd, P->n, P->p, P->prec, P->lds_limit, R, lxmax, lymax);
 }
 
 // Sizes of the pipelined 2D packing: elements of one pass's packed coefficients (t) and face
@@ -378,7 +387,7 @@ psw_status stat_setup(psw_problem *P, hipStream_t st) {
     S.fast = false;
     S.ready = true;
     int R, lxmax, lymax;
-    if (P->dim != 2 || P->force_generic || !fast_shape(2, P->n, P->p, PSW_F64, P->lds_limit, R, lxmax, lymax))
+    if (P->kd != 2 || P->force_generic || !fast_shape(2, P->n, P->p, PSW_F64, P->lds_limit, R, lxmax, lymax))
         return PSW_OK;
     std::vector<int> lo0, len0, lo1, len1;
     partition(P->n[0], P->p[0], lo0, len0);
@@ -413,11 +422,12 @@ psw_status stat_setup(psw_problem *P, hipStream_t st) {
     double *piv = P->w_y.as<double>(); // pivots of one direction map at a time, consumed by the packing
     const double *d[7];
     diag64(P, d);
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < (1 << P->dim); ++c) {
         FastPassBuf &B = S.fp[c];
         if (!B.inv.ensure(eb * t) || !B.ax.ensure(eb * t) || !B.ay.ensure(eb * t) || !B.face.ensure(eb * (f + 8)))
             return PSW_ENOMEM;
-        const int *sig = kCycle2[c];
+        int sig[3];
+        cycle_sig(P, c, sig);
         HIPCHK(launch_sor_piv2d(P->n, P->p, sig, d[0], P->omega, piv, st));
         const PassGeom g = geom(P, sig);
         HIPCHK(launch_pack2d(g, Store::F64, R, false, d, piv, S.toff.as<int64_t>(), S.foff.as<int64_t>(), B.inv.p,
@@ -502,7 +512,7 @@ psw_status precond_setup(psw_problem *P, psw_precond kind, hipStream_t st) {
     if (ps) return ps;
     if ((ps = ensure_work(P))) return ps;
     size_t eb = store_bytes(s) * (size_t)P->N;
-    for (int k = 1; k < 2 * P->dim + 1; ++k) {
+    for (int k = 1; k < 2 * P->kd + 1; ++k) {
         if (!S.diag[k].ensure(eb)) return PSW_ENOMEM;
         HIPCHK(launch_convert(P->diag[k].as<double>(), S.diag[k].p, s, P->N, 1.0, st));
     }
@@ -814,7 +824,7 @@ psw_status sweep_once(psw_problem *P, int64_t it, const double *u_in, const doub
     sched_sig(P, it, sig);
     const double *d[7];
     diag64(P, d);
-    if (P->dim == 2 && !P->force_generic) {
+    if (P->kd == 2 && !P->force_generic) {
         if (!P->stat.ready) {
             psw_status ps = stat_setup(P, st);
             if (ps) return ps;
@@ -822,8 +832,7 @@ psw_status sweep_once(psw_problem *P, int64_t it, const double *u_in, const doub
         if (P->stat.fast) {
             psw_status ps = ensure_work(P);
             if (ps) return ps;
-            int c = (int)(it % 4);
-            if (P->phase) c ^= 1;
+            const int c = sched_step(P, it);
             StatState &S = P->stat;
             double *rhs = P->w_z.as<double>();
             HIPCHK(launch_sor_rhs2d(P->n, P->p, sig, d, P->omega, f, u_in, rhs, st));
@@ -887,7 +896,7 @@ psw_status solve_stationary(psw_problem *P, double rtol, int64_t maxit, const do
         if ((ps = restricted ? sweep_restricted(P, it, u, f, tmp, st) : sweep_once(P, it, u, f, tmp, st))) return ps;
         HIPCHK(hipMemcpyAsync(u, tmp, sizeof(double) * P->N, hipMemcpyDeviceToDevice, st));
         ++it;
-        HIPCHK(launch_residual(P->dim, P->n, d, f, u, res, st));
+        HIPCHK(launch_residual(P->kd, P->n, d, f, u, res, st));
         double nr;
         if ((ps = host_norm(P, res, &nr, st))) return ps;
         rel = nr / nf;
@@ -997,7 +1006,7 @@ psw_status solve_cg(psw_problem *P, psw_precond kind, double rtol, int64_t maxit
     double nf;
     if ((ps = host_norm(P, f, &nf, st))) return ps;
     if (nf == 0.0) nf = 1.0;
-    HIPCHK(launch_residual(P->dim, P->n, d, f, x, r, st));
+    HIPCHK(launch_residual(P->kd, P->n, d, f, x, r, st));
     double nr;
     if ((ps = host_norm(P, r, &nr, st))) return ps;
     double rel = nr / nf;
@@ -1010,7 +1019,7 @@ psw_status solve_cg(psw_problem *P, psw_precond kind, double rtol, int64_t maxit
         double *z2 = P->w_z1.as<double>();
         const double hc = kind != PSW_NONE ? 0.5 * P->pc[kind].c : 0.0;
         double *part_pq = part + kRedBlocks, *part_rz = part + 2 * kRedBlocks;
-        if (P->dim == 2) {
+        if (P->kd == 2) {
             ps = cg2d_fused(P, kind, split, rtol, maxit, nf, x, it, conv, st);
             if (ps) return ps;
             goto done;
@@ -1043,7 +1052,7 @@ psw_status solve_cg(psw_problem *P, psw_precond kind, double rtol, int64_t maxit
         if (!P->hs.ensure()) return PSW_ENOMEM;
         double *h = P->hs.p;
         while (it < maxit) {
-            HIPCHK(launch_spmv(P->dim, P->n, d, p, q, st));
+            HIPCHK(launch_spmv(P->kd, P->n, d, p, q, st));
             HIPCHK(launch_dot_partial(p, q, N, part_pq, st));
             HIPCHK(launch_cg_update_xr(x, r, p, q, s_rz, part_pq, s_pq, N, part, s_rr, st));
             ++it;
@@ -1080,7 +1089,7 @@ psw_status solve_cg(psw_problem *P, psw_precond kind, double rtol, int64_t maxit
     }
 done:
     // true residual at exit
-    HIPCHK(launch_residual(P->dim, P->n, d, f, x, r, st));
+    HIPCHK(launch_residual(P->kd, P->n, d, f, x, r, st));
     if ((ps = host_norm(P, r, &nr, st))) return ps;
     if (info) {
         info->iters = it;
@@ -1114,7 +1123,7 @@ psw_status solve_fgmres(psw_problem *P, psw_precond kind, double rtol, int64_t m
     double rel = 1.0;
     std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hv(m + 1);
     while (it < maxit) {
-        HIPCHK(launch_residual(P->dim, P->n, d, f, x, r, st));
+        HIPCHK(launch_residual(P->kd, P->n, d, f, x, r, st));
         double beta;
         if ((ps = host_norm(P, r, &beta, st))) return ps;
         rel = beta / nf;
@@ -1131,7 +1140,7 @@ psw_status solve_fgmres(psw_problem *P, psw_precond kind, double rtol, int64_t m
         for (int k = 0; k < m && it < maxit; ++k) {
             double *Vk = V + (size_t)k * N, *Zk = Z + (size_t)k * N;
             if ((ps = precond_apply(P, kind, 0, Vk, Zk, st))) return ps;
-            HIPCHK(launch_spmv(P->dim, P->n, d, Zk, w, st));
+            HIPCHK(launch_spmv(P->kd, P->n, d, Zk, w, st));
             // classical Gram-Schmidt, two passes
             for (int pass = 0; pass < 2; ++pass) {
                 HIPCHK(launch_multi_dot(V, w, k + 1, N, part, hd, st));
@@ -1178,7 +1187,7 @@ psw_status solve_fgmres(psw_problem *P, psw_precond kind, double rtol, int64_t m
             break;
         }
     }
-    HIPCHK(launch_residual(P->dim, P->n, d, f, x, r, st));
+    HIPCHK(launch_residual(P->kd, P->n, d, f, x, r, st));
     double nr;
     if ((ps = host_norm(P, r, &nr, st))) return ps;
     if (info) {
@@ -1211,7 +1220,7 @@ struct BatchRun {
 };
 
 bool batch_eligible(psw_problem *P, psw_precond kind) {
-    if (P->dim != 2 || !P->has_diag || !P->has_decomp) return false;
+    if (P->kd != 2 || !P->has_diag || !P->has_decomp) return false;
     if (kind != PSW_SSOR && kind != PSW_ILU0) return false;
     int R, lx, ly;
     return fast_eligible(P, R, lx, ly);
@@ -2119,7 +2128,7 @@ const char *psw_status_string(psw_status st) {
 psw_status psw_problem_create(int dim, const int64_t n[3], int stencil, psw_problem **out) {
     if (!out || !n) return PSW_EINVAL;
     *out = nullptr;
-    if (dim < 2 || dim > 3) return dim == 1 ? PSW_ENOTSUP : PSW_EINVAL;
+    if (dim < 1 || dim > 3) return PSW_EINVAL;
     if (stencil != 2 * dim + 1) return PSW_EINVAL;
     int64_t N = 1;
     for (int a = 0; a < dim; ++a) {
@@ -2137,6 +2146,7 @@ psw_status psw_problem_create(int dim, const int64_t n[3], int stencil, psw_prob
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, P->device) == hipSuccess && lds > 0)
         P->lds_limit = (size_t)lds;
     P->dim = dim;
+    P->kd = dim < 2 ? 2 : dim;
     for (int a = 0; a < 3; ++a) P->n[a] = a < dim ? (int)n[a] : 1;
     P->N = N;
     *out = P;
@@ -2151,6 +2161,16 @@ psw_status psw_problem_destroy(psw_problem *P) {
     return PSW_OK;
 }
 
+// A 1D problem runs on the 2D kernels as an n x 1 grid: its S and N couplings exist and are zero.
+static psw_status zero_missing_couplings(psw_problem *P, hipStream_t st) {
+    const size_t b = sizeof(double) * (size_t)P->N;
+    for (int k = 2 * P->dim + 1; k < 2 * P->kd + 1; ++k) {
+        if (!P->diag[k].ensure(b)) return PSW_ENOMEM;
+        HIPCHK(hipMemsetAsync(P->diag[k].p, 0, b, st));
+    }
+    return PSW_OK;
+}
+
 static void invalidate(psw_problem *P) {
     P->pc[0].ready = false;
     P->pc[1].ready = false;
@@ -2159,6 +2179,7 @@ static void invalidate(psw_problem *P) {
 
 psw_status psw_set_diagonals(psw_problem *P, const double *const diag[], int on_device, psw_prec prec, void *stream) {
     if (!P || !diag || prec < PSW_F64 || prec > PSW_BF16) return PSW_EINVAL;
+    psw_status ps;
     DeviceGuard dg(P->device);
     hipStream_t st = (hipStream_t)stream;
     size_t b = sizeof(double) * (size_t)P->N;
@@ -2167,6 +2188,7 @@ psw_status psw_set_diagonals(psw_problem *P, const double *const diag[], int on_
         if (!P->diag[k].ensure(b)) return PSW_ENOMEM;
         HIPCHK(hipMemcpyAsync(P->diag[k].p, diag[k], b, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
     }
+    if ((ps = zero_missing_couplings(P, st))) return ps;
     if (!on_device) HIPCHK(hipStreamSynchronize(st));
     P->prec = prec;
     P->has_diag = true;
@@ -2188,6 +2210,8 @@ psw_status psw_assemble_diffusion(psw_problem *P, const double *const alpha[], d
     for (int a = 0; a < P->dim; ++a)
         if (!alpha[a]) return PSW_EINVAL;
     HIPCHK(launch_assemble(P->dim, P->n, alpha, beta, out, st));
+    psw_status ps = zero_missing_couplings(P, st);
+    if (ps) return ps;
     P->prec = prec;
     P->has_diag = true;
     invalidate(P);
@@ -2368,7 +2392,7 @@ psw_status psw_spmv(psw_problem *P, const double *x, double *y, void *stream) {
     if (!P->has_diag) return PSW_ESTATE;
     DeviceGuard dg(P->device);
     const double *d[7];
-    HIPCHK(launch_spmv(P->dim, P->n, diag64(P, d), x, y, (hipStream_t)stream));
+    HIPCHK(launch_spmv(P->kd, P->n, diag64(P, d), x, y, (hipStream_t)stream));
     return PSW_OK;
 }
 

@@ -47,10 +47,11 @@ def test_create_rejects_bad_arguments_without_touching_gpu():
     L = ctypes.CDLL(SO)
     h = ctypes.c_void_p()
     n = (ctypes.c_int64 * 3)(8, 8, 1)
-    # stencil must be 2*dim+1; dim 4 invalid; 1D unsupported on the GPU path
+    # stencil must be 2*dim+1; dim 4 and dim 0 invalid
     assert L.psw_problem_create(2, n, 7, ctypes.byref(h)) == -1
     assert L.psw_problem_create(4, n, 9, ctypes.byref(h)) == -1
-    assert L.psw_problem_create(1, n, 3, ctypes.byref(h)) == -8
+    assert L.psw_problem_create(1, n, 5, ctypes.byref(h)) == -1
+    assert L.psw_problem_create(0, n, 1, ctypes.byref(h)) == -1
 
 
 def test_server_rejects_bad_arguments_without_touching_gpu():
