@@ -23,6 +23,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -30,16 +32,24 @@ HBM_PEAK_GBS = 8000.0
 SEQ_ITERS_FILE = os.path.join(ROOT, "tests", "golden", "sequential_iterations.json")
 
 
-def sequential_iterations(key, iters):
+def sequential_iterations(key, iters, decomposed_key=None):
     """CG iterations of the sequential preconditioner (one subdomain) on the same input, from the CPU
-    oracle's stored run, and the decomposed solve's count relative to it."""
+    oracle's stored run, and the decomposed solve's count relative to it; with decomposed_key also the
+    oracle's count for the same decomposition (FP64, same input)."""
     try:
-        rec = json.load(open(SEQ_ITERS_FILE))[key]
+        recs = json.load(open(SEQ_ITERS_FILE))
+        rec = recs[key]
     except (OSError, ValueError, KeyError):
         return {"iterations_sequential": None}
     seq = rec["iterations"]
-    return {"iterations_sequential": seq, "iterations_vs_sequential": round(max(iters) / seq, 4),
-            "sequential_source": "CPU FP64 oracle, one subdomain, same input (tests/golden/sequential_iterations.json)"}
+    out = {"iterations_sequential": seq, "iterations_vs_sequential": round(max(iters) / seq, 4),
+           "sequential_source": "CPU FP64 oracle, one subdomain, same input (tests/golden/sequential_iterations.json)"}
+    if decomposed_key and decomposed_key in recs:
+        od = recs[decomposed_key]["iterations"]
+        out.update({"iterations_oracle": od, "iterations_vs_oracle": max(iters) - od,
+                    "oracle_source": "CPU FP64 oracle, the same decomposition and symmetric preconditioner, "
+                                     "same input (tests/golden/sequential_iterations.json)"})
+    return out
 
 
 def parse():
@@ -68,6 +78,8 @@ def parse():
     ap.add_argument("--n3", type=int, default=256, help="poisson3d256: grid points per axis")
     ap.add_argument("--p3", type=int, default=8, help="poisson3d256: subdomains per axis")
     ap.add_argument("--prec3", default="f32", choices=["f32", "bf16"], help="poisson3d256: sweep precision")
+    ap.add_argument("--no-fp64-reference", dest="fp64_reference", action="store_false",
+                    help="poisson3d256: skip the plain FP64 GPU solve that the result is compared with")
     ap.add_argument("--plain-sample", type=int, default=24, help="batch512: problems solved one by one in FP64")
     ap.add_argument("--serve-count", type=int, default=40, help="serve: number of requests in the stream")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="serve: mean arrival rate (requests/s)")
@@ -167,9 +179,15 @@ def main():
     roofline = measure_roofline(g, N, args, stream, k_ms=live[0][0], k_n=live[0][1])
     passes = pass_table(N, args, live)
     roofline_cg = cg_step_roofline(N, args, *live[4])
-    cpu = None
+    cpu = cpu_par = None
     if not args.no_cpu:
         cpu = cpu_baseline(w, n, p, args.precond, args.cpu_sample_s)
+        from oracle import oracle as O
+        diags = O.assemble(2, (n, n), w["alphas"])
+        pc = O.Precond(args.precond, 2, (n, n), (p, p), diags, omega=1.0)
+        cpu_par = cpu_parallel(2, (n, n), (p, p), pc.dirs_f, diags, w["f"], args.cpu_sample_s, 40,
+                               f"forward half-sweeps of the {args.precond} preconditioner ({p}x{p} subdomains)",
+                               piv=pc.piv)
 
     rec = {
         "metric": "sweep Gpoints/s (whole job, PCG to 1e-8)",
@@ -192,11 +210,14 @@ def main():
         "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
         "iterations": iters,
         "relres": [i["relres"] for i in infos],
-        **(sequential_iterations("varcoef2048", iters) if n == 2048 and args.precond == "ilu0" else {}),
+        **(sequential_iterations(*{"ilu0": ("varcoef2048", "varcoef2048_p16"),
+                                   "ssor": ("varcoef2048_ssor", "varcoef2048_ssor_p16")}[args.precond])
+           if n == 2048 and p == 16 else {}),
         "roofline": roofline,
         "roofline_passes": passes,
         "roofline_cg_step": roofline_cg,
         "cpu_baseline": cpu,
+        "cpu_parallel": cpu_par,
     }
     print(json.dumps(rec), flush=True)
 
@@ -347,12 +368,12 @@ def bench_sor2048(args):
     """Decomposed SOR sweeps (Gauss-Seidel, w = 1) on the 2048^2 variable-coefficient operator with 16x16
     subdomains: u_out = sweep(u_in) at successive schedule steps, ping-pong buffers, on inputs resident in
     HBM.  Algorithmic bytes per point: u_in, f, five diagonals, u_out = 64."""
-    import numpy as np
     import torch
 
     import paper_1008_3699_amd as P
     import synth
 
+    cpu_par = None
     dev = torch.device("cuda:0")
     n, p = args.n, args.p
     w = synth.varcoef_2d(n=n)
@@ -398,6 +419,8 @@ def bench_sor2048(args):
         dt = time.perf_counter() - t1
         cpu = {"value": round(N * k / dt / 1e9, 5), "unit": "Gpoints/s", "cores": 1, "kind": "oracle",
                "sample": f"{k} decomposed sweeps on the full {n}x{n} grid ({p}x{p} subdomains), single-threaded C oracle"}
+        cpu_par = cpu_parallel(2, (n, n), (p, p), O.schedule(2, (p, p), 0, 0), diags, w["f"], args.cpu_sample_s, 64,
+                               f"decomposed SOR sweeps ({p}x{p} subdomains)", uold=np.zeros(N), omega=[1.0] * 4)
     rec = {
         "metric": "decomposed SOR sweep Gpoints/s",
         "value": round(N * args.sweeps * args.steps / elapsed / 1e9, 3), "unit": "Gpoints/s",
@@ -414,6 +437,7 @@ def bench_sor2048(args):
                      "timing": "HIP events on the launching stream around each step's sweeps",
                      "bytes_per_point": bpp, "algorithmic_bytes": N * bpp},
         "cpu_baseline": cpu,
+        "cpu_parallel": cpu_par,
     }
     print(json.dumps(rec), flush=True)
 
@@ -689,6 +713,7 @@ def bench_poisson3d(args):
     import paper_1008_3699_amd as P
     import synth
 
+    cpu_par = None
     dev = torch.device("cuda:0")
     n, p = args.n3, args.p3
     w = synth.poisson_3d(n=n)
@@ -758,6 +783,29 @@ def bench_poisson3d(args):
         cpu = {"value": round(N * halves / dt / 1e9, 5), "unit": "Gpoints/s", "cores": 1, "kind": "oracle",
                "sample": f"{halves} forward half-sweeps of the {args.precond} preconditioner on the full {n}^3 grid "
                          f"({p}^3 subdomains), single-threaded C oracle in FP64"}
+        cpu_par = cpu_parallel(3, (n, n, n), (p, p, p), pc.dirs_f, diags, w["f"], args.cpu_sample_s, 48,
+                               f"FP64 forward half-sweeps of the {args.precond} preconditioner ({p}^3 subdomains)",
+                               piv=pc.piv)
+    # the result against the plain FP64 GPU solver (FP64 sweeps, same decomposition and preconditioner)
+    ref64 = None
+    if args.fp64_reference:
+        h = P.Problem(3, (n, n, n))
+        h.assemble([torch.from_numpy(a).to(dev) for a in w["alphas"]], 0.0, "f64")
+        h.set_relaxation([1.0])
+        h.set_decomposition((p, p, p), overlap=2, phase=0)
+        u64 = torch.zeros_like(u)
+        torch.cuda.synchronize()
+        a0 = time.perf_counter()
+        i64 = h.solve("cg", args.precond, f, u64, rtol=args.rtol, maxit=args.maxit)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - a0
+        err = float(torch.linalg.norm(u - u64) / torch.linalg.norm(u64))
+        ref64 = {"rel_error_vs_fp64_solver": err, "fp64_iterations": i64["iters"], "fp64_relres": i64["relres"],
+                 "fp64_solve_s": round(t64, 3),
+                 "what": "||u - u64|| / ||u64||, u64 from the plain FP64 GPU solver (FP64 sweeps on the level "
+                         "kernels, same decomposition and preconditioner, same tolerance); the FP64 oracle's error "
+                         "is stated per result at 64^3 with the same 32^3 tiles in tests/test_gpu_precision.py"}
+        h.close()
     rec = {
         "metric": "sweep Gpoints/s (whole job, PCG to 1e-8)",
         "value": round(value, 3),
@@ -780,10 +828,50 @@ def bench_poisson3d(args):
         "iterations": iters,
         "relres": [i["relres"] for i in infos],
         **(sequential_iterations("poisson3d256", iters) if n == 256 and args.precond == "ilu0" else {}),
+        "error_vs_fp64": ref64,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cpu_parallel": cpu_par,
     }
     print(json.dumps(rec), flush=True)
+
+
+def host_info():
+    """CPU model, logical CPUs of the host, and its STREAM triad bandwidth (all threads)."""
+    import bench_cpu
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "omp_threads": bench_cpu.threads(),
+            "host_triad_gbs": round(bench_cpu.triad_gbs(), 1)}
+
+
+def cpu_parallel(dim, n, p, dirs, diags, f, budget_s, bytes_per_point, what, uold=None, piv=None, omega=None):
+    """The decomposed sweep on all host cores (bench_cpu: OpenMP over subdomains), timed for about
+    budget_s seconds on the full grid, with the host's triad bandwidth beside it."""
+    import bench_cpu
+    N = int(np.prod(n))
+    bench_cpu.dsweep(dim, n, p, dirs, diags, f, uold=uold, piv=piv, omega=omega)  # warm-up
+    t0 = time.perf_counter()
+    k = 0
+    while True:
+        bench_cpu.dsweep(dim, n, p, dirs, diags, f, uold=uold, piv=piv, omega=omega)
+        k += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    hi = host_info()
+    gbs = N * bytes_per_point * k / dt / 1e9
+    return {"value": round(N * k / dt / 1e9, 5), "unit": "Gpoints/s", "cores": hi["omp_threads"],
+            "kind": "decomposed sweep on all host cores (OpenMP over subdomains, held to the oracle in tests)",
+            "sample": f"{k} {what} on the full grid", "achieved_gbs": round(gbs, 2),
+            "frac_of_host_triad": round(gbs / hi["host_triad_gbs"], 3) if hi["host_triad_gbs"] > 0 else None,
+            **hi}
 
 
 def cpu_baseline(w, n, p, kind, budget_s):
