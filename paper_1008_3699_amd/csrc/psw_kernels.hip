@@ -2352,9 +2352,20 @@ __global__ void __launch_bounds__(1024) k_tile3(Tile3Args<S, TIN, TOUT> A) {
     constexpr int PD = kTile3Pd;
     // The ring's loads are unconditional and each slot is reloaded after its last use in the
     // level, so the slot keeps its registers and no wait is needed before the level's barrier.
-    Pk3<S> ring[PD];
+    // The ring is filled in level order (a scheduling barrier after each load keeps the compiler
+    // from issuing them in another order): the wait before level t's coefficients is then for the
+    // load issued PD levels earlier, with the younger loads still in flight.  Issued in reverse
+    // order, every level would wait for all outstanding loads.  A pencil reads its slot of level t
+    // only if it has a point at that level: the level-major layout keeps a slot for every (level,
+    // pencil) pair, about (len0 + L1 + L2 - 2) / len0 times the point count, and reading them all
+    // would move that many times the coefficient bytes.
+    auto has_point = [&](int t) { return have && t - l1 - l2 >= 0 && t - l1 - l2 < len0; };
+    Pk3<S> ring[PD] = {};
 #pragma unroll
-    for (int k = 0; k < PD; ++k) ring[k] = pk[(int64_t)min(k, nlev - 1) * C];
+    for (int k = 0; k < PD; ++k) {
+        if (has_point(k)) ring[k] = pk[(int64_t)k * C];
+        __builtin_amdgcn_sched_barrier(0);
+    }
     for (int t0 = 0; t0 < nlev; t0 += PD) {
 #pragma unroll
         for (int k = 0; k < PD; ++k) {
@@ -2379,7 +2390,7 @@ __global__ void __launch_bounds__(1024) k_tile3(Tile3Args<S, TIN, TOUT> A) {
                         own[o] = acc;
                     }
                 }
-                ring[k] = pk[(int64_t)min(t + PD, nlev - 1) * C];
+                if (has_point(t + PD)) ring[k] = pk[(int64_t)(t + PD) * C];
                 lds_barrier();
             }
         }
