@@ -81,7 +81,7 @@ def parse():
     ap.add_argument("--no-fp64-reference", dest="fp64_reference", action="store_false",
                     help="poisson3d256: skip the plain FP64 GPU solve that the result is compared with")
     ap.add_argument("--plain-sample", type=int, default=24, help="batch512: problems solved one by one in FP64")
-    ap.add_argument("--serve-count", type=int, default=40, help="serve: number of requests in the stream")
+    ap.add_argument("--serve-count", type=int, default=400, help="serve: number of requests in the stream")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="serve: mean arrival rate (requests/s)")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0, help="serve: admission budget (GiB of HBM)")
     ap.add_argument("--serve-precond", default="ssor", choices=["ilu0", "ssor"], help="serve: preconditioner")
@@ -210,8 +210,8 @@ def main():
         "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
         "iterations": iters,
         "relres": [i["relres"] for i in infos],
-        **(sequential_iterations(*{"ilu0": ("varcoef2048", "varcoef2048_p16"),
-                                   "ssor": ("varcoef2048_ssor", "varcoef2048_ssor_p16")}[args.precond])
+        **(sequential_iterations({"ilu0": "varcoef2048", "ssor": "varcoef2048_ssor"}[args.precond], iters,
+                                 {"ilu0": "varcoef2048_p16", "ssor": "varcoef2048_ssor_p16"}[args.precond])
            if n == 2048 and p == 16 else {}),
         "roofline": roofline,
         "roofline_passes": passes,
@@ -442,6 +442,35 @@ def bench_sor2048(args):
     print(json.dumps(rec), flush=True)
 
 
+def cg_iteration_bytes(dim, prec):
+    """Algorithmic HBM bytes per point of one CG iteration with the symmetric preconditioner: the four
+    half-sweeps (pass_bytes; 3D passes read three couplings), the operator product (2 dim + 2 FP64
+    arrays read, one written) and the vector work (r update with its norm, r.z, p update: about 13
+    FP64 values moved)."""
+    pb = pass_bytes(prec)
+    sz = {"f64": 8, "f32": 4, "bf16": 2}[prec]
+    passes = sum(pb.values()) + (2 * sz if dim == 3 else 0)  # one more coupling per pass in 3D
+    spmv = 8 * (2 * dim + 2) + 8
+    return passes + spmv + 13 * 8
+
+
+def oracle_solve_rate(items, budget_s, kind="ssor"):
+    """The CPU FP64 oracle (single-threaded) solving the given problems in order until budget_s has
+    passed: (solves, seconds, points)."""
+    from oracle import oracle as O
+    t0 = time.perf_counter()
+    done, pts = 0, 0
+    for dim, n, alphas, f, p in items:
+        diags = O.assemble(dim, n, alphas)
+        pc = O.Precond(kind, dim, n, p, diags, omega=1.0)
+        O.cg(lambda v: O.spmv(dim, n, diags, v), pc.apply_sym, f, rtol=1e-8, maxit=100000)
+        done += 1
+        pts += int(np.prod(n))
+        if time.perf_counter() - t0 > budget_s:
+            break
+    return done, time.perf_counter() - t0, pts
+
+
 def bench_batch(args):
     """512 independent anisotropic problems -(u_xx + eps u_yy), n ~ U{32..512}, SSOR(1)-PCG to 1e-8,
     FP64 CG with FP32 sweeps, all problems advanced together by the batched executor."""
@@ -514,6 +543,31 @@ def bench_batch(args):
         t_plain += time.perf_counter() - a
         err.append(float(torch.linalg.norm(us[k] - u) / torch.linalg.norm(u)))
     plain_rate = len(sample) / t_plain
+    # the whole batched iteration against HBM: algorithmic bytes of every problem's iterations / time
+    bit = cg_iteration_bytes(2, prec)
+    moved = float(np.sum(Ns * (iters + 1))) * bit * args.steps
+    gbs = moved / elapsed / 1e9
+    rl = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+          "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+          "kernel": "the whole batched CG iteration (four batched passes, end faces, SpMV, dots, updates) "
+                    "over all problems",
+          "kernel_ms": round(1e3 * elapsed / args.steps, 3), "timed_launches": args.steps,
+          "timing": "host clock around the timed batched solves", "bytes_per_point": bit,
+          "bytes_per_point_note": f"{bit} B per point and CG iteration (FP32 sweeps, FP64 vectors)",
+          "algorithmic_bytes": int(moved / args.steps)}
+    cpu = None
+    if not args.no_cpu:
+        items = []
+        for k in sample:
+            sp = specs[k]
+            n = sp["n"][0]
+            side = side_of[max(32, int(round(n / 64.0)) * 64)]
+            pp = max(1, min(n // 2, -(-n // side)))
+            items.append((2, (n, n), sp["alphas"], sp["f"], (pp, pp)))
+        done, dt, pts = oracle_solve_rate(items, args.cpu_sample_s, "ssor")
+        cpu = {"value": round(done / dt, 4), "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"{done} problems of the batch (the plain-solver sample, {pts} points) solved one by one "
+                         "by the single-threaded FP64 oracle (SSOR(1)-CG, same decompositions)"}
     rec = {
         "metric": "batched PCG solves/s to 1e-8 (512 uneven 2D problems)",
         "value": round(args.steps * len(specs) / elapsed, 3),
@@ -531,7 +585,7 @@ def bench_batch(args):
         "plain_fp64_sequential_solves_per_s": round(plain_rate, 3),
         "speedup_vs_plain": round(args.steps * len(specs) / elapsed / plain_rate, 2),
         "max_rel_diff_vs_plain_fp64": max(err),
-        "roofline": None, "cpu_baseline": None,
+        "roofline": rl, "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
 
@@ -606,6 +660,29 @@ def bench_serve(args):
         err.append(float(torch.linalg.norm(us - u) / torch.linalg.norm(u)))
         g.close()
     rate = len(reqs) / elapsed
+    moved = sum(int(np.prod(r["n"])) * (o[1]["iters"] + 1) * cg_iteration_bytes(r["dim"], prec)
+                for r, o in zip(reqs, out))
+    gbs = moved / elapsed / 1e9
+    rl = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+          "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+          "kernel": "all served CG iterations (2D batch and 3D lanes together)",
+          "kernel_ms": round(1e3 * elapsed, 1), "timed_launches": 1,
+          "timing": "host clock from the first arrival to the last result",
+          "bytes_per_point": cg_iteration_bytes(2, prec),
+          "bytes_per_point_note": "per point and CG iteration: 2D as given, 3D " + str(cg_iteration_bytes(3, prec)),
+          "algorithmic_bytes": int(moved)}
+    cpu = None
+    if not args.no_cpu:
+        items = []
+        for k in order:
+            fl = fields[k]
+            nn = fl["n"]
+            pp = tuple(max(1, min(v // 2, -(-v // (128 if fl["dim"] == 2 else 32)))) for v in nn)
+            items.append((fl["dim"], nn, fl["alphas"], fl["f"], pp))
+        done, dt, pts = oracle_solve_rate(items, args.cpu_sample_s, precond)
+        cpu = {"value": round(done / dt, 4), "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"{done} requests of the stream ({pts} points) solved one by one by the single-threaded "
+                         f"FP64 oracle ({precond.upper()}(1)-CG)"}
     rec = {
         "metric": "served PCG solves/s to 1e-8 with p50/p99 latency (Poisson arrivals)",
         "value": round(rate, 3),
@@ -631,9 +708,11 @@ def bench_serve(args):
         "plain_fp64_sequential_solves_per_s": round(n_plain / t_plain, 3) if t_plain > 0 else None,
         "plain_sample": n_plain,
         "max_rel_diff_vs_plain_fp64": max(err) if err else None,
-        "capacity_note": "offered load above the served rate: latency is then mostly queueing"
-        if rate < args.serve_rate else "served rate keeps up with the offered load",
-        "roofline": None, "cpu_baseline": None,
+        "capacity_note": ("queueing-dominated: the offered load exceeds what the GPU serves, so requests wait "
+                          "for admission and latency grows with the stream"
+                          if float(np.percentile(queue, 99)) > float(np.percentile(lat, 50))
+                          else "stable: the 99th percentile of the admission wait stays below the median latency"),
+        "roofline": rl, "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
 

@@ -66,12 +66,13 @@ def test_stored_3d_sequential_count_is_a_converged_run():
 
 
 def test_stored_2048_counts_are_converged_runs_within_ten_percent():
-    """The 2048^2 ILU(0) CG counts from the oracle: one subdomain (lexicographic ILU(0)) and 16x16
-    subdomains (the decomposed preconditioner's symmetric form); both stored runs converged, and the
-    decomposed count is within 10 % of the sequential one."""
+    """The 2048^2 ILU(0) and SSOR(1) CG counts from the oracle: one subdomain (lexicographic ILU(0) /
+    SSOR) and 16x16 subdomains (the decomposed preconditioner's symmetric form); every stored run
+    converged, and each decomposed count is within 10 % of its sequential one."""
     recs = _stored()
-    seq, dec = recs["varcoef2048"], recs["varcoef2048_p16"]
-    assert seq["subdomains"] == [1, 1] and dec["subdomains"] == [16, 16]
-    for r in (seq, dec):
-        assert r["rtol"] == 1e-8 and r["relres_true"] <= 1.05e-8 and r["precond"] == "ilu0"
-    assert dec["iterations"] <= 1.10 * seq["iterations"]
+    for kind, ks, kd in (("ilu0", "varcoef2048", "varcoef2048_p16"), ("ssor", "varcoef2048_ssor", "varcoef2048_ssor_p16")):
+        seq, dec = recs[ks], recs[kd]
+        assert seq["subdomains"] == [1, 1] and dec["subdomains"] == [16, 16]
+        for r in (seq, dec):
+            assert r["rtol"] == 1e-8 and r["relres_true"] <= 1.05e-8 and r["precond"] == kind
+        assert dec["iterations"] <= 1.10 * seq["iterations"], kind
