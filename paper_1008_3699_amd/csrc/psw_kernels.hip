@@ -36,6 +36,9 @@ template <> __device__ __forceinline__ float ldv<float, float>(const float *p, i
 template <> __device__ __forceinline__ float ldv<float, double>(const double *p, int64_t i) { return (float)p[i]; }
 template <> __device__ __forceinline__ double ldv<double, float>(const float *p, int64_t i) { return (double)p[i]; }
 template <> __device__ __forceinline__ float ldv<float, uint16_t>(const uint16_t *p, int64_t i) { return bf16_to_f32(p[i]); }
+// conversion of a loaded input value to the arithmetic type
+template <typename T> __device__ __forceinline__ T cvt_in(double v) { return (T)v; }
+template <typename T> __device__ __forceinline__ T cvt_in(float v) { return (T)v; }
 
 // diagonal index of the coupling of a point towards its neighbour on axis a,
 // side s (-1: W/S/B, +1: E/N/F)
@@ -101,6 +104,27 @@ constexpr int kWave = 64;
 __device__ __forceinline__ void wave_order() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
+}
+
+// Workgroup copy of n elements from global memory into LDS.  Each thread issues U
+// loads before its first LDS store: a loop that stores every element as soon as
+// it arrives waits a full memory latency per element.
+template <int U, typename T>
+__device__ __forceinline__ void copy_to_lds(T *__restrict__ dst, const T *__restrict__ src, int n) {
+    const int nth = blockDim.x;
+    for (int i0 = threadIdx.x; i0 < n; i0 += U * nth) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * nth;
+            v[u] = i < n ? src[i] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * nth;
+            if (i < n) dst[i] = v[u];
+        }
+    }
 }
 
 // Workgroup barrier that orders LDS only: the waves wait for their own LDS
@@ -375,11 +399,75 @@ __global__ void __launch_bounds__(1024) k_start_faces3(StartArgs<S, TIN, TOUT> A
 // sweep (the right-hand sides of its points scaled by 1/Piv, and each point's
 // three couplings scaled by 1/Piv) is loaded once, with all loads in flight
 // together; the level loop then reads LDS and the rings only.  A point on one
-// coupled face has a record of two members, a point on an edge or the corner
-// a record of eight member slots (indexed by the member's face bits).
-// Level order, ring use and block equations are those of the generic kernel.
+// coupled face has a record of two members and the inverse determinant of its
+// 2x2 block (9 values: an odd stride keeps the lanes' record reads on distinct
+// LDS banks); a point on an edge or the corner has a record of eight member
+// slots (indexed by the member's face bits).  An edge block uses four of the
+// slots; the inverse of its 4x4 matrix goes into the other four.  Both inverses
+// depend on the coefficients only and are part of the stored image.  Level
+// order, ring use and block equations are those of the generic kernel.
+constexpr int kRec1 = 9;  // values per single-face record
+constexpr int kRecM = 32; // values per edge / corner record
+// end faces: per (tile, face) image, kRec1 values per point and 2 upstream couplings across the
+// face; in LDS the records and the two solved planes
+constexpr int kEndImg = kRec1 + 2;
+
 __host__ __device__ __forceinline__ int faces3_rec_floats(int len0, int len1, int len2, int lmax) {
-    return 8 * (len1 * len2 + len0 * len2 + len0 * len1) + 32 * (3 * lmax + 1);
+    return kRec1 * (len1 * len2 + len0 * len2 + len0 * len1) + kRecM * (3 * lmax + 1);
+}
+
+// Rings of this kernel: the own and x-partner rings are indexed by pencil with a
+// row pitch of L1 + 1, so that the lanes of the y face (one pencil row apart)
+// meet distinct banks.
+__host__ __device__ __forceinline__ int faces3_ring_pencils(const PassGeom &g) { return g.cmax + g.l2max; }
+__host__ __device__ __forceinline__ size_t faces3_rings_elems(const PassGeom &g) {
+    return (size_t)(4 * faces3_ring_pencils(g) + 4 * g.l2max + 4 * g.l1max + 2);
+}
+
+// the inverse of the 4x4 edge block: m-th member shifted across qa if m & 1 and across qb
+// if m & 2; row m holds -w(member, qa) at column m ^ 1 and -w(member, qb) at column m ^ 2
+template <typename T>
+__device__ __forceinline__ void edge_inverse(T *rc, int qa, int qb) {
+    const int qc = 3 - qa - qb;
+    T M[4][4], X[4][4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const T *r4 = rc + 4 * (((m & 1) << qa) | ((m >> 1) << qb));
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            M[m][q] = (m == q) ? T(1) : T(0);
+            X[m][q] = (m == q) ? T(1) : T(0);
+        }
+        M[m][m ^ 1] = -r4[1 + qa];
+        M[m][m ^ 2] = -r4[1 + qb];
+    }
+    // Gauss-Jordan without pivoting (the blocks are diagonally dominant)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const T ip = T(1) / M[k][k];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            M[k][q] *= ip;
+            X[k][q] *= ip;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (i == k) continue;
+            const T l = M[i][k];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                M[i][q] -= l * M[k][q];
+                X[i][q] -= l * X[k][q];
+            }
+        }
+    }
+    // row m of the inverse into the slot of member m shifted across qc (unused by the block)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        T *dst = rc + 4 * ((((m & 1) << qa) | ((m >> 1) << qb)) | (1 << qc));
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dst[q] = X[m][q];
+    }
 }
 
 template <typename T, typename S, typename TIN, typename TOUT>
@@ -390,14 +478,21 @@ __global__ void __launch_bounds__(1024) k_start_faces3g(StartArgs<S, TIN, TOUT> 
     const TileFrame F = make_frame<3>(g, td);
     const int len[3] = {F.len[0], F.len[1], F.len[2]};
     const int L1 = len[1];
-    Rings<T> rg = make_rings<T>(smem, g);
-    const size_t rb = (rings_bytes(g, sizeof(T)) + 15) / 16 * 16;
+    const int PC = faces3_ring_pencils(g), RP = L1 + 1;
+    T *const rown = reinterpret_cast<T *>(smem);
+    T *const rxp = rown + 2 * PC;
+    T *const ryp = rxp + 2 * PC;
+    T *const rzp = ryp + 2 * g.l2max;
+    T *const rxyp = rzp + 2 * g.l1max;
+    T *const rxzp = rxyp + 2 * g.l2max;
+    T *const ryzp = rxzp + 2 * g.l1max;
+    const size_t nring = faces3_rings_elems(g);
+    const size_t rb = (nring * sizeof(T) + 15) / 16 * 16;
     // rings start at zero: a weight of zero (no upstream point) then meets a finite value
-    for (size_t i = threadIdx.x; i < rings_bytes(g, sizeof(T)) / sizeof(T); i += blockDim.x)
-        reinterpret_cast<T *>(smem)[i] = T(0);
-    T *rec1 = reinterpret_cast<T *>(smem + rb);                      // single-face records, 8 values each
+    for (size_t i = threadIdx.x; i < nring; i += blockDim.x) rown[i] = T(0);
+    T *rec1 = reinterpret_cast<T *>(smem + rb);                      // single-face records
     const int nf[3] = {len[1] * len[2], len[0] * len[2], len[0] * len[1]};
-    T *recm = rec1 + 8 * (nf[0] + nf[1] + nf[2]);                       // edge / corner records, 32 values each
+    T *recm = rec1 + kRec1 * (nf[0] + nf[1] + nf[2]);                 // edge / corner records
     const int nth = blockDim.x;
     const bool scale = A.scale_by_piv != 0;
 
@@ -424,12 +519,20 @@ __global__ void __launch_bounds__(1024) k_start_faces3g(StartArgs<S, TIN, TOUT> 
     auto rec_of = [&](int a, int j, int l0, int l1, int l2, int Am) -> T * {
         if ((Am & (Am - 1)) == 0) {
             const int off = a == 0 ? 0 : (a == 1 ? nf[0] : nf[0] + nf[1]);
-            return rec1 + 8 * (off + j);
+            return rec1 + kRec1 * (off + j);
         }
-        if (Am == 7) return recm + 32 * (3 * lmax);
+        if (Am == 7) return recm + kRecM * (3 * lmax);
         const int e = Am == 3 ? 0 : (Am == 5 ? 1 : 2); // x-y edge (along z), x-z (along y), y-z (along x)
         const int pos = Am == 3 ? l2 : (Am == 5 ? l1 : l0);
-        return recm + 32 * (e * lmax + pos);
+        return recm + kRecM * (e * lmax + pos);
+    };
+    // global index of member B of the block at local point (l0, l1, l2): the point shifted
+    // one step against the sweep across every start face in B
+    auto member_index = [&](int l0, int l1, int l2, int B) -> int64_t {
+        const int gq[3] = {F.base[0] + F.d[0] * l0 - (((B >> 0) & 1) ? F.d[0] : 0),
+                           F.base[1] + F.d[1] * l1 - (((B >> 1) & 1) ? F.d[1] : 0),
+                           F.base[2] + F.d[2] * l2 - (((B >> 2) & 1) ? F.d[2] : 0)};
+        return lin(g.n, gq);
     };
     // member B of the block at local point (l0, l1, l2): r = rhs / Piv, w[a] = coupling along a / Piv
     auto gather = [&](int l0, int l1, int l2, int B, T *r4, bool coef_only) {
@@ -459,16 +562,12 @@ __global__ void __launch_bounds__(1024) k_start_faces3g(StartArgs<S, TIN, TOUT> 
             r4[1 + a] = (q[a] >= 0 && q[a] < g.n[a]) ? sc * ldv<T>(A.diag[dk(a, su)], Q) : T(0);
         }
     };
-
-    // the right-hand side of member B from its pivot, left in r4[0] by the coefficient image
-    // (the same operations as in gather)
-    auto fill_rhs = [&](int l0, int l1, int l2, int B, T *r4) {
-        const int gq[3] = {F.base[0] + F.d[0] * l0 - (((B >> 0) & 1) ? F.d[0] : 0),
-                           F.base[1] + F.d[1] * l1 - (((B >> 1) & 1) ? F.d[1] : 0),
-                           F.base[2] + F.d[2] * l2 - (((B >> 2) & 1) ? F.d[2] : 0)};
+    // the right-hand side of a member from its input value and its pivot, left in r4[0] by the
+    // coefficient image (the same operations as in gather)
+    auto rhs_from = [&](T *r4, TIN v) {
         const T D = r4[0];
         const T sc = T(1) / D;
-        T acc = ldv<T>(A.in, lin(g.n, gq));
+        T acc = cvt_in<T>(v);
         if (scale) acc *= D;
         r4[0] = sc * acc;
     };
@@ -492,18 +591,73 @@ __global__ void __launch_bounds__(1024) k_start_faces3g(StartArgs<S, TIN, TOUT> 
             }
         }
     };
+    // the sweep-independent parts of the records: 1/det of the 2x2 blocks, the 4x4 inverses
+    auto finalize = [&]() {
+        members([&](int l0, int l1, int l2, int B, T *r4) {
+            int Am = (l0 == 0 && F.start_cpl[0] ? 1 : 0) | (l1 == 0 && F.start_cpl[1] ? 2 : 0) |
+                     (l2 == 0 && F.start_cpl[2] ? 4 : 0);
+            if (B != 0) return; // once per block
+            if ((Am & (Am - 1)) == 0) {
+                const int bit = Am == 1 ? 0 : (Am == 2 ? 1 : 2);
+                r4[8] = T(1) / (T(1) - r4[1 + bit] * r4[4 + 1 + bit]);
+            } else if (Am != 7) {
+                edge_inverse<T>(r4, (Am & 1) ? 0 : 1, (Am & 4) ? 2 : 1);
+            }
+        });
+    };
 
     // ---- gather
     const int nrec = faces3_rec_floats(len[0], len[1], len[2], lmax);
     T *img = A.img_mode ? reinterpret_cast<T *>(A.img) + (int64_t)blockIdx.x * A.img_stride : nullptr;
     if (A.img_mode == 2) {
-        // the coefficients as stored (one contiguous read per tile), then the right-hand sides
-        for (int i = threadIdx.x; i < nrec; i += nth) rec1[i] = img[i];
-        __syncthreads();
-        members([&](int l0, int l1, int l2, int B, T *r4) { fill_rhs(l0, l1, l2, B, r4); });
+        // the coefficients as stored (one contiguous read per tile), then the right-hand sides,
+        // every thread's loads issued before its first record update (a load index that is not
+        // needed repeats the tile's first point)
+        copy_to_lds<16>(rec1, img, nrec);
+        __syncthreads(); // a record's pivot is read by the thread of its point, not by its copier
+        const int64_t i0 = member_index(0, 0, 0, 0);
+        for (int j = threadIdx.x; j < max(nf[0], max(nf[1], nf[2])); j += nth) {
+            TIN v[3][2];
+            bool ok[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                int l0 = 0, l1 = 0, l2 = 0, Am = 0;
+                ok[a] = j < nf[a] && point(a, j, l0, l1, l2, Am) && (Am & (Am - 1)) == 0;
+                v[a][0] = A.in[ok[a] ? member_index(l0, l1, l2, 0) : i0];
+                v[a][1] = A.in[ok[a] ? member_index(l0, l1, l2, 1 << a) : i0];
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (!ok[a]) continue;
+                int l0, l1, l2, Am;
+                point(a, j, l0, l1, l2, Am);
+                T *rc = rec_of(a, j, l0, l1, l2, Am);
+                rhs_from(rc, v[a][0]);
+                rhs_from(rc + 4, v[a][1]);
+            }
+        }
+        // edges (thread k < 3 lmax: edge k / lmax at position k % lmax) and the corner (k = 3 lmax)
+        for (int k = threadIdx.x; k <= 3 * lmax; k += nth) {
+            const int e = k / lmax, pos = k - e * lmax;
+            const int l0 = e == 2 ? pos : 0, l1 = e == 1 ? pos : 0, l2 = e == 0 ? pos : 0;
+            const int Am = (l0 == 0 && F.start_cpl[0] ? 1 : 0) | (l1 == 0 && F.start_cpl[1] ? 2 : 0) |
+                           (l2 == 0 && F.start_cpl[2] ? 4 : 0);
+            const int want = e == 0 ? 3 : (e == 1 ? 5 : (e == 2 ? 6 : 7));
+            const bool ok = Am == want && l0 < len[0] && l1 < len[1] && l2 < len[2];
+            TIN v[8];
+#pragma unroll
+            for (int B = 0; B < 8; ++B) v[B] = A.in[(ok && !(B & ~Am)) ? member_index(l0, l1, l2, B) : i0];
+            if (!ok) continue;
+            T *rc = recm + kRecM * (e == 3 ? 3 * lmax : e * lmax + pos);
+#pragma unroll
+            for (int B = 0; B < 8; ++B)
+                if (!(B & ~Am)) rhs_from(rc + 4 * B, v[B]);
+        }
     } else {
         const bool coef_only = A.img_mode == 1;
         members([&](int l0, int l1, int l2, int B, T *r4) { gather(l0, l1, l2, B, r4, coef_only); });
+        __syncthreads();
+        finalize();
         if (coef_only) {
             __syncthreads();
             for (int i = threadIdx.x; i < nrec; i += nth) img[i] = rec1[i];
@@ -522,9 +676,9 @@ __global__ void __launch_bounds__(1024) k_start_faces3g(StartArgs<S, TIN, TOUT> 
     const int Lm = max(len[0], max(len[1], len[2]));
     // ring slot of member B at (q1, q2), B varying over the lanes: the address by selects
     auto rslot = [&](int B, int buf, int q1, int q2) -> T * {
-        T *base = B == 0 ? rg.own : B == 1 ? rg.xp : B == 2 ? rg.yp : B == 4 ? rg.zp : B == 3 ? rg.xyp : B == 5 ? rg.xzp : rg.yzp;
-        const int off = B <= 1 ? buf * rg.cmax + q1 + L1 * q2
-                      : (B == 2 || B == 3) ? buf * rg.l2max + q2 : (B == 4 || B == 5) ? buf * rg.l1max + q1 : buf;
+        T *base = B == 0 ? rown : B == 1 ? rxp : B == 2 ? ryp : B == 4 ? rzp : B == 3 ? rxyp : B == 5 ? rxzp : ryzp;
+        const int off = B <= 1 ? buf * PC + q1 + RP * q2
+                      : (B == 2 || B == 3) ? buf * g.l2max + q2 : (B == 4 || B == 5) ? buf * g.l1max + q1 : buf;
         return base + off;
     };
     const int scm = (F.start_cpl[0] ? 1 : 0) | (F.start_cpl[1] ? 2 : 0) | (F.start_cpl[2] ? 4 : 0);
@@ -559,32 +713,28 @@ __global__ void __launch_bounds__(1024) k_start_faces3g(StartArgs<S, TIN, TOUT> 
         if ((Am & (Am - 1)) == 0) {
             const int bit = Am == 1 ? 0 : (Am == 2 ? 1 : 2);
             const T R0 = rhs(0, rc), Rb = rhs(Am, rc + 4);
-            const T m0 = -rc[1 + bit], mb = -rc[4 + 1 + bit];
-            const T det = T(1) - m0 * mb;
-            x0 = (R0 - m0 * Rb) / det;
-            const T xb = (Rb - mb * R0) / det;
+            const T m0 = -rc[1 + bit], mb = -rc[4 + 1 + bit], idet = rc[8];
+            x0 = (R0 - m0 * Rb) * idet;
+            const T xb = (Rb - mb * R0) * idet;
             *rslot(Am, cur, l1, l2) = xb;
         } else if (Am != 7) {
-            // edge: a 4x4 block over the two coupled axes qa < qb; member m is the point
-            // shifted across qa if m & 1 and across qb if m & 2 (same elimination order
-            // as the 8x8 form, whose other rows and columns are identity)
-            const int qa = (Am & 1) ? 0 : 1, qb = (Am & 4) ? 2 : 1;
-            T M[4][4], R[4];
+            // edge: the 4x4 block over the two coupled axes qa < qb through its stored inverse
+            const int qa = (Am & 1) ? 0 : 1, qb = (Am & 4) ? 2 : 1, qc = 3 - qa - qb;
+            T R[4];
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
                 const int B = ((m & 1) << qa) | ((m >> 1) << qb);
-                const T *r4 = rc + 4 * B;
-                R[m] = rhs(B, r4);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) M[m][q] = (m == q) ? T(1) : T(0);
-                M[m][m ^ 1] = -r4[1 + qa];
-                M[m][m ^ 2] = -r4[1 + qb];
+                R[m] = rhs(B, rc + 4 * B);
             }
-            ge_solve<T, 4>(M, R);
-            x0 = R[0];
+            T X[4];
 #pragma unroll
-            for (int m = 1; m < 4; ++m)
-                *rslot(((m & 1) << qa) | ((m >> 1) << qb), cur, l1, l2) = R[m];
+            for (int m = 0; m < 4; ++m) {
+                const T *iv = rc + 4 * ((((m & 1) << qa) | ((m >> 1) << qb)) | (1 << qc));
+                X[m] = iv[0] * R[0] + iv[1] * R[1] + iv[2] * R[2] + iv[3] * R[3];
+            }
+            x0 = X[0];
+#pragma unroll
+            for (int m = 1; m < 4; ++m) *rslot(((m & 1) << qa) | ((m >> 1) << qb), cur, l1, l2) = X[m];
         } else {
             T M[8][8], R[8];
 #pragma unroll
@@ -606,9 +756,9 @@ __global__ void __launch_bounds__(1024) k_start_faces3g(StartArgs<S, TIN, TOUT> 
             x0 = R[0];
 #pragma unroll
             for (int B = 1; B < 7; ++B)
-                if (!(B & ~Am)) *rg.slot(B, cur, l1, l2, L1) = R[B];
+                if (!(B & ~Am)) *rslot(B, cur, l1, l2) = R[B];
         }
-        *rg.slot(0, cur, l1, l2, L1) = x0;
+        *rslot(0, cur, l1, l2) = x0;
         const int gp[3] = {F.base[0] + F.d[0] * l0, F.base[1] + F.d[1] * l1, F.base[2] + F.d[2] * l2};
         A.out[lin(g.n, gp)] = (TOUT)((T)A.cscale * x0);
     };
@@ -664,7 +814,7 @@ __global__ void __launch_bounds__(1024) k_start_faces3g(StartArgs<S, TIN, TOUT> 
 }
 
 size_t faces3_lds_bytes(const PassGeom &g, int fmax, size_t elem) {
-    return (rings_bytes(g, elem) + 15) / 16 * 16 + elem * (size_t)fmax;
+    return (faces3_rings_elems(g) * elem + 15) / 16 * 16 + elem * (size_t)fmax;
 }
 
 // ------------------------------------------------------------------ end-coupled (transposed) sweep
@@ -877,13 +1027,12 @@ __device__ __forceinline__ void end_face3g_body(const EndArgs<S, TIN, TOUT> &A, 
     const int nb = F.end_cpl[b] ? F.len[b] - 1 : F.len[b];
     const int nc = F.end_cpl[c] ? F.len[c] - 1 : F.len[c];
     const int np = nb * nc;
-    T *rec = reinterpret_cast<T *>(smem); // 8 values per point
-    T *vP = rec + 8 * np, *vQ = vP + np;   // solved values of the P and Q planes
+    T *rec = reinterpret_cast<T *>(smem); // kRec1 values per point (8 and the inverse determinant)
+    T *vP = rec + kRec1 * np, *vQ = vP + np; // solved values of the P and Q planes
     const int nth = blockDim.x;
     T *img = A.img_mode ? reinterpret_cast<T *>(A.img) + (int64_t)blockIdx.x * A.img_stride : nullptr;
-    T *cup = img ? img + 8 * np : nullptr; // coupling to the upstream point across AX, 2 per point
-    if (A.img_mode == 2)
-        for (int i = threadIdx.x; i < 8 * np; i += nth) rec[i] = img[i];
+    T *cup = img ? img + kRec1 * np : nullptr; // coupling to the upstream point across AX, 2 per point
+    if (A.img_mode == 2) copy_to_lds<8>(rec, img, kRec1 * np);
     // the records of point j: mode 0 gathers them into LDS, mode 1 writes their coefficient part to
     // the image, mode 2 completes the right-hand sides of the records copied from it
     T *const rdst = A.img_mode == 1 ? img : rec;
@@ -896,7 +1045,7 @@ __device__ __forceinline__ void end_face3g_body(const EndArgs<S, TIN, TOUT> &A, 
         int gp[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) gp[q] = F.base[q] + F.d[q] * l[q];
-        T *rc = rdst + 8 * j;
+        T *rc = rdst + kRec1 * j;
 #pragma unroll
         for (int m = 0; m < 2; ++m) {
             int gq[3] = {gp[0], gp[1], gp[2]}, dq[3] = {F.d[0], F.d[1], F.d[2]};
@@ -950,6 +1099,8 @@ __device__ __forceinline__ void end_face3g_body(const EndArgs<S, TIN, TOUT> &A, 
             rc[4 * m + 3] = mx;
             if (A.img_mode == 1) cup[2 * j + m] = cu;
         }
+        // the inverse determinant of the 2x2 block (coefficients only: part of the image)
+        if (A.img_mode != 2) rc[8] = T(1) / (T(1) - rc[3] * rc[7]);
     }
     if (A.img_mode == 1) return;
     __syncthreads();
@@ -961,7 +1112,7 @@ __device__ __forceinline__ void end_face3g_body(const EndArgs<S, TIN, TOUT> &A, 
             const int lc = t - lb;
             if (lc < 0 || lc >= nc) continue;
             const int j = lb + lc * nb;
-            const T *rc = rec + 8 * j;
+            const T *rc = rec + kRec1 * j;
             T R0 = rc[0], Rb = rc[4];
             if (lb > 0) {
                 R0 += rc[1] * vP[j - 1];
@@ -971,10 +1122,9 @@ __device__ __forceinline__ void end_face3g_body(const EndArgs<S, TIN, TOUT> &A, 
                 R0 += rc[2] * vP[j - nb];
                 Rb += rc[6] * vQ[j - nb];
             }
-            const T m0 = rc[3], mb = rc[7];
-            const T det = T(1) - m0 * mb;
-            const T x0 = (R0 - m0 * Rb) / det;
-            const T xb = (Rb - mb * R0) / det;
+            const T m0 = rc[3], mb = rc[7], idet = rc[8];
+            const T x0 = (R0 - m0 * Rb) * idet;
+            const T xb = (Rb - mb * R0) * idet;
             vP[j] = x0;
             vQ[j] = xb;
             int l[3];
@@ -997,7 +1147,10 @@ __global__ void __launch_bounds__(1024) k_end_faces3g(EndArgs<S, TIN, TOUT> A) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int tile = blockIdx.x / 3, a = blockIdx.x % 3;
     const TileFrame F = make_frame<3>(A.g, A.g.tiles[tile]);
-    if (!(F.d[a] > 0 && F.end_cpl[a])) return;
+    // the frame's arrays are read with constant indices only (a run-time index would put the
+    // frame in scratch memory)
+    auto owns = [&](int q) { return F.d[q] > 0 && F.end_cpl[q]; };
+    if (!(a == 0 ? owns(0) : (a == 1 ? owns(1) : owns(2)))) return;
     if (a == 0) end_face3g_body<0, T, S, TIN, TOUT>(A, F, smem);
     else if (a == 1) end_face3g_body<1, T, S, TIN, TOUT>(A, F, smem);
     else end_face3g_body<2, T, S, TIN, TOUT>(A, F, smem);
@@ -1105,7 +1258,10 @@ __global__ void __launch_bounds__(64) k_end_edges3g(EndArgs<S, TIN, TOUT> A) {
     const int tile = blockIdx.x / 3, c = blockIdx.x % 3;
     const int a = (c + 1) % 3, b = (c + 2) % 3;
     const TileFrame F = make_frame<3>(A.g, A.g.tiles[tile]);
-    if (!(F.d[a] > 0 && F.end_cpl[a] && F.d[b] > 0 && F.end_cpl[b])) return;
+    auto owns = [&](int q) { return F.d[q] > 0 && F.end_cpl[q]; };
+    const bool oa = a == 0 ? owns(0) : (a == 1 ? owns(1) : owns(2));
+    const bool ob = b == 0 ? owns(0) : (b == 1 ? owns(1) : owns(2));
+    if (!(oa && ob)) return;
     if (c == 0) end_edge3g_body<0, T, S, TIN, TOUT>(A, F, smem);
     else if (c == 1) end_edge3g_body<1, T, S, TIN, TOUT>(A, F, smem);
     else end_edge3g_body<2, T, S, TIN, TOUT>(A, F, smem);
@@ -1439,23 +1595,23 @@ static hipError_t end_part_impl(const PassGeom &g, const void *const *diag, cons
         if (g.dim != 3) return hipErrorInvalidValue;
         // largest end face: every face has at most max(len_b len_c) points
         const int fmax = std::max(g.l1max * g.l2max, len0max * std::max(g.l1max, g.l2max));
-        const bool gathered = len0max > 0 && fmax <= 1024 && 10 * (size_t)fmax * sizeof(T) <= lds_limit;
+        const bool gathered = len0max > 0 && fmax <= 1024 && kEndImg * (size_t)fmax * sizeof(T) <= lds_limit;
         if (img_mode == 1) {
             // only the coefficient image of the gathered-record kernel
             if (!gathered || !img) return hipErrorNotSupported;
             A.img_mode = 1;
             A.img = img;
-            A.img_stride = 10 * (int64_t)fmax;
+            A.img_stride = kEndImg * (int64_t)fmax;
             hipLaunchKernelGGL((k_end_faces3g<T, S, TIN, TOUT>), dim3(g.ntiles * 3),
-                               dim3(std::max(64, (fmax + 63) / 64 * 64)), 10 * (size_t)fmax * sizeof(T), st, A);
+                               dim3(std::max(64, (fmax + 63) / 64 * 64)), kEndImg * (size_t)fmax * sizeof(T), st, A);
             return hipGetLastError();
         }
         if (gathered) {
             A.img_mode = img ? 2 : 0;
             A.img = img;
-            A.img_stride = 10 * (int64_t)fmax;
+            A.img_stride = kEndImg * (int64_t)fmax;
             hipLaunchKernelGGL((k_end_faces3g<T, S, TIN, TOUT>), dim3(g.ntiles * 3),
-                               dim3(std::max(64, (fmax + 63) / 64 * 64)), 10 * (size_t)fmax * sizeof(T), st, A);
+                               dim3(std::max(64, (fmax + 63) / 64 * 64)), kEndImg * (size_t)fmax * sizeof(T), st, A);
         } else {
             hipLaunchKernelGGL((k_end_faces<3, T, S, TIN, TOUT>), dim3(g.ntiles * 3), dim3(64), 0, st, A);
         }
@@ -2334,13 +2490,42 @@ __global__ void __launch_bounds__(1024) k_tile3(Tile3Args<S, TIN, TOUT> A) {
     const int np = len0 * C;
     // the input, and for a start-coupled pass the values of the coupled start-face points,
     // which the level kernel has already solved into out (unscaled)
-    for (int e = threadIdx.x; e < np; e += nth) {
-        const int l0 = e % len0, c = e / len0, l1 = c % L1, l2 = c / L1;
-        const int gp[3] = {F.base[0] + F.d[0] * l0, F.base[1] + F.d[1] * l1, F.base[2] + F.d[2] * l2};
-        const bool face = CPL && ((l0 == 0 && F.start_cpl[0]) || (l1 == 0 && F.start_cpl[1]) ||
-                                  (l2 == 0 && F.start_cpl[2]));
-        const int64_t P = lin(g.n, gp);
-        own[c * pitch + l0] = face ? ldv<T>((const TOUT *)A.out, P) : ldv<T>(A.in, P);
+    // U loads in flight per thread before the LDS stores.  The loads are unconditional (a
+    // guarded load gets its conversion, and so a wait, inside the guard): indices past the
+    // tile repeat its last point, and the start-face points are loaded too and not stored.
+    auto on_face = [&](int l0, int l1, int l2) {
+        return CPL && ((l0 == 0 && F.start_cpl[0]) || (l1 == 0 && F.start_cpl[1]) || (l2 == 0 && F.start_cpl[2]));
+    };
+    constexpr int U = 16;
+    for (int e0 = threadIdx.x; e0 < np; e0 += U * nth) {
+        TIN v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = min(e0 + u * nth, np - 1);
+            const int l0 = e % len0, c = e / len0, l1 = c % L1, l2 = c / L1;
+            const int gp[3] = {F.base[0] + F.d[0] * l0, F.base[1] + F.d[1] * l1, F.base[2] + F.d[2] * l2};
+            v[u] = A.in[lin(g.n, gp)];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * nth;
+            const int l0 = e % len0, c = e / len0;
+            if (e < np && !on_face(l0, c % L1, c / L1)) own[c * pitch + l0] = cvt_in<T>(v[u]);
+        }
+    }
+    if (CPL) {
+        // the coupled start-face points: a point on two faces is written twice with one value
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (!F.start_cpl[a]) continue;
+            const int lb = a == 0 ? L1 : len0, nf = a == 2 ? len0 * L1 : (a == 1 ? len0 * L2 : L1 * L2);
+            for (int j = threadIdx.x; j < nf; j += nth) {
+                const int u = j % lb, w = j / lb;
+                const int l0 = a == 0 ? 0 : u, l1 = a == 1 ? 0 : (a == 0 ? u : w), l2 = a == 2 ? 0 : w;
+                const int gp[3] = {F.base[0] + F.d[0] * l0, F.base[1] + F.d[1] * l1, F.base[2] + F.d[2] * l2};
+                own[(l1 + L1 * l2) * pitch + l0] = ldv<T>((const TOUT *)A.out, lin(g.n, gp));
+            }
+        }
     }
     __syncthreads();
 
@@ -2350,27 +2535,33 @@ __global__ void __launch_bounds__(1024) k_tile3(Tile3Args<S, TIN, TOUT> A) {
     const Pk3<S> *pk = A.pk + A.poff[blockIdx.x] + (have ? c : 0); // threads beyond the tile read slot 0
     const bool scale = A.scale_by_piv != 0;
     constexpr int PD = kTile3Pd;
-    // The ring's loads are unconditional and each slot is reloaded after its last use in the
-    // level, so the slot keeps its registers and no wait is needed before the level's barrier.
-    // The ring is filled in level order (a scheduling barrier after each load keeps the compiler
-    // from issuing them in another order): the wait before level t's coefficients is then for the
-    // load issued PD levels earlier, with the younger loads still in flight.  Issued in reverse
-    // order, every level would wait for all outstanding loads.  A pencil reads its slot of level t
-    // only if it has a point at that level: the level-major layout keeps a slot for every (level,
-    // pencil) pair, about (len0 + L1 + L2 - 2) / len0 times the point count, and reading them all
-    // would move that many times the coefficient bytes.
-    auto has_point = [&](int t) { return have && t - l1 - l2 >= 0 && t - l1 - l2 < len0; };
-    Pk3<S> ring[PD] = {};
+    // The ring's loads are issued by every lane at every level, and each slot is reloaded after
+    // its last use in the level, so the slot keeps its registers and no wait is needed before the
+    // level's barrier.  The ring is filled in level order (a scheduling barrier after each load
+    // keeps the compiler from issuing them in another order): the wait before level t's
+    // coefficients is then for the load issued PD levels earlier, with the younger loads still in
+    // flight.  A load under a branch (or issued in reverse order) makes every level wait for all
+    // outstanding loads.  A pencil with no point at a level reads the tile's first slot instead
+    // of its own: the level-major layout keeps a slot for every (level, pencil) pair, about
+    // (len0 + L1 + L2 - 2) / len0 times the point count, and reading them all would move that
+    // many times the coefficient bytes, while the one shared slot stays in cache.
+    const Pk3<S> *pk0 = A.pk + A.poff[blockIdx.x];
+    auto slot = [&](int t) -> const Pk3<S> * {
+        return (have && t - l1 - l2 >= 0 && t - l1 - l2 < len0) ? pk + (int64_t)t * C : pk0;
+    };
+    Pk3<S> ring[PD];
 #pragma unroll
     for (int k = 0; k < PD; ++k) {
-        if (has_point(k)) ring[k] = pk[(int64_t)k * C];
+        ring[k] = *slot(k);
         __builtin_amdgcn_sched_barrier(0);
     }
+    // whole blocks of PD levels: the levels past the last one hold no point (no branch around
+    // the ring's loads)
     for (int t0 = 0; t0 < nlev; t0 += PD) {
 #pragma unroll
         for (int k = 0; k < PD; ++k) {
             const int t = t0 + k;
-            if (t < nlev) {
+            {
                 const Pk3<S> &cf = ring[k];
                 const int l0 = t - l1 - l2;
                 if (have && l0 >= 0 && l0 < len0) {
@@ -2390,7 +2581,7 @@ __global__ void __launch_bounds__(1024) k_tile3(Tile3Args<S, TIN, TOUT> A) {
                         own[o] = acc;
                     }
                 }
-                if (has_point(t + PD)) ring[k] = pk[(int64_t)(t + PD) * C];
+                ring[k] = *slot(t + PD);
                 lds_barrier();
             }
         }
@@ -2510,8 +2701,8 @@ hipError_t launch_end_fixups3(const PassGeom &g, Store s, const void *const *dia
 int64_t end_faces3_image_elems(const PassGeom &g, int len0max, size_t lds_limit) {
     if (g.dim != 3 || len0max <= 0) return 0;
     const int fmax = std::max(g.l1max * g.l2max, len0max * std::max(g.l1max, g.l2max));
-    if (fmax > 1024 || 10 * (size_t)fmax * sizeof(float) > lds_limit) return 0;
-    return 10 * (int64_t)fmax * g.ntiles * 3;
+    if (fmax > 1024 || kEndImg * (size_t)fmax * sizeof(float) > lds_limit) return 0;
+    return kEndImg * (int64_t)fmax * g.ntiles * 3;
 }
 
 hipError_t launch_end_faces3_image(const PassGeom &g, Store s, const void *const *diag, const void *piv, int len0max,
