@@ -766,28 +766,107 @@ __global__ void __launch_bounds__(1024) k_start_faces3g(StartArgs<S, TIN, TOUT> 
     if (Lm <= kWave && nth >= 4 * kWave) {
         // Waves 0-2 take the 2x2 blocks of faces 0-2 (lane u), wave 3 the 4x4 edge blocks (lane 0:
         // the edge (0, 0, t), 1: (0, t, 0), 2: (t, 0, 0)) and the corner at level 0: every wave runs
-        // one block type, so a level costs the longest of them, not their sum.
+        // one block type, so a level costs the longest of them, not their sum.  A wave is alone on
+        // its SIMD, so a level costs about four cycles per instruction on the longest path: the
+        // addresses of a lane's record, ring slots and output advance by fixed strides from level
+        // to level and are set up once, and each member's right-hand side reads only the ring
+        // slots of its upstream neighbours outside the block.
         const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
         if (w >= 4) return;
+        // global index of local point (l0, l1, l2): g0 + sum l_q gs[q]
+        const int64_t g0 = member_index(0, 0, 0, 0);
+        const int64_t gs0 = F.d[0], gs1 = (int64_t)F.d[1] * g.n[0], gs2 = (int64_t)F.d[2] * g.n[0] * g.n[1];
+        const T cs = (T)A.cscale;
+        if (w < 3) {
+            const int a = w;
+            const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2; // in-face axes, b < c
+            const int lenb = a == 0 ? len[1] : len[0], lenc = a == 2 ? len[1] : len[2];
+            const int u = lane;
+            // the other coupled faces through this face (their points are edge points)
+            const bool cb = (scm >> b) & 1, cc = (scm >> c) & 1;
+            const bool lane_ok = ((scm >> a) & 1) && u < lenb && !(u == 0 && cb);
+            const int off_a = a == 0 ? 0 : (a == 1 ? nf[0] : nf[0] + nf[1]);
+            // own ring: a = 0 pencil (u, v), a = 1 pencil (0, v), a = 2 pencil (v, 0)
+            const int osv = a == 2 ? 1 : RP, ou = a == 0 ? u : 0;
+            const int ob = a == 0 ? (u > 0 ? -1 : 0) : 0; // b-upstream: the pencil before (a = 0) or the same
+            T *const pr = a == 0 ? rxp : (a == 1 ? ryp : rzp);
+            const int psz = a == 0 ? PC : (a == 1 ? g.l2max : g.l1max);
+            const int psv = a == 0 ? RP : 1, pu = a == 0 ? u : 0;
+            const int64_t gsb = b == 0 ? gs0 : gs1, gsc = c == 1 ? gs1 : gs2;
+            const int64_t gu = g0 + (int64_t)u * gsb;
+            for (int t = 0; t < nlev; ++t) {
+                const int cur = t & 1, prv = cur ^ 1;
+                const int v = t - u;
+                if (lane_ok && v >= 0 && v < lenc && !(v == 0 && cc)) {
+                    const T *rc = rec1 + kRec1 * (off_a + u + v * lenb);
+                    const int oi = ou + osv * v, pi = pu + psv * v;
+                    const int vu = v > 0 ? 1 : 0;
+                    const T *oprv = rown + prv * PC, *pprv = pr + prv * psz;
+                    const T R0 = rc[0] + rc[1 + b] * oprv[oi + ob] + rc[1 + c] * oprv[oi - vu * osv];
+                    const T Rb = rc[4] + rc[5 + b] * pprv[pi + ob] + rc[5 + c] * pprv[pi - vu * psv];
+                    const T idet = rc[8];
+                    const T x0 = (R0 + rc[1 + a] * Rb) * idet;
+                    const T xb = (Rb + rc[5 + a] * R0) * idet;
+                    rown[cur * PC + oi] = x0;
+                    pr[cur * psz + pi] = xb;
+                    A.out[gu + (int64_t)v * gsc] = (TOUT)(cs * x0);
+                }
+                lds_barrier(); // out is written, never read back, inside the sweep
+            }
+            return;
+        }
+        // edges: lane e runs the edge along axis c with the coupled faces qa < qb
+        const int e = lane;
+        const int qa = e == 2 ? 1 : 0, qb = e == 0 ? 1 : 2, c = 3 - qa - qb;
+        const bool edge_ok = e < 3 && ((scm >> qa) & 1) && ((scm >> qb) & 1);
+        const int lenc = c == 0 ? len[0] : (c == 1 ? len[1] : len[2]);
+        // member m = point shifted across qa if m & 1 and across qb if m & 2: its ring, buffer size
+        // and index stride along the edge
+        const int B1 = 1 << qa, B2 = 1 << qb, B3 = B1 | B2;
+        auto ring_of = [&](int B) -> T * {
+            return B == 0 ? rown : B == 1 ? rxp : B == 2 ? ryp : B == 4 ? rzp : B == 3 ? rxyp : B == 5 ? rxzp : ryzp;
+        };
+        auto size_of = [&](int B) -> int {
+            return B <= 1 ? PC : (B == 2 || B == 3) ? g.l2max : (B == 4 || B == 5) ? g.l1max : 1;
+        };
+        // own and x-partner rings index pencils (l1 + RP l2), the others one coordinate
+        auto stride_of = [&](int B) -> int { return B <= 1 ? (c == 2 ? RP : (c == 1 ? 1 : 0)) : (c == 0 ? 0 : 1); };
+        T *const m0r = ring_of(0), *const m1r = ring_of(B1), *const m2r = ring_of(B2), *const m3r = ring_of(B3);
+        const int z0 = size_of(0), z1 = size_of(B1), z2 = size_of(B2), z3 = size_of(B3);
+        const int s0 = stride_of(0), s1 = stride_of(B1), s2 = stride_of(B2), s3 = stride_of(B3);
+        const int64_t gsE = c == 0 ? gs0 : (c == 1 ? gs1 : gs2);
+        const int qc = c;
         for (int t = 0; t < nlev; ++t) {
             const int cur = t & 1, prv = cur ^ 1;
-            int l0, l1, l2, j;
-            if (w < 3) {
-                const int lenb = w == 0 ? len[1] : len[0], lenc = w == 2 ? len[1] : len[2];
-                const int v = t - lane;
-                if (((scm >> w) & 1) && lane < lenb && v >= 0 && v < lenc) {
-                    const int Am = locate(w, lane, v, l0, l1, l2, j);
-                    if ((Am & (Am - 1)) == 0) solve_point(w, j, l0, l1, l2, Am, cur, prv);
+            if (t == 0) {
+                // the corner, or the start of the one edge through it: the general block solve
+                if (lane == 0) {
+                    int l0, l1, l2, j;
+                    const int Am = locate(0, 0, 0, l0, l1, l2, j);
+                    if (Am & (Am - 1)) solve_point(0, j, l0, l1, l2, Am, cur, prv);
                 }
-            } else if (lane < 3 && (t > 0 || lane == 0)) {
-                const int a = lane == 2 ? 1 : 0, u = lane == 0 ? 0 : t, v = lane == 0 ? t : 0;
-                const int lim = lane == 0 ? len[2] : (lane == 1 ? len[1] : len[0]);
-                if (t < lim) {
-                    const int Am = locate(a, u, v, l0, l1, l2, j);
-                    if (Am & (Am - 1)) solve_point(a, j, l0, l1, l2, Am, cur, prv);
+            } else if (edge_ok && t < lenc) {
+                const T *rc = recm + kRecM * (e * lmax + t);
+                const T *r0 = rc, *r1 = rc + 4 * B1, *r2 = rc + 4 * B2, *r3 = rc + 4 * B3;
+                const int up = t - 1;
+                T R[4];
+                R[0] = r0[0] + r0[1 + c] * m0r[prv * z0 + s0 * up];
+                R[1] = r1[0] + r1[1 + c] * m1r[prv * z1 + s1 * up];
+                R[2] = r2[0] + r2[1 + c] * m2r[prv * z2 + s2 * up];
+                R[3] = r3[0] + r3[1 + c] * m3r[prv * z3 + s3 * up];
+                T X[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const T *iv = rc + 4 * ((((m & 1) << qa) | ((m >> 1) << qb)) | (1 << qc));
+                    X[m] = iv[0] * R[0] + iv[1] * R[1] + iv[2] * R[2] + iv[3] * R[3];
                 }
+                m0r[cur * z0 + s0 * t] = X[0];
+                m1r[cur * z1 + s1 * t] = X[1];
+                m2r[cur * z2 + s2 * t] = X[2];
+                m3r[cur * z3 + s3 * t] = X[3];
+                A.out[g0 + (int64_t)t * gsE] = (TOUT)(cs * X[0]);
             }
-            lds_barrier(); // out is written, never read back, inside the sweep
+            lds_barrier();
         }
         return;
     }
