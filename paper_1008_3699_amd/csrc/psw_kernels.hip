@@ -114,11 +114,10 @@ __device__ __forceinline__ void copy_to_lds(T *__restrict__ dst, const T *__rest
     const int nth = blockDim.x;
     for (int i0 = threadIdx.x; i0 < n; i0 += U * nth) {
         T v[U];
+        // unconditional loads (an index past the end repeats the last element): a guarded load
+        // becomes a branch, and the branches wait for their loads one by one
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int i = i0 + u * nth;
-            v[u] = i < n ? src[i] : T(0);
-        }
+        for (int u = 0; u < U; ++u) v[u] = src[min(i0 + u * nth, n - 1)];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int i = i0 + u * nth;
@@ -1115,8 +1114,47 @@ __device__ __forceinline__ void end_face3g_body(const EndArgs<S, TIN, TOUT> &A, 
     // the records of point j: mode 0 gathers them into LDS, mode 1 writes their coefficient part to
     // the image, mode 2 completes the right-hand sides of the records copied from it
     T *const rdst = A.img_mode == 1 ? img : rec;
-    if (A.img_mode == 2) __syncthreads();
-    for (int j = threadIdx.x; j < np; j += nth) {
+    if (A.img_mode == 2) {
+        __syncthreads();
+        // the right-hand sides: every member's two loads in flight before the first update
+        const int64_t sa = a == 0 ? (int64_t)F.d[0] : (a == 1 ? (int64_t)F.d[1] * g.n[0] : (int64_t)F.d[2] * g.n[0] * g.n[1]);
+        for (int k = threadIdx.x; k < np; k += nth) {
+            // consecutive threads take consecutive x where x is an in-face axis (coalesced loads);
+            // record j = lb + lc nb
+            int lb, lc;
+            if (a == 1) {
+                lc = k % nc;
+                lb = k / nc;
+            } else {
+                lb = k % nb;
+                lc = k / nb;
+            }
+            const int j = lb + lc * nb;
+            int l[3];
+            l[a] = F.len[a] - 1;
+            l[b] = lb;
+            l[c] = lc;
+            int gp[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) gp[q] = F.base[q] + F.d[q] * l[q];
+            // P, its partner Q = P + d_a e_a, and the upstream points across a of each
+            const int64_t P = lin(g.n, gp);
+            const TIN iP = A.in[P], iQ = A.in[P + sa];
+            const TOUT uP = A.out[P - sa], uQ = A.out[P + 2 * sa];
+            T *rc = rec + kRec1 * j;
+            const T D0 = rc[0], D1 = rc[4];
+            T a0 = cvt_in<T>(iP), a1 = cvt_in<T>(iQ);
+            if (A.scale_by_piv) {
+                a0 *= D0;
+                a1 *= D1;
+            }
+            a0 += cup[2 * j] * cvt_in<T>(uP);
+            a1 += cup[2 * j + 1] * cvt_in<T>(uQ);
+            rc[0] = a0 / D0;
+            rc[4] = a1 / D1;
+        }
+    }
+    for (int j = threadIdx.x; j < (A.img_mode == 2 ? 0 : np); j += nth) {
         int l[3];
         l[a] = F.len[a] - 1;
         l[b] = j % nb;
@@ -1136,14 +1174,6 @@ __device__ __forceinline__ void end_face3g_body(const EndArgs<S, TIN, TOUT> &A, 
             int r[3] = {gq[0], gq[1], gq[2]};
             r[a] -= dq[a];
             const int64_t Ri = lin(g.n, r);
-            if (A.img_mode == 2) {
-                const T D = rc[4 * m + 0];
-                T acc = ldv<T>(A.in, Q);
-                if (A.scale_by_piv) acc *= D;
-                acc += cup[2 * j + m] * ldv<T>(A.out, Ri);
-                rc[4 * m + 0] = acc / D;
-                continue;
-            }
             const T D = ldv<T>(A.piv, Q);
             // the upstream point across AX (inside the member's own tile, final)
             const T cu = ldv<T>(A.diag[dk(a, dq[a])], Ri);
@@ -1184,6 +1214,12 @@ __device__ __forceinline__ void end_face3g_body(const EndArgs<S, TIN, TOUT> &A, 
     if (A.img_mode == 1) return;
     __syncthreads();
     if (threadIdx.x >= kWave) return; // level loop in wave 0 alone, as for the start faces
+    // global strides of the local axes (with the sweep direction) and the point (len_a - 1, 0, 0)
+    const int64_t st[3] = {F.d[0], (int64_t)F.d[1] * g.n[0], (int64_t)F.d[2] * g.n[0] * g.n[1]};
+    int e0[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) e0[q] = F.base[q] + (q == a ? F.d[q] * (F.len[a] - 1) : 0);
+    const int64_t g0 = lin(g.n, e0);
     const int nlev = nb + nc - 1;
     for (int t = 0; t < nlev; ++t) {
         // the points of level t: (lb, t - lb)
@@ -1192,30 +1228,27 @@ __device__ __forceinline__ void end_face3g_body(const EndArgs<S, TIN, TOUT> &A, 
             if (lc < 0 || lc >= nc) continue;
             const int j = lb + lc * nb;
             const T *rc = rec + kRec1 * j;
+            // the in-face upstream values (a weight is zero where the neighbour is outside the face;
+            // the clamped index keeps the read in range and the select drops it)
+            const int jb = lb > 0 ? j - 1 : j, jc = lc > 0 ? j - nb : j;
+            const T pb = vP[jb], qb = vQ[jb], pc = vP[jc], qc = vQ[jc];
             T R0 = rc[0], Rb = rc[4];
             if (lb > 0) {
-                R0 += rc[1] * vP[j - 1];
-                Rb += rc[5] * vQ[j - 1];
+                R0 += rc[1] * pb;
+                Rb += rc[5] * qb;
             }
             if (lc > 0) {
-                R0 += rc[2] * vP[j - nb];
-                Rb += rc[6] * vQ[j - nb];
+                R0 += rc[2] * pc;
+                Rb += rc[6] * qc;
             }
             const T m0 = rc[3], mb = rc[7], idet = rc[8];
             const T x0 = (R0 - m0 * Rb) * idet;
             const T xb = (Rb - mb * R0) * idet;
             vP[j] = x0;
             vQ[j] = xb;
-            int l[3];
-            l[a] = F.len[a] - 1;
-            l[b] = lb;
-            l[c] = lc;
-            int gp[3];
-#pragma unroll
-            for (int q = 0; q < 3; ++q) gp[q] = F.base[q] + F.d[q] * l[q];
-            A.out[lin(g.n, gp)] = (TOUT)x0;
-            gp[a] += F.d[a];
-            A.out[lin(g.n, gp)] = (TOUT)xb;
+            const int64_t gp = g0 + lb * st[b] + lc * st[c];
+            A.out[gp] = (TOUT)x0;
+            A.out[gp + st[a]] = (TOUT)xb;
         }
         wave_order();
     }
