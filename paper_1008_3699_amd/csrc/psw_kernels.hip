@@ -2601,28 +2601,58 @@ __global__ void __launch_bounds__(1024) k_tile3(Tile3Args<S, TIN, TOUT> A) {
     const int nth = blockDim.x;
     const int np = len0 * C;
     // the input, and for a start-coupled pass the values of the coupled start-face points,
-    // which the level kernel has already solved into out (unscaled)
-    // U loads in flight per thread before the LDS stores.  The loads are unconditional (a
-    // guarded load gets its conversion, and so a wait, inside the guard): indices past the
-    // tile repeat its last point, and the start-face points are loaded too and not stored.
+    // which the level kernel has already solved into out (unscaled).  Row-wise: thread t takes
+    // column x = t % XS of the rows (pencils) t / XS + k RPI, U rows at a time with all their
+    // loads in flight before the LDS stores.  The loads are unconditional (a guarded load gets
+    // its conversion, and so a wait, inside the guard; a row past the tile reads its first row),
+    // and the coordinates and addresses advance by fixed steps (the index arithmetic of a general
+    // element order costs more than the copy).
     auto on_face = [&](int l0, int l1, int l2) {
         return CPL && ((l0 == 0 && F.start_cpl[0]) || (l1 == 0 && F.start_cpl[1]) || (l2 == 0 && F.start_cpl[2]));
     };
-    constexpr int U = 16;
-    for (int e0 = threadIdx.x; e0 < np; e0 += U * nth) {
-        TIN v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = min(e0 + u * nth, np - 1);
-            const int l0 = e % len0, c = e / len0, l1 = c % L1, l2 = c / L1;
-            const int gp[3] = {F.base[0] + F.d[0] * l0, F.base[1] + F.d[1] * l1, F.base[2] + F.d[2] * l2};
-            v[u] = A.in[lin(g.n, gp)];
+    const int XS = min(len0, nth), RPI = max(1, nth / len0);
+    const int tx = threadIdx.x % XS, tc = threadIdx.x / XS;
+    const int64_t gs0 = F.d[0], gs1 = (int64_t)F.d[1] * g.n[0], gs2 = (int64_t)F.d[2] * g.n[0] * g.n[1];
+    const int64_t gb = lin(g.n, F.base);
+    const int dl1 = RPI % L1, dl2 = RPI / L1;
+    const int64_t dg = dl1 * gs1 + dl2 * gs2, wrapg = gs2 - (int64_t)L1 * gs1;
+    // row c -> (l1, l2) and its global index at column x
+    auto row_at = [&](int c, int x, int &l1, int &l2, int64_t &gi) {
+        l1 = c % L1;
+        l2 = c / L1;
+        gi = gb + x * gs0 + l1 * gs1 + l2 * gs2;
+    };
+    auto advance = [&](int &l1, int &l2, int64_t &gi) {
+        l1 += dl1;
+        l2 += dl2;
+        gi += dg;
+        if (l1 >= L1) {
+            l1 -= L1;
+            ++l2;
+            gi += wrapg;
         }
+    };
+    constexpr int U = 16;
+    if (tc < RPI) {
+        for (int x = tx; x < len0; x += XS) {
+            const int64_t gx = gb + x * gs0;
+            for (int c0 = tc; c0 < C; c0 += U * RPI) {
+                int l1, l2;
+                int64_t gi;
+                row_at(c0, x, l1, l2, gi);
+                TIN v[U];
+                unsigned keep = 0;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = e0 + u * nth;
-            const int l0 = e % len0, c = e / len0;
-            if (e < np && !on_face(l0, c % L1, c / L1)) own[c * pitch + l0] = cvt_in<T>(v[u]);
+                for (int u = 0; u < U; ++u) {
+                    const bool in = c0 + u * RPI < C;
+                    v[u] = A.in[in ? gi : gx];
+                    if (in && !on_face(x, l1, l2)) keep |= 1u << u;
+                    advance(l1, l2, gi);
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if ((keep >> u) & 1u) own[(c0 + u * RPI) * pitch + x] = cvt_in<T>(v[u]);
+            }
         }
     }
     if (CPL) {
@@ -2658,8 +2688,9 @@ __global__ void __launch_bounds__(1024) k_tile3(Tile3Args<S, TIN, TOUT> A) {
     // (len0 + L1 + L2 - 2) / len0 times the point count, and reading them all would move that
     // many times the coefficient bytes, while the one shared slot stays in cache.
     const Pk3<S> *pk0 = A.pk + A.poff[blockIdx.x];
+    const int o = l1 + l2;
     auto slot = [&](int t) -> const Pk3<S> * {
-        return (have && t - l1 - l2 >= 0 && t - l1 - l2 < len0) ? pk + (int64_t)t * C : pk0;
+        return (have && (unsigned)(t - o) < (unsigned)len0) ? pk + (int64_t)t * C : pk0;
     };
     Pk3<S> ring[PD];
 #pragma unroll
@@ -2699,10 +2730,20 @@ __global__ void __launch_bounds__(1024) k_tile3(Tile3Args<S, TIN, TOUT> A) {
         }
     }
     const T cs = (T)A.cscale;
-    for (int e = threadIdx.x; e < np; e += nth) {
-        const int l0 = e % len0, c2 = e / len0;
-        const int gp[3] = {F.base[0] + F.d[0] * l0, F.base[1] + F.d[1] * (c2 % L1), F.base[2] + F.d[2] * (c2 / L1)};
-        A.out[lin(g.n, gp)] = (TOUT)(cs * own[c2 * pitch + l0]);
+    if (tc < RPI) {
+        for (int x = tx; x < len0; x += XS) {
+            for (int c0 = tc; c0 < C; c0 += U * RPI) {
+                int l1w, l2w;
+                int64_t gi;
+                row_at(c0, x, l1w, l2w, gi);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int cr = c0 + u * RPI;
+                    if (cr < C) A.out[gi] = (TOUT)(cs * own[cr * pitch + x]);
+                    advance(l1w, l2w, gi);
+                }
+            }
+        }
     }
 }
 
