@@ -2716,11 +2716,15 @@ __global__ void __launch_bounds__(1024) k_tile3(Tile3Args<S, TIN, TOUT> A) {
                     }
                     const int o = c * pitch + l0;
                     if (Am == 0) {
+                        // the four reads issued together: a missing upstream neighbour (l = 0) has a
+                        // packed weight of exactly zero and reads the point itself (finite)
+                        const int o0 = l0 > 0 ? o - 1 : o, o1 = l1 > 0 ? o - pitch : o, o2 = l2 > 0 ? o - pitch * L1 : o;
                         T acc = own[o];
+                        const T u0 = own[o0], u1 = own[o1], u2 = own[o2];
                         if (!scale) acc *= s2f(cf.inv);
-                        if (l0 > 0) acc = __fmaf_rn(s2f(cf.c0), own[o - 1], acc);
-                        if (l1 > 0) acc = __fmaf_rn(s2f(cf.c1), own[o - pitch], acc);
-                        if (l2 > 0) acc = __fmaf_rn(s2f(cf.c2), own[o - pitch * L1], acc);
+                        acc = __fmaf_rn(s2f(cf.c0), u0, acc);
+                        acc = __fmaf_rn(s2f(cf.c1), u1, acc);
+                        acc = __fmaf_rn(s2f(cf.c2), u2, acc);
                         own[o] = acc;
                     }
                 }
