@@ -89,8 +89,8 @@ def parse():
     ap.add_argument("--serve-plain-s", type=float, default=10.0,
                     help="serve: time spent solving a sample one by one with the plain FP64 solver")
     ap.add_argument("--roofline-only", action="store_true",
-                    help="varcoef2048: only the timed half-sweeps of the roofline object and a plain copy of "
-                         "512 MiB (the reference for hardware byte counters); no solve")
+                    help="varcoef2048 and poisson3d256: only the timed half-sweeps of the roofline object and a "
+                         "plain copy of 512 MiB (the reference for hardware byte counters); no solve")
     return ap.parse_args()
 
 
@@ -783,6 +783,41 @@ def measure_roofline(g, N, args, stream, k_ms=None, k_n=None):
             "algorithmic_bytes": alg_bytes, **alone}
 
 
+TRAFFIC3_FILE = os.path.join(ROOT, "profiles", "traffic_pass0_poisson3d256_f32.json")
+
+
+def roofline3d(g, f, N, args):
+    """The 3D forward start-coupled half-sweep (start-face kernel + LDS-tile interior kernel), timed with
+    HIP events on the stream it runs on, standalone applications after the timed solves."""
+    import numpy as np
+    import torch
+    y = torch.empty_like(f)
+    stream = torch.cuda.current_stream()
+    reps = 20
+    for _ in range(3):
+        g.precond_half(args.precond, 0, f, y)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record(stream)
+        g.precond_half(args.precond, 0, f, y)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    bpp = 8 + 16 + 8  # FP64 input, packed FP32 coefficients (1/Piv and three couplings), FP64 output
+    if args.prec3 == "bf16":
+        bpp = 8 + 8 + 8
+    achieved = N * bpp / (ms * 1e-3) / 1e9
+    traffic = None
+    if args.prec3 == "f32" and args.n3 == 256 and args.p3 == 8 and args.precond == "ilu0":
+        traffic = measured_traffic(TRAFFIC3_FILE, CG_KERNEL_SRC)
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "3D forward start-coupled half-sweep: k_start_faces3g (coupled start faces) + k_tile3 (interior)",
+            "kernel_ms": round(ms, 4), "timed_launches": reps,
+            "timing": "HIP events on the launching stream around standalone pass-0 applications after the timed solves",
+            "bytes_per_point": bpp, "algorithmic_bytes": N * bpp}
+
+
 def bench_poisson3d(args):
     """3D Poisson, 7-point, n^3 grid (256^3), p^3 subdomains (8^3), overlap 2: FP64 CG with ILU(0) (or
     SSOR) sweeps in FP32 (FP32- or BF16-stored coefficients) to 1e-8."""
@@ -805,6 +840,15 @@ def bench_poisson3d(args):
     f = torch.from_numpy(w["f"]).to(dev)
     u = torch.zeros(N, dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
+    if args.roofline_only:
+        roofline = roofline3d(g, f, N, args)
+        # reference for byte counters: one plain device copy of 512 MiB
+        src = torch.ones(64 << 20, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"roofline": roofline, "copy_bytes_each_way": src.numel() * 8}), flush=True)
+        return
 
     def one_solve():
         u.zero_()
@@ -824,28 +868,7 @@ def bench_poisson3d(args):
     iters = [i["iters"] for i in infos]
     value = N * sum(4 * (it + 1) for it in iters) / elapsed / 1e9
 
-    # the forward half-sweep (start-face level kernel + LDS-tile interior kernel), timed with events
-    # on the stream it runs on, after the timed solves
-    y = torch.empty_like(f)
-    stream = torch.cuda.current_stream()
-    reps = 20
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
-    for a, b in ev:
-        a.record(stream)
-        g.precond_half(args.precond, 0, f, y)
-        b.record(stream)
-    torch.cuda.synchronize()
-    ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-    bpp = 8 + 16 + 8  # FP64 input, packed FP32 coefficients (1/Piv and three couplings), FP64 output
-    if args.prec3 == "bf16":
-        bpp = 8 + 8 + 8
-    achieved = N * bpp / (ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
-                "frac": round(achieved / 8000.0, 4), "traffic": None,
-                "kernel": "3D forward start-coupled half-sweep: k_start_faces3g (coupled start faces) + k_tile3 (interior)",
-                "kernel_ms": round(ms, 4), "timed_launches": reps,
-                "timing": "HIP events on the launching stream around standalone pass-0 applications after the timed solves",
-                "bytes_per_point": bpp, "algorithmic_bytes": N * bpp}
+    roofline = roofline3d(g, f, N, args)
     cpu = None
     if not args.no_cpu:
         from oracle import oracle as O
