@@ -160,6 +160,10 @@ struct psw_problem {
     int n[3] = {1, 1, 1};
     int64_t N = 0;
     bool has_diag = false;
+    // the FP64 diagonals store a symmetric operator (a^W(P) = a^E(P - e_x), ...), bit for bit:
+    // checked once per set of diagonals; the Krylov loops' SpMV then reads the upper couplings only
+    bool sym = false;
+    DevBuf symflag;
     psw_prec prec = PSW_F64;
     DevBuf diag[7];
     double omega[8] = {1, 1, 1, 1, 1, 1, 1, 1};
@@ -184,6 +188,8 @@ struct psw_problem {
     PassTiming timing[5]; // per pass 0..3, and 4: the fused 2D CG step
     int timing_last = 0;
 };
+
+static hipError_t krylov_spmv(psw_problem *P, const double *const *d, const double *p, double *q, hipStream_t st);
 
 namespace {
 
@@ -1052,7 +1058,7 @@ psw_status solve_cg(psw_problem *P, psw_precond kind, double rtol, int64_t maxit
         if (!P->hs.ensure()) return PSW_ENOMEM;
         double *h = P->hs.p;
         while (it < maxit) {
-            HIPCHK(launch_spmv(P->kd, P->n, d, p, q, st));
+            HIPCHK(krylov_spmv(P, d, p, q, st));
             HIPCHK(launch_dot_partial(p, q, N, part_pq, st));
             HIPCHK(launch_cg_update_xr(x, r, p, q, s_rz, part_pq, s_pq, N, part, s_rr, st));
             ++it;
@@ -1140,7 +1146,7 @@ psw_status solve_fgmres(psw_problem *P, psw_precond kind, double rtol, int64_t m
         for (int k = 0; k < m && it < maxit; ++k) {
             double *Vk = V + (size_t)k * N, *Zk = Z + (size_t)k * N;
             if ((ps = precond_apply(P, kind, 0, Vk, Zk, st))) return ps;
-            HIPCHK(launch_spmv(P->kd, P->n, d, Zk, w, st));
+            HIPCHK(krylov_spmv(P, d, Zk, w, st));
             // classical Gram-Schmidt, two passes
             for (int pass = 0; pass < 2; ++pass) {
                 HIPCHK(launch_multi_dot(V, w, k + 1, N, part, hd, st));
@@ -2171,6 +2177,28 @@ static psw_status zero_missing_couplings(psw_problem *P, hipStream_t st) {
     return PSW_OK;
 }
 
+// whether the FP64 diagonals are symmetric (checked once, at set-up, on the set-up stream)
+static psw_status check_symmetric(psw_problem *P, hipStream_t st) {
+    const double *d[7];
+    for (int k = 0; k < 7; ++k) d[k] = P->diag[k].as<double>();
+    if (!P->symflag.ensure(sizeof(int))) return PSW_ENOMEM;
+    int *h = nullptr;
+    if (hipHostMalloc((void **)&h, sizeof(int), hipHostMallocDefault) != hipSuccess) return PSW_ENOMEM;
+    *h = 1;
+    hipError_t e = hipMemcpyAsync(P->symflag.p, h, sizeof(int), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = launch_sym_check(P->kd, P->n, d, P->symflag.as<int>(), st);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, P->symflag.p, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    P->sym = e == hipSuccess && *h == 1;
+    (void)hipHostFree(h);
+    return e == hipSuccess ? PSW_OK : PSW_EDEVICE;
+}
+
+// q = A p in the Krylov loops
+static hipError_t krylov_spmv(psw_problem *P, const double *const *d, const double *p, double *q, hipStream_t st) {
+    return P->sym ? launch_spmv_sym(P->kd, P->n, d, p, q, st) : launch_spmv(P->kd, P->n, d, p, q, st);
+}
+
 static void invalidate(psw_problem *P) {
     P->pc[0].ready = false;
     P->pc[1].ready = false;
@@ -2189,7 +2217,7 @@ psw_status psw_set_diagonals(psw_problem *P, const double *const diag[], int on_
         HIPCHK(hipMemcpyAsync(P->diag[k].p, diag[k], b, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
     }
     if ((ps = zero_missing_couplings(P, st))) return ps;
-    if (!on_device) HIPCHK(hipStreamSynchronize(st));
+    if ((ps = check_symmetric(P, st))) return ps;
     P->prec = prec;
     P->has_diag = true;
     invalidate(P);
@@ -2212,6 +2240,7 @@ psw_status psw_assemble_diffusion(psw_problem *P, const double *const alpha[], d
     HIPCHK(launch_assemble(P->dim, P->n, alpha, beta, out, st));
     psw_status ps = zero_missing_couplings(P, st);
     if (ps) return ps;
+    if ((ps = check_symmetric(P, st))) return ps;
     P->prec = prec;
     P->has_diag = true;
     invalidate(P);

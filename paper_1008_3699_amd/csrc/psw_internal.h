@@ -116,6 +116,11 @@ hipError_t launch_assemble(int dim, const int n[3], const double *const *alpha, 
                            double *const *diag, hipStream_t st);
 hipError_t launch_spmv(int dim, const int n[3], const double *const *diag, const double *x, double *y,
                        hipStream_t st);
+// the same with the lower couplings read as the neighbours' upper ones (symmetric storage only)
+hipError_t launch_spmv_sym(int dim, const int n[3], const double *const *diag, const double *x, double *y,
+                           hipStream_t st);
+// flag[0] (set to 1 by the caller) becomes 0 unless every lower coupling equals the neighbour's upper one
+hipError_t launch_sym_check(int dim, const int n[3], const double *const *diag, int *flag, hipStream_t st);
 hipError_t launch_convert(const double *src, void *dst, Store s, int64_t N, double scale, hipStream_t st);
 hipError_t launch_scale_add(double *z, const double *a, double ca, const void *b, bool b_f64, double cb,
                             int64_t N, hipStream_t st);

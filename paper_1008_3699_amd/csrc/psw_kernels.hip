@@ -1870,6 +1870,52 @@ __global__ void k_spmv(int n0, int n1, int n2, DiagPtrs D, const double *__restr
     }
 }
 
+// SpMV of a structurally symmetric operator stored as P, W, E, S, N (, B, F) diagonals whose
+// lower couplings equal the upper couplings of the neighbours (a^W(P) = a^E(P - e_x), a^S(P) =
+// a^N(P - e_y), a^B(P) = a^F(P - e_z)): the lower couplings are read as the neighbours' upper
+// ones, the same values in the same order as k_spmv, so four (2D: three) diagonal streams
+// come from HBM instead of seven (five); the shifted reads hit lines that neighbouring
+// threads have just brought into the caches.
+template <int DIM>
+__global__ void k_spmv_sym(int n0, int n1, int n2, DiagPtrs D, const double *__restrict__ x, double *__restrict__ y) {
+    const int64_t N = (int64_t)n0 * n1 * n2;
+    const int64_t s1 = n0, s2 = (int64_t)n0 * n1;
+    const double *__restrict__ aP = D.d[0], *__restrict__ aE = D.d[2], *__restrict__ aN = D.d[4];
+    for (int64_t P = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; P < N; P += (int64_t)gridDim.x * blockDim.x) {
+        int i = (int)(P % n0);
+        int j = (int)((P / n0) % n1);
+        double acc = aP[P] * x[P];
+        if (i > 0) acc -= aE[P - 1] * x[P - 1];
+        if (i < n0 - 1) acc -= aE[P] * x[P + 1];
+        if (j > 0) acc -= aN[P - s1] * x[P - s1];
+        if (j < n1 - 1) acc -= aN[P] * x[P + s1];
+        if (DIM == 3) {
+            const double *__restrict__ aF = D.d[6];
+            int k = (int)(P / s2);
+            if (k > 0) acc -= aF[P - s2] * x[P - s2];
+            if (k < n2 - 1) acc -= aF[P] * x[P + s2];
+        }
+        y[P] = acc;
+    }
+}
+
+// flag[0] = 0 if some lower coupling differs (bit for bit) from the neighbour's upper coupling
+__global__ void k_sym_check(int dim, int n0, int n1, int n2, DiagPtrs D, int *flag) {
+    const int64_t N = (int64_t)n0 * n1 * n2;
+    const int64_t s1 = n0, s2 = (int64_t)n0 * n1;
+    bool ok = true;
+    for (int64_t P = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; P < N; P += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(P % n0), j = (int)((P / n0) % n1);
+        if (i < n0 - 1 && D.d[2][P] != D.d[1][P + 1]) ok = false;
+        if (j < n1 - 1 && D.d[4][P] != D.d[3][P + s1]) ok = false;
+        if (dim == 3) {
+            const int k = (int)(P / s2);
+            if (k < n2 - 1 && D.d[6][P] != D.d[5][P + s2]) ok = false;
+        }
+    }
+    if (!ok) flag[0] = 0;
+}
+
 static unsigned grid_for(int64_t N, int threads = 256, int64_t cap = 8192) {
     int64_t b = (N + threads - 1) / threads;
     if (b > cap) b = cap;
@@ -1897,6 +1943,26 @@ hipError_t launch_spmv(int dim, const int n[3], const double *const *diag, const
         hipLaunchKernelGGL(k_spmv<2>, dim3(grid_for(N)), dim3(256), 0, st, n[0], n[1], n[2], D, x, y, (const double *)nullptr);
     else
         hipLaunchKernelGGL(k_spmv<3>, dim3(grid_for(N)), dim3(256), 0, st, n[0], n[1], n[2], D, x, y, (const double *)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv_sym(int dim, const int n[3], const double *const *diag, const double *x, double *y,
+                           hipStream_t st) {
+    DiagPtrs D{};
+    for (int k = 0; k < 2 * dim + 1; ++k) D.d[k] = diag[k];
+    int64_t N = (int64_t)n[0] * n[1] * n[2];
+    if (dim == 2)
+        hipLaunchKernelGGL(k_spmv_sym<2>, dim3(grid_for(N)), dim3(256), 0, st, n[0], n[1], n[2], D, x, y);
+    else
+        hipLaunchKernelGGL(k_spmv_sym<3>, dim3(grid_for(N)), dim3(256), 0, st, n[0], n[1], n[2], D, x, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_sym_check(int dim, const int n[3], const double *const *diag, int *flag, hipStream_t st) {
+    DiagPtrs D{};
+    for (int k = 0; k < 2 * dim + 1; ++k) D.d[k] = diag[k];
+    int64_t N = (int64_t)n[0] * n[1] * n[2];
+    hipLaunchKernelGGL(k_sym_check, dim3(grid_for(N)), dim3(256), 0, st, dim, n[0], n[1], n[2], D, flag);
     return hipGetLastError();
 }
 
