@@ -253,8 +253,9 @@ def pass_table(N, args, live):
 def cg_step_roofline(N, args, c_ms, c_n):
     """The fused 2D CG step (k_cg_pq2d): p = z + beta p with z formed from its two pieces, the
     deferred x update, q = A p and the p.q partials.  Algorithmic bytes per point: z1, z2, old p,
-    five diagonals and x read (72), new p, q and x written (24)."""
-    bpp = 96
+    three diagonals (the operator is stored symmetric: a^P, a^E, a^N) and x read (56), new p, q and
+    x written (24)."""
+    bpp = 80
     alg = bpp * N
     achieved = alg / (c_ms * 1e-3) / 1e9
     traffic = None
@@ -262,7 +263,7 @@ def cg_step_roofline(N, args, c_ms, c_n):
         traffic = measured_traffic(CG_TRAFFIC_FILE, CG_KERNEL_SRC)
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_cg_pq2d<true,2> (fused CG step: p update, x update, q = A p, p.q partials)",
+            "kernel": "k_cg_pq2d<true,2,true> (fused CG step on symmetric storage: p update, x update, q = A p, p.q partials)",
             "kernel_ms": round(c_ms, 4), "timed_launches": c_n,
             "timing": "HIP events on the launching stream around every 8th fused step inside the timed solves",
             "bytes_per_point": bpp, "algorithmic_bytes": alg}
@@ -444,13 +445,13 @@ def bench_sor2048(args):
 
 def cg_iteration_bytes(dim, prec):
     """Algorithmic HBM bytes per point of one CG iteration with the symmetric preconditioner: the four
-    half-sweeps (pass_bytes; 3D passes read three couplings), the operator product (2 dim + 2 FP64
-    arrays read, one written) and the vector work (r update with its norm, r.z, p update: about 13
-    FP64 values moved)."""
+    half-sweeps (pass_bytes; 3D passes read three couplings), the operator product on symmetric
+    storage (a^P and one coupling per axis, and p read, q written: dim + 3 FP64 values) and the
+    vector work (r update with its norm, r.z, p update: about 13 FP64 values moved)."""
     pb = pass_bytes(prec)
     sz = {"f64": 8, "f32": 4, "bf16": 2}[prec]
     passes = sum(pb.values()) + (2 * sz if dim == 3 else 0)  # one more coupling per pass in 3D
-    spmv = 8 * (2 * dim + 2) + 8
+    spmv = 8 * (dim + 3)
     return passes + spmv + 13 * 8
 
 

@@ -967,7 +967,7 @@ psw_status cg2d_fused(psw_problem *P, psw_precond kind, bool split, double rtol,
         const bool timed = T.on && (T.calls++ % PassTiming::kStride) == 0 && T.used < PassTiming::kPool;
         if (timed) HIPCHK(hipEventRecord(T.ev[2 * T.used], st));
         HIPCHK(launch_cg_pq2d(P->n[0], P->n[1], d, z1, z2, hc, pa, pb, q, x, part_rz, s_rz2, s_rz, out + 1, it == 0,
-                              part_pq, &npq, st));
+                              part_pq, &npq, P->sym, st));
         if (timed) {
             HIPCHK(hipEventRecord(T.ev[2 * T.used + 1], st));
             ++T.used;

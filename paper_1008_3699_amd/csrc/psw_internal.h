@@ -171,7 +171,7 @@ hipError_t launch_axpy_dev(double *y, const double *a, const double *x, int64_t 
 hipError_t launch_cg_pq2d(int n0, int n1, const double *const *diag, const double *z1, const double *z2, double hb,
                           const double *pold, double *pnew, double *q, double *x, const double *rz_part,
                           double *rz_new, const double *rz_old, const double *alpha_prev, bool first,
-                          double *pq_part, int *npq, hipStream_t st);
+                          double *pq_part, int *npq, bool sym, hipStream_t st);
 // r -= alpha q, alpha = rz[0] / (sum of npq partials); out[0] = p.q, out[1] = alpha,
 // out[2 .. 2 + kRedBlocks) = partials of r.r; the same to hout (device-visible pinned host memory) if given
 hipError_t launch_cg_r(double *r, const double *q, const double *rz, const double *pq_part, int npq, double *out,

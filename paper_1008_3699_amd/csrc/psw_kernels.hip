@@ -2291,8 +2291,12 @@ template <int V> struct CgRowOp {
 // the wave is formed once per tile by a gather and handed out row by row.
 // The blocks of one XCD (blockIdx mod 8) take one contiguous range of tiles,
 // so vertically adjacent tiles, and their halo rows, share that XCD's L2.
+// SYM: symmetric storage (checked at set-up): the W coupling of a point is the E coupling of its
+// left neighbour (the lane to the left, or the wave's left halo column gathered per tile) and the
+// S coupling the N coupling of the row below (carried from the previous row): three diagonal
+// streams instead of five, the same values in the same order.
 constexpr int kCgRows = 16;
-template <bool SPLIT, int V>
+template <bool SPLIT, int V, bool SYM>
 __global__ void __launch_bounds__(256) k_cg_pq2d(int n0, int n1, int nbx, int ntiles, int tpb, DiagPtrs D,
                                                  const double *__restrict__ z1, const double *__restrict__ z2,
                                                  double hb, const double *__restrict__ pold, double *__restrict__ pnew,
@@ -2317,7 +2321,8 @@ __global__ void __launch_bounds__(256) k_cg_pq2d(int n0, int n1, int nbx, int nt
     };
     auto load_op = [&](CgRowOp<V> &o, int64_t P) {
 #pragma unroll
-        for (int k = 0; k < 5; ++k) ldv<V>(D.d[k], P, o.d[k]);
+        for (int k = 0; k < 5; ++k)
+            if (!SYM || k % 2 == 0) ldv<V>(D.d[k], P, o.d[k]);
         if (!first) ldv<V>(x, P, o.x);
     };
     auto form = [&](const CgRowIn<V> &r, double (&o)[V]) {
@@ -2335,15 +2340,21 @@ __global__ void __launch_bounds__(256) k_cg_pq2d(int n0, int n1, int nbx, int nt
         const bool in = i < n0;
         const int ic = in ? i : 0; // loads of lanes beyond the grid read column 0 and are dropped
         // new p on the columns beyond the wave's two sides, rows j0-1 .. j1: lanes 0.. left, 32.. right
-        double hn = 0.0;
+        double hn = 0.0, he = 0.0; // he (SYM, left column): its E coupling, the W of column c0
         {
             const int hr = lane & 31, hrow = j0 - 1 + hr;
             const int hcol = (lane >> 5) ? c0 + 64 * V : c0 - 1;
             if (hr < j1 - j0 + 2 && hrow >= 0 && hrow < n1 && hcol >= 0 && hcol < n0) {
                 const int64_t H = (int64_t)hrow * n0 + hcol;
                 hn = newp(z1[H], SPLIT ? z2[H] : 0.0, first ? 0.0 : pold[H]);
+                if (SYM && !(lane >> 5)) he = D.d[2][H];
             }
         }
+        // SYM: the N coupling of the row below the strip (the S coupling of its first row)
+        double nprev[V];
+#pragma unroll
+        for (int c = 0; c < V; ++c) nprev[c] = 0.0;
+        if (SYM && j0 > 0) ldv<V>(D.d[4], (int64_t)(j0 - 1) * n0 + ic, nprev);
         double pm[V], pc[V], oc[V];
         CgRowIn<V> ra, rb; // new-p inputs of rows j+1 and j+2
         CgRowOp<V> oa, ob; // operator rows j and j+1
@@ -2367,6 +2378,22 @@ __global__ void __launch_bounds__(256) k_cg_pq2d(int n0, int n1, int nbx, int nt
             form(ra, pp);
             const double sl = from_lower_lane(pc[V - 1]), sr = from_upper_lane(pc[0]); // every lane takes part
             const double h = __shfl(hn, (lane == 63 ? 32 : 0) + (j - j0 + 1), 64);
+            double wc[V], sc[V]; // W and S couplings of this row
+            if (SYM) {
+                const double el = from_lower_lane(oa.d[2][V - 1]);
+                const double eh = __shfl(he, j - j0 + 1, 64);
+#pragma unroll
+                for (int c = 0; c < V; ++c) {
+                    wc[c] = c > 0 ? oa.d[2][c - 1] : (lane == 0 ? eh : el);
+                    sc[c] = nprev[c];
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < V; ++c) {
+                    wc[c] = oa.d[1][c];
+                    sc[c] = oa.d[3][c];
+                }
+            }
             if (in) {
                 const int64_t P = (int64_t)j * n0 + i;
                 double qa[V], xn[V];
@@ -2375,9 +2402,9 @@ __global__ void __launch_bounds__(256) k_cg_pq2d(int n0, int n1, int nbx, int nt
                     const double pl = c > 0 ? pc[c - 1] : (lane == 0 ? h : sl);
                     const double pr = c < V - 1 ? pc[c + 1] : (lane == 63 ? h : sr);
                     double a = oa.d[0][c] * pc[c];
-                    if (i + c > 0) a -= oa.d[1][c] * pl;
+                    if (i + c > 0) a -= wc[c] * pl;
                     if (i + c < n0 - 1) a -= oa.d[2][c] * pr;
-                    if (j > 0) a -= oa.d[3][c] * pm[c];
+                    if (j > 0) a -= sc[c] * pm[c];
                     if (j < n1 - 1) a -= oa.d[4][c] * pp[c];
                     qa[c] = a;
                     acc += pc[c] * a;
@@ -2392,6 +2419,7 @@ __global__ void __launch_bounds__(256) k_cg_pq2d(int n0, int n1, int nbx, int nt
                 pm[c] = pc[c];
                 pc[c] = pp[c];
                 oc[c] = first ? 0.0 : ra.po[c];
+                nprev[c] = oa.d[4][c];
             }
             ra = rb;
             oa = ob;
@@ -2404,7 +2432,7 @@ __global__ void __launch_bounds__(256) k_cg_pq2d(int n0, int n1, int nbx, int nt
 hipError_t launch_cg_pq2d(int n0, int n1, const double *const *diag, const double *z1, const double *z2, double hb,
                           const double *pold, double *pnew, double *q, double *x, const double *rz_part,
                           double *rz_new, const double *rz_old, const double *alpha_prev, bool first,
-                          double *pq_part, int *npq, hipStream_t st) {
+                          double *pq_part, int *npq, bool sym, hipStream_t st) {
     DiagPtrs D{};
     bool al = n0 % 2 == 0;
     for (int k = 0; k < 5; ++k) {
@@ -2421,13 +2449,19 @@ hipError_t launch_cg_pq2d(int n0, int n1, const double *const *diag, const doubl
     grid = (grid + 7) / 8 * 8; // at most kRedBlocks, a multiple of 8
     *npq = grid;
     const int tpb = (ntiles + grid - 1) / grid;
-#define PSW_CG_PQ(S, VV)                                                                                              \
-    hipLaunchKernelGGL((k_cg_pq2d<S, VV>), dim3(grid), dim3(256), 0, st, n0, n1, nbx, ntiles, tpb, D, z1, z2, hb,   \
+#define PSW_CG_PQ(S, VV, SY)                                                                                          \
+    hipLaunchKernelGGL((k_cg_pq2d<S, VV, SY>), dim3(grid), dim3(256), 0, st, n0, n1, nbx, ntiles, tpb, D, z1, z2, hb,\
                        pold, pnew, q, x, rz_part, rz_new, rz_old, alpha_prev, (int)first, pq_part)
-    if (z2) {
-        if (V == 2) PSW_CG_PQ(true, 2); else PSW_CG_PQ(true, 1);
+    if (sym) {
+        if (z2) {
+            if (V == 2) PSW_CG_PQ(true, 2, true); else PSW_CG_PQ(true, 1, true);
+        } else {
+            if (V == 2) PSW_CG_PQ(false, 2, true); else PSW_CG_PQ(false, 1, true);
+        }
+    } else if (z2) {
+        if (V == 2) PSW_CG_PQ(true, 2, false); else PSW_CG_PQ(true, 1, false);
     } else {
-        if (V == 2) PSW_CG_PQ(false, 2); else PSW_CG_PQ(false, 1);
+        if (V == 2) PSW_CG_PQ(false, 2, false); else PSW_CG_PQ(false, 1, false);
     }
 #undef PSW_CG_PQ
     return hipGetLastError();
