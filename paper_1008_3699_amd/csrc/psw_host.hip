@@ -997,6 +997,78 @@ psw_status cg2d_fused(psw_problem *P, psw_precond kind, bool split, double rtol,
     return PSW_OK;
 }
 
+// The same loop on a 3D grid with the fused 3D step (k_cg_pq3d).  With the LDS-tile passes in
+// FP32/BF16 the preconditioned residual stays in two pieces, z = 0.5 z1 + 0.5 c z2 with z2 the
+// FP32 output of the transposed pair, formed inside the kernels that read it.
+psw_status cg3d_fused(psw_problem *P, psw_precond kind, double rtol, int64_t maxit, double nf, double *x,
+                      int64_t &it, bool &conv, hipStream_t st) {
+    const double *d[7];
+    diag64(P, d);
+    const int64_t N = P->N;
+    double *r = P->w_r.as<double>(), *z = P->w_z.as<double>(), *q = P->w_q.as<double>();
+    double *pa = P->w_p.as<double>(), *pb = P->w_t.as<double>();
+    const bool split3 = kind != PSW_NONE && P->pc[kind].tile3 && P->prec != PSW_F64;
+    const double hc = split3 ? 0.5 * P->pc[kind].c : 0.0;
+    const float *z2f = nullptr;
+    double *s = P->scal.as<double>();
+    double *s_rz = s + 0, *s_rz2 = s + 1;
+    double *part = P->partials.as<double>();
+    // the fused step writes up to kCgPq3dMaxBlocks p.q partials: their own region, after out
+    double *part_rz = part + 2 * kRedBlocks, *out = part + 3 * kRedBlocks, *part_pq = part + 5 * kRedBlocks;
+    static_assert(5 * kRedBlocks + kCgPq3dMaxBlocks <= 64 * kRedBlocks, "partials region");
+    int npq = 0;
+    psw_status ps;
+    // z from r, then its r.z partials
+    auto precond = [&]() -> psw_status {
+        if (split3) {
+            const void *zp = nullptr;
+            psw_status e = precond_sym_split3(P, kind, r, z, &zp, st);
+            if (e) return e;
+            z2f = (const float *)zp;
+            HIPCHK(launch_dot_partial_zf(r, z, z2f, hc, N, part_rz, st));
+        } else {
+            const double *zz = r;
+            if (kind != PSW_NONE) {
+                psw_status e = precond_apply(P, kind, 1, r, z, st);
+                if (e) return e;
+                zz = z;
+            }
+            HIPCHK(launch_dot_partial(r, zz, N, part_rz, st));
+        }
+        return PSW_OK;
+    };
+    const double *z1 = kind != PSW_NONE ? z : r;
+    if ((ps = precond())) return ps;
+    if (!P->hs.ensure()) return PSW_ENOMEM;
+    double *h = P->hs.p, *hdev = nullptr;
+    HIPCHK(hipHostGetDevicePointer((void **)&hdev, h, 0));
+    while (it < maxit) {
+        HIPCHK(launch_cg_pq3d(P->n, d, z1, split3 ? z2f : nullptr, hc, pa, pb, q, x, part_rz, s_rz2, s_rz, out + 1,
+                              it == 0, part_pq, &npq, P->sym, st));
+        std::swap(pa, pb);
+        std::swap(s_rz, s_rz2);
+        // p.q and the r.r partials go straight to pinned host memory, read behind an event; the
+        // next preconditioner is queued before the host waits for them
+        HIPCHK(launch_cg_r(r, q, s_rz, part_pq, npq, out, N, hdev, st));
+        ++it;
+        HIPCHK(hipEventRecord(P->hs.ev, st));
+        if ((ps = precond())) return ps;
+        HIPCHK(hipEventSynchronize(P->hs.ev));
+        double rr = 0.0;
+        for (int b = 0; b < kRedBlocks; ++b) rr += h[2 + b];
+        if (!(h[0] > 0.0) || !std::isfinite(rr)) {
+            (void)hipStreamSynchronize(st);
+            return PSW_EBREAKDOWN;
+        }
+        if (std::sqrt(rr) / nf <= rtol) {
+            conv = true;
+            break;
+        }
+    }
+    if (it > 0) HIPCHK(launch_axpy_dev(x, out + 1, pa, N, st));
+    return PSW_OK;
+}
+
 psw_status solve_cg(psw_problem *P, psw_precond kind, double rtol, int64_t maxit, const double *f, double *x,
                     psw_info *info, hipStream_t st) {
     psw_status ps = ensure_work(P);
@@ -1004,11 +1076,7 @@ psw_status solve_cg(psw_problem *P, psw_precond kind, double rtol, int64_t maxit
     if (kind != PSW_NONE && (ps = precond_setup(P, kind, st))) return ps;
     const double *d[7];
     diag64(P, d);
-    const int64_t N = P->N;
-    double *r = P->w_r.as<double>(), *z = P->w_z.as<double>(), *p = P->w_p.as<double>(), *q = P->w_q.as<double>();
-    double *s = P->scal.as<double>();
-    double *s_rz = s + 0, *s_rz2 = s + 1, *s_pq = s + 2, *s_rr = s + 3;
-    double *part = P->partials.as<double>();
+    double *r = P->w_r.as<double>();
     double nf;
     if ((ps = host_norm(P, f, &nf, st))) return ps;
     if (nf == 0.0) nf = 1.0;
@@ -1022,78 +1090,10 @@ psw_status solve_cg(psw_problem *P, psw_precond kind, double rtol, int64_t maxit
         // with the pipelined 2D passes the preconditioned residual stays in two pieces,
         // z = 0.5 z1 + 0.5 c z2, formed inside the two kernels that read it
         const bool split = kind != PSW_NONE && P->pc[kind].fast;
-        double *z2 = P->w_z1.as<double>();
-        const double hc = kind != PSW_NONE ? 0.5 * P->pc[kind].c : 0.0;
-        double *part_pq = part + kRedBlocks, *part_rz = part + 2 * kRedBlocks;
-        if (P->kd == 2) {
-            ps = cg2d_fused(P, kind, split, rtol, maxit, nf, x, it, conv, st);
-            if (ps) return ps;
-            goto done;
-        }
-        // 3D LDS-tile passes in FP32/BF16: z stays as z1 (FP64) and the FP32 output of the
-        // transposed pair, formed inside the r.z and p kernels
-        const bool split3 = kind != PSW_NONE && P->pc[kind].tile3 && P->prec != PSW_F64;
-        const float *z2f = nullptr;
-        auto apply3 = [&]() -> psw_status {
-            const void *zp = nullptr;
-            psw_status e = precond_sym_split3(P, kind, r, z, &zp, st);
-            z2f = (const float *)zp;
-            return e;
-        };
-        if (split3) {
-            if ((ps = apply3())) return ps;
-            HIPCHK(launch_dot_partial_zf(r, z, z2f, hc, N, part_rz, st));
-            HIPCHK(launch_dot_final(part_rz, s_rz, st));
-            HIPCHK(launch_zcomb_f(p, z, z2f, hc, N, st));
-        } else if (split) {
-            if ((ps = precond_sym_split(P, kind, r, z, z2, st))) return ps;
-            HIPCHK(launch_dot_partial_zz(r, z, z2, hc, N, part_rz, st));
-            HIPCHK(launch_dot_final(part_rz, s_rz, st));
-            HIPCHK(launch_zcomb(p, z, z2, hc, N, st));
-        } else {
-            if ((ps = precond_apply(P, kind, 1, r, z, st))) return ps;
-            HIPCHK(launch_dot(r, z, N, part, s_rz, st));
-            HIPCHK(hipMemcpyAsync(p, z, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
-        }
-        if (!P->hs.ensure()) return PSW_ENOMEM;
-        double *h = P->hs.p;
-        while (it < maxit) {
-            HIPCHK(krylov_spmv(P, d, p, q, st));
-            HIPCHK(launch_dot_partial(p, q, N, part_pq, st));
-            HIPCHK(launch_cg_update_xr(x, r, p, q, s_rz, part_pq, s_pq, N, part, s_rr, st));
-            ++it;
-            // p.q and r.r of this iteration go to the host behind an event; the rest of the
-            // iteration (which leaves x alone) is queued before the host waits for them, so the
-            // device stays busy while the stopping test runs
-            HIPCHK(hipMemcpyAsync(h, s_pq, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-            HIPCHK(hipEventRecord(P->hs.ev, st));
-            if (split3) {
-                if ((ps = apply3())) return ps;
-                HIPCHK(launch_dot_partial_zf(r, z, z2f, hc, N, part_rz, st));
-                HIPCHK(launch_cg_update_p_red_zf(p, z, z2f, hc, part_rz, s_rz2, s_rz, N, st));
-            } else if (split) {
-                if ((ps = precond_sym_split(P, kind, r, z, z2, st))) return ps;
-                HIPCHK(launch_dot_partial_zz(r, z, z2, hc, N, part_rz, st));
-                HIPCHK(launch_cg_update_p_red_zz(p, z, z2, hc, part_rz, s_rz2, s_rz, N, st));
-            } else {
-                if ((ps = precond_apply(P, kind, 1, r, z, st))) return ps;
-                HIPCHK(launch_dot_partial(r, z, N, part_rz, st));
-                HIPCHK(launch_cg_update_p_red(p, z, part_rz, s_rz2, s_rz, N, st));
-            }
-            std::swap(s_rz, s_rz2);
-            HIPCHK(hipEventSynchronize(P->hs.ev));
-            if (!(h[0] > 0.0) || !std::isfinite(h[1])) {
-                (void)hipStreamSynchronize(st);
-                return PSW_EBREAKDOWN;
-            }
-            rel = std::sqrt(h[1]) / nf;
-            if (rel <= rtol) {
-                conv = true;
-                break;
-            }
-        }
+        ps = P->kd == 2 ? cg2d_fused(P, kind, split, rtol, maxit, nf, x, it, conv, st)
+                        : cg3d_fused(P, kind, rtol, maxit, nf, x, it, conv, st);
+        if (ps) return ps;
     }
-done:
     // true residual at exit
     HIPCHK(launch_residual(P->kd, P->n, d, f, x, r, st));
     if ((ps = host_norm(P, r, &nr, st))) return ps;
@@ -2196,6 +2196,7 @@ static psw_status check_symmetric(psw_problem *P, hipStream_t st) {
 
 // q = A p in the Krylov loops
 static hipError_t krylov_spmv(psw_problem *P, const double *const *d, const double *p, double *q, hipStream_t st) {
+    if (P->kd == 3) return launch_spmv3(P->n, d, P->sym, p, q, st);
     return P->sym ? launch_spmv_sym(P->kd, P->n, d, p, q, st) : launch_spmv(P->kd, P->n, d, p, q, st);
 }
 

@@ -119,6 +119,9 @@ hipError_t launch_spmv(int dim, const int n[3], const double *const *diag, const
 // the same with the lower couplings read as the neighbours' upper ones (symmetric storage only)
 hipError_t launch_spmv_sym(int dim, const int n[3], const double *const *diag, const double *x, double *y,
                            hipStream_t st);
+// 3D q = A x marching through z runs; sym: the lower couplings read as the neighbours' upper ones
+hipError_t launch_spmv3(const int n[3], const double *const *diag, bool sym, const double *x, double *q,
+                        hipStream_t st);
 // flag[0] (set to 1 by the caller) becomes 0 unless every lower coupling equals the neighbour's upper one
 hipError_t launch_sym_check(int dim, const int n[3], const double *const *diag, int *flag, hipStream_t st);
 hipError_t launch_convert(const double *src, void *dst, Store s, int64_t N, double scale, hipStream_t st);
@@ -128,40 +131,21 @@ hipError_t launch_scale_add(double *z, const double *a, double ca, const void *b
 // Deterministic reductions: partial sums per block in fixed order, then one
 // block sums the partials in fixed order.  `partials` holds kRedBlocks doubles.
 constexpr int kRedBlocks = 1024;
+// most blocks (and p.q partials) of the fused 3D CG step
+constexpr int kCgPq3dMaxBlocks = 2 * kRedBlocks;
 constexpr int kRedThreads = 256;
 hipError_t launch_dot(const double *x, const double *y, int64_t N, double *partials, double *out,
                       hipStream_t st);
 
 // CG helpers with device-resident scalars.
-//   x += alpha p ; r -= alpha q ; alpha = s[0]/s[1]; partial dot r.r -> out
-hipError_t launch_cg_update_xr(double *x, double *r, const double *p, const double *q, const double *num,
-                               const double *den_partials, double *den, int64_t N, double *partials, double *rr,
-                               hipStream_t st);
-// out[0] = sum of kRedBlocks partials (fixed order)
-hipError_t launch_dot_final(const double *partials, double *out, hipStream_t st);
 // per-block partial sums of x.y (kRedBlocks of them)
 hipError_t launch_dot_partial(const double *x, const double *y, int64_t N, double *partials, hipStream_t st);
-// with z = 0.5 z1 + b z2 formed on the fly: r.z partials; p = z + beta p (beta from r.z partials); z itself
+// r.z partials with z = 0.5 z1 + b z2 formed on the fly (z2 in FP64, or in FP32: the output of
+// FP32/BF16 sweeps)
 hipError_t launch_dot_partial_zz(const double *r, const double *z1, const double *z2, double b, int64_t N,
                                  double *partials, hipStream_t st);
-hipError_t launch_cg_update_p_red_zz(double *p, const double *z1, const double *z2, double b,
-                                     const double *num_partials, double *num, const double *den, int64_t N,
-                                     hipStream_t st);
-hipError_t launch_zcomb(double *z, const double *z1, const double *z2, double b, int64_t N, hipStream_t st);
-// The same three with the second piece z2 in FP32 (the output of FP32/BF16 sweeps).
 hipError_t launch_dot_partial_zf(const double *r, const double *z1, const float *z2, double b, int64_t N,
                                  double *partials, hipStream_t st);
-hipError_t launch_cg_update_p_red_zf(double *p, const double *z1, const float *z2, double b,
-                                     const double *num_partials, double *num, const double *den, int64_t N,
-                                     hipStream_t st);
-hipError_t launch_zcomb_f(double *z, const double *z1, const float *z2, double b, int64_t N, hipStream_t st);
-// p = z + beta p with beta = (sum of num_partials) / den[0]; stores the sum to num[0]
-hipError_t launch_cg_update_p_red(double *p, const double *z, const double *num_partials, double *num,
-                                  const double *den, int64_t N, hipStream_t st);
-//   p = z + beta p ; beta = num/den
-hipError_t launch_cg_update_p(double *p, const double *z, const double *num, const double *den, int64_t N,
-                              hipStream_t st);
-hipError_t launch_axpy(double *y, double a, const double *x, int64_t N, hipStream_t st);
 // y += a[0] x, a on the device
 hipError_t launch_axpy_dev(double *y, const double *a, const double *x, int64_t N, hipStream_t st);
 // Fused CG step on a 2D grid (5-point operator in diag[0..4]): beta = rz / rz_old[0] with rz the
@@ -169,6 +153,12 @@ hipError_t launch_axpy_dev(double *y, const double *a, const double *x, int64_t 
 // x += alpha_prev[0] pold (skipped when first), q = A pnew, and *npq (<= kRedBlocks) partials of p.q.
 // z = 0.5 z1 + hb z2 when z2 is given, else z1.  pnew must not alias pold.
 hipError_t launch_cg_pq2d(int n0, int n1, const double *const *diag, const double *z1, const double *z2, double hb,
+                          const double *pold, double *pnew, double *q, double *x, const double *rz_part,
+                          double *rz_new, const double *rz_old, const double *alpha_prev, bool first,
+                          double *pq_part, int *npq, bool sym, hipStream_t st);
+// The same on a 3D grid (7-point operator in diag[0..6]); z = 0.5 z1 + hb z2 with z2 in FP32 when
+// given, else z1.  pnew must not alias pold.  *npq <= kCgPq3dMaxBlocks partials of p.q.
+hipError_t launch_cg_pq3d(const int n[3], const double *const *diag, const double *z1, const float *z2, double hb,
                           const double *pold, double *pnew, double *q, double *x, const double *rz_part,
                           double *rz_new, const double *rz_old, const double *alpha_prev, bool first,
                           double *pq_part, int *npq, bool sym, hipStream_t st);

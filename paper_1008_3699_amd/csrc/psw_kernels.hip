@@ -2116,61 +2116,107 @@ hipError_t launch_dot(const double *x, const double *y, int64_t N, double *parti
     return hipGetLastError();
 }
 
-// sum of kRedBlocks partials in the fixed order of k_dot_final, by every block that needs it
-__device__ __forceinline__ double sum_partials(const double *p, double *sh) {
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < kRedBlocks; i += kRedThreads) acc += p[i];
-    return block_sum(acc, sh);
-}
-
-// x += alpha p, r -= alpha q, r.r partials; alpha = num / (sum of den_partials), the sum stored to den
-__global__ void __launch_bounds__(kRedThreads) k_cg_xr(double *x, double *r, const double *p, const double *q,
-                                                      const double *num, const double *den_partials, double *den,
-                                                      int64_t N, double *partials) {
-    __shared__ double sh[kRedThreads];
-    const double pq = sum_partials(den_partials, sh);
-    if (blockIdx.x == 0 && threadIdx.x == 0) den[0] = pq;
-    const double alpha = num[0] / pq;
-    double acc = 0.0;
-    const int64_t stride = (int64_t)kRedBlocks * kRedThreads;
-    for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < N; i += stride) {
-        x[i] += alpha * p[i];
-        double ri = r[i] - alpha * q[i];
-        r[i] = ri;
-        acc += ri * ri;
-    }
-    double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) partials[blockIdx.x] = s;
-}
-
-hipError_t launch_cg_update_xr(double *x, double *r, const double *p, const double *q, const double *num,
-                               const double *den_partials, double *den, int64_t N, double *partials, double *rr,
-                               hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_xr, dim3(kRedBlocks), dim3(kRedThreads), 0, st, x, r, p, q, num, den_partials, den, N,
-                       partials);
-    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kRedThreads), 0, st, partials, rr);
-    return hipGetLastError();
-}
-
-hipError_t launch_dot_final(const double *partials, double *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kRedThreads), 0, st, partials, out);
-    return hipGetLastError();
-}
-
 hipError_t launch_dot_partial(const double *x, const double *y, int64_t N, double *partials, hipStream_t st) {
     hipLaunchKernelGGL(k_dot_partial, dim3(kRedBlocks), dim3(kRedThreads), 0, st, x, y, N, partials);
     return hipGetLastError();
 }
 
-// p = z + beta p, beta = (sum of num_partials) / den; the sum stored to num
-__global__ void __launch_bounds__(kRedThreads) k_cg_p_red(double *p, const double *z, const double *num_partials,
-                                                         double *num, const double *den, int64_t N) {
-    __shared__ double sh[kRedThreads];
-    const double rz = sum_partials(num_partials, sh);
-    if (blockIdx.x == 0 && threadIdx.x == 0) num[0] = rz;
-    const double beta = rz / den[0];
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = z[i] + beta * p[i];
+// 3D q = A x (7-point), the Krylov operator product outside the fused CG step.  Each thread walks
+// one (x, y) column through a run of z planes and keeps the values of the planes below and above in
+// registers, so x and the z couplings come from HBM once; the in-plane neighbours hit lines that
+// the neighbouring lanes and waves load for their own columns.  Every load is unconditional
+// (clamped index; an absent neighbour gets a zero coupling), and so is the store: a lane past the
+// grid's edge works on the clamped edge column and writes the same bits as that column's own lane,
+// so no load is sunk under a branch and waits there.  The terms are taken in the order of k_spmv.
+// SYM: the lower couplings are the neighbours' upper ones (a^W(P) = a^E(P - e_x), a^S(P) =
+// a^N(P - e_y), a^B(P) = a^F(P - e_z)).  Blocks walk (column tile, z run) items; with a block count
+// that is a multiple of 8, block b starts at item (b mod 8) * (blocks / 8) + b / 8, so the blocks
+// of one XCD (b mod 8) hold neighbouring tiles of one z run and meet each other's halo lines in
+// their L2.
+constexpr int kSp3X = 64, kSp3Y = 4;
+
+template <bool SYM>
+__global__ void __launch_bounds__(kSp3X *kSp3Y)
+    k_spmv3(int n0, int n1, int n2, int ntx, int nty, int lz, int nitems, DiagPtrs D, const double *__restrict__ x,
+            double *__restrict__ q) {
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int start = (nb & 7) == 0 ? (b & 7) * (nb >> 3) + (b >> 3) : b;
+    const int64_t s1 = n0, s2 = (int64_t)n0 * n1;
+    const int lx = threadIdx.x % kSp3X, ly = threadIdx.x / kSp3X;
+    const double *__restrict__ aP = D.d[0], *__restrict__ aE = D.d[2], *__restrict__ aN = D.d[4];
+    const double *__restrict__ aF = D.d[6];
+    for (int it = start; it < nitems; it += nb) {
+        const int cx = it % ntx, rest = it / ntx, cy = rest % nty, cz = rest / nty;
+        const int i = cx * kSp3X + lx, j = cy * kSp3Y + ly;
+        const int ic = min(i, n0 - 1), jc = min(j, n1 - 1);
+        const int k0 = cz * lz, k1 = min(n2, k0 + lz);
+        const bool hw = ic > 0, he = ic < n0 - 1, hs = jc > 0, hn = jc < n1 - 1;
+        const int oW = hw ? -1 : 0, oE = he ? 1 : 0, oS = hs ? -n0 : 0, oN = hn ? n0 : 0;
+        int64_t P = ic + (int64_t)jc * s1 + (int64_t)k0 * s2;
+        const int64_t Pb = k0 > 0 ? P - s2 : P;
+        double xb = x[Pb];                   // x of the plane below
+        double cb = SYM ? aF[Pb] : 0.0;      // (SYM) its upper z coupling = this point's a^B
+        double xc = x[P];
+        for (int k = k0; k < k1; ++k, P += s2) {
+            const bool hu = k < n2 - 1, hd = k > 0;
+            const double xu = x[hu ? P + s2 : P];
+            const double cP = aP[P];
+            const double cW = SYM ? aE[P + oW] : D.d[1][P];
+            const double cE = aE[P];
+            const double cS = SYM ? aN[P + oS] : D.d[3][P];
+            const double cN = aN[P];
+            const double cB = SYM ? cb : D.d[5][P];
+            const double cF = aF[P];
+            const double xW = x[P + oW], xE = x[P + oE], xS = x[P + oS], xN = x[P + oN];
+            double acc = cP * xc;
+            acc = fma(-(hw ? cW : 0.0), xW, acc);
+            acc = fma(-(he ? cE : 0.0), xE, acc);
+            acc = fma(-(hs ? cS : 0.0), xS, acc);
+            acc = fma(-(hn ? cN : 0.0), xN, acc);
+            acc = fma(-(hd ? cB : 0.0), xb, acc);
+            acc = fma(-(hu ? cF : 0.0), xu, acc);
+            q[P] = acc;
+            xb = xc;
+            xc = xu;
+            cb = cF;
+        }
+    }
+}
+
+// Items of k_spmv3: column tiles of kSp3X x kSp3Y, each cut into z runs of lz
+// planes when the tiles alone are fewer than kRedBlocks; blocks = min(items, kRedBlocks).
+struct Sp3Plan {
+    int ntx, nty, lz, items, nb;
+};
+
+static bool sp3_plan(const int n[3], Sp3Plan &pl) {
+    if (n[0] < 1 || n[1] < 1 || n[2] < 1) return false;
+    pl.ntx = (n[0] + kSp3X - 1) / kSp3X;
+    pl.nty = (n[1] + kSp3Y - 1) / kSp3Y;
+    const int64_t ncol = (int64_t)pl.ntx * pl.nty;
+    int nz = ncol < kRedBlocks ? (int)std::min<int64_t>(n[2], kRedBlocks / ncol) : 1;
+    pl.lz = (n[2] + nz - 1) / nz;
+    nz = (n[2] + pl.lz - 1) / pl.lz;
+    const int64_t items = ncol * nz;
+    if (items > (int64_t)0x7fffffff) return false;
+    pl.items = (int)items;
+    pl.nb = (int)std::min<int64_t>(items, kRedBlocks);
+    return true;
+}
+
+hipError_t launch_spmv3(const int n[3], const double *const *diag, bool sym, const double *x, double *q,
+                        hipStream_t st) {
+    Sp3Plan pl;
+    if (!sp3_plan(n, pl)) return hipErrorInvalidValue;
+    DiagPtrs D{};
+    for (int k = 0; k < 7; ++k) D.d[k] = diag[k];
+    if (sym)
+        hipLaunchKernelGGL(k_spmv3<true>, dim3(pl.nb), dim3(kSp3X * kSp3Y), 0, st, n[0], n[1], n[2], pl.ntx,
+                           pl.nty, pl.lz, pl.items, D, x, q);
+    else
+        hipLaunchKernelGGL(k_spmv3<false>, dim3(pl.nb), dim3(kSp3X * kSp3Y), 0, st, n[0], n[1], n[2], pl.ntx,
+                           pl.nty, pl.lz, pl.items, D, x, q);
+    return hipGetLastError();
 }
 
 // z = 0.5 z1 + b z2, with one rounding after the exact halving (the symmetric preconditioner's combination)
@@ -2198,34 +2244,6 @@ hipError_t launch_dot_partial_zz(const double *r, const double *z1, const double
 hipError_t launch_dot_partial_zf(const double *r, const double *z1, const float *z2, double b, int64_t N,
                                  double *partials, hipStream_t st) {
     hipLaunchKernelGGL(k_dot_partial_zz<float>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, r, z1, z2, b, N, partials);
-    return hipGetLastError();
-}
-
-template <typename Z2>
-__global__ void __launch_bounds__(kRedThreads) k_cg_p_red_zz(double *p, const double *z1, const Z2 *z2, double b,
-                                                            const double *num_partials, double *num,
-                                                            const double *den, int64_t N) {
-    __shared__ double sh[kRedThreads];
-    const double rz = sum_partials(num_partials, sh);
-    if (blockIdx.x == 0 && threadIdx.x == 0) num[0] = rz;
-    const double beta = rz / den[0];
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = zcomb(z1[i], (double)z2[i], b) + beta * p[i];
-}
-
-hipError_t launch_cg_update_p_red_zz(double *p, const double *z1, const double *z2, double b,
-                                     const double *num_partials, double *num, const double *den, int64_t N,
-                                     hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_p_red_zz<double>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, p, z1, z2, b, num_partials,
-                       num, den, N);
-    return hipGetLastError();
-}
-
-hipError_t launch_cg_update_p_red_zf(double *p, const double *z1, const float *z2, double b,
-                                     const double *num_partials, double *num, const double *den, int64_t N,
-                                     hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_p_red_zz<float>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, p, z1, z2, b, num_partials,
-                       num, den, N);
     return hipGetLastError();
 }
 
@@ -2467,6 +2485,186 @@ hipError_t launch_cg_pq2d(int n0, int n1, const double *const *diag, const doubl
     return hipGetLastError();
 }
 
+// ------------------------------------------------ fused CG step, 7-point operator
+// Element i of an array: with 32-bit indices (I = uint32_t, used when every byte offset fits in
+// 31 bits) the byte offset is formed in 32 bits, so the loads take an SGPR base and one VGPR
+// offset instead of a 64-bit address per load.
+template <typename I, typename T> __device__ __forceinline__ const T &elt(const T *b, I i) {
+    if constexpr (sizeof(I) == 4)
+        return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(b) + (uint32_t)(i * (uint32_t)sizeof(T)));
+    else
+        return b[i];
+}
+template <typename I, typename T> __device__ __forceinline__ T &elt(T *b, I i) {
+    if constexpr (sizeof(I) == 4)
+        return *reinterpret_cast<T *>(reinterpret_cast<char *>(b) + (uint32_t)(i * (uint32_t)sizeof(T)));
+    else
+        return b[i];
+}
+
+// The 3D counterpart of k_cg_pq2d: beta = rz / rz_old[0] with rz the sum of kRedBlocks partials
+// (stored to rz_new[0]; beta = 0 when first), pnew = z + beta pold with z = 0.5 z1 + hb z2
+// (SPLIT: z2 the FP32 piece of the split preconditioner) or z = z1, x += alpha_prev[0] pold (not
+// when first), q = A pnew, and one partial of pnew.q per block (*npq of them).  The columns march
+// through z runs as in k_spmv3: pnew of the planes below and above stays in registers, and each
+// in-plane neighbour's pnew is formed again from its z and pold (lines that the neighbouring lanes
+// and waves load for their own columns), so no point waits for another's result.  Each step issues
+// all its loads before the first use.  pnew and q are stored by every lane (a lane past the grid's
+// edge stores its clamped column's bits again); x, read and written, only by the column's own lane.
+template <bool SYM, bool SPLIT, typename I>
+__global__ void __launch_bounds__(kSp3X *kSp3Y)
+    k_cg_pq3d(int n0, int n1, int n2, int ntx, int nty, int lz, int nitems, DiagPtrs D,
+              const double *__restrict__ z1, const float *__restrict__ z2, double hb,
+              const double *__restrict__ pold, double *__restrict__ pnew, double *__restrict__ q,
+              double *__restrict__ x, const double *rz_part, double *rz_new, const double *rz_old,
+              const double *alpha_prev, int first, double *pq_part) {
+    __shared__ double sh[kSp3X * kSp3Y];
+    __shared__ double s_rz;
+    if (threadIdx.x < 64) {
+        const double v = wave_sum_partials(rz_part, kRedBlocks);
+        if (threadIdx.x == 0) s_rz = v;
+    }
+    __syncthreads();
+    const double rz = s_rz;
+    if (blockIdx.x == 0 && threadIdx.x == 0) rz_new[0] = rz;
+    const double beta = first ? 0.0 : rz / rz_old[0];
+    const double alpha = first ? 0.0 : alpha_prev[0];
+    // pnew from z1, z2 and pold at one point (pold read also when first, and then not used)
+    auto form = [&](double a1, float a2, double po) -> double {
+        const double zv = SPLIT ? zcomb(a1, (double)a2, hb) : a1;
+        return first ? zv : __fma_rn(beta, po, zv);
+    };
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int start = (nb & 7) == 0 ? (b & 7) * (nb >> 3) + (b >> 3) : b;
+    const I s1 = (I)n0, s2 = (I)n0 * (I)n1;
+    const int lx = threadIdx.x % kSp3X, ly = threadIdx.x / kSp3X;
+    const double *__restrict__ aP = D.d[0], *__restrict__ aE = D.d[2], *__restrict__ aN = D.d[4];
+    const double *__restrict__ aF = D.d[6];
+    double dot = 0.0;
+    for (int it = start; it < nitems; it += nb) {
+        const int cx = it % ntx, rest = it / ntx, cy = rest % nty, cz = rest / nty;
+        const int i = cx * kSp3X + lx, j = cy * kSp3Y + ly;
+        const bool own = i < n0 && j < n1;
+        const int ic = min(i, n0 - 1), jc = min(j, n1 - 1);
+        const int k0 = cz * lz, k1 = min(n2, k0 + lz);
+        const bool hw = ic > 0, he = ic < n0 - 1, hs = jc > 0, hn = jc < n1 - 1;
+        const I oW = hw ? (I)-1 : (I)0, oE = he ? (I)1 : (I)0, oS = hs ? (I)0 - s1 : (I)0, oN = hn ? s1 : (I)0;
+        I P = (I)ic + (I)jc * s1 + (I)k0 * s2;
+        const I Pb = k0 > 0 ? P - s2 : P;
+        double pb = form(elt(z1, Pb), SPLIT ? elt(z2, Pb) : 0.f, elt(pold, Pb)); // pnew of the plane below
+        double cb = SYM ? elt(aF, Pb) : 0.0; // (SYM) its upper z coupling = this point's a^B
+        double poc = elt(pold, P);
+        double pc = form(elt(z1, P), SPLIT ? elt(z2, P) : 0.f, poc);
+        // the run's first values are waited for here, once, and not at every step's head
+        __asm__ volatile("" : : "v"(pb), "v"(cb), "v"(poc), "v"(pc));
+        for (int k = k0; k < k1; ++k, P += s2) {
+            const bool hu = k < n2 - 1, hd = k > 0;
+            // every load of the step is issued before the first use (order: the plane above,
+            // the four in-plane neighbours, the couplings, x last)
+            const I Q[5] = {hu ? P + s2 : P, P + oW, P + oE, P + oS, P + oN};
+            double l1[5], lo[5];
+            float l2[5];
+#pragma unroll
+            for (int u = 0; u < 5; ++u) {
+                l1[u] = elt(z1, Q[u]);
+                l2[u] = SPLIT ? elt(z2, Q[u]) : 0.f;
+                lo[u] = elt(pold, Q[u]);
+            }
+            const double cP = elt(aP, P);
+            const double cW = SYM ? elt(aE, P + oW) : elt(D.d[1], P);
+            const double cE = elt(aE, P);
+            const double cS = SYM ? elt(aN, P + oS) : elt(D.d[3], P);
+            const double cN = elt(aN, P);
+            const double cB = SYM ? cb : elt(D.d[5], P);
+            const double cF = elt(aF, P);
+            const double xv = elt((const double *)x, P);
+            __builtin_amdgcn_sched_barrier(0);
+            double pn[5];
+#pragma unroll
+            for (int u = 0; u < 5; ++u) pn[u] = form(l1[u], l2[u], lo[u]);
+            double acc = cP * pc;
+            acc = fma(-(hw ? cW : 0.0), pn[1], acc);
+            acc = fma(-(he ? cE : 0.0), pn[2], acc);
+            acc = fma(-(hs ? cS : 0.0), pn[3], acc);
+            acc = fma(-(hn ? cN : 0.0), pn[4], acc);
+            acc = fma(-(hd ? cB : 0.0), pb, acc);
+            acc = fma(-(hu ? cF : 0.0), pn[0], acc);
+            elt(pnew, P) = pc;
+            elt(q, P) = acc;
+            dot = fma(own ? pc : 0.0, acc, dot);
+            // xv is used here, outside the branch, so that its load stays with the others
+            // instead of being moved under the branch and waited for there
+            __asm__ volatile("" : : "v"(xv));
+            if (own && !first) elt(x, P) = __fma_rn(alpha, poc, xv);
+            pb = pc;
+            pc = pn[0];
+            poc = lo[0];
+            cb = cF;
+        }
+    }
+    const double s = block_sum(dot, sh);
+    if (threadIdx.x == 0) pq_part[b] = s;
+}
+
+// blocks of k_cg_pq3d<SYM, SPLIT, I> resident on the device at once (queried once per instance)
+template <bool SYM, bool SPLIT, typename I> static int cg_pq3d_resident() {
+    static int cached = 0;
+    if (cached == 0) {
+        int dev = 0, ncu = 0, per = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cg_pq3d<SYM, SPLIT, I>, kSp3X * kSp3Y, 0) !=
+                hipSuccess || ncu < 1 || per < 1)
+            return kRedBlocks;
+        cached = std::min(ncu * per, kCgPq3dMaxBlocks);
+    }
+    return cached;
+}
+
+template <bool SYM, bool SPLIT, typename I>
+static hipError_t cg_pq3d_launch(const int n[3], const DiagPtrs &D, const double *z1, const float *z2, double hb,
+                                 const double *pold, double *pnew, double *q, double *x, const double *rz_part,
+                                 double *rz_new, const double *rz_old, const double *alpha_prev, bool first,
+                                 double *pq_part, int *npq, hipStream_t st) {
+    // one z run per resident block where the column tiles allow it, so the blocks run in one round
+    const int cap = cg_pq3d_resident<SYM, SPLIT, I>();
+    const int ntx = (n[0] + kSp3X - 1) / kSp3X, nty = (n[1] + kSp3Y - 1) / kSp3Y;
+    const int64_t ncol = (int64_t)ntx * nty;
+    int nz = ncol < cap ? (int)std::min<int64_t>(n[2], cap / ncol) : 1;
+    const int lz = (n[2] + nz - 1) / nz;
+    nz = (n[2] + lz - 1) / lz;
+    const int64_t items = ncol * nz;
+    if (items > (int64_t)0x7fffffff) return hipErrorInvalidValue;
+    const int nb = (int)std::min<int64_t>(items, cap);
+    *npq = nb;
+    hipLaunchKernelGGL((k_cg_pq3d<SYM, SPLIT, I>), dim3(nb), dim3(kSp3X * kSp3Y), 0, st, n[0], n[1], n[2], ntx, nty,
+                       lz, (int)items, D, z1, z2, hb, pold, pnew, q, x, rz_part, rz_new, rz_old, alpha_prev,
+                       (int)first, pq_part);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_pq3d(const int n[3], const double *const *diag, const double *z1, const float *z2, double hb,
+                          const double *pold, double *pnew, double *q, double *x, const double *rz_part,
+                          double *rz_new, const double *rz_old, const double *alpha_prev, bool first,
+                          double *pq_part, int *npq, bool sym, hipStream_t st) {
+    if (n[0] < 1 || n[1] < 1 || n[2] < 1) return hipErrorInvalidValue;
+    DiagPtrs D{};
+    for (int k = 0; k < 7; ++k) D.d[k] = diag[k];
+    const bool i32 = (int64_t)n[0] * n[1] * n[2] * (int64_t)sizeof(double) < ((int64_t)1 << 31);
+#define PSW_CG_PQ3(SY, SP)                                                                                           \
+    (i32 ? cg_pq3d_launch<SY, SP, uint32_t>(n, D, z1, z2, hb, pold, pnew, q, x, rz_part, rz_new, rz_old,            \
+                                            alpha_prev, first, pq_part, npq, st)                                     \
+         : cg_pq3d_launch<SY, SP, int64_t>(n, D, z1, z2, hb, pold, pnew, q, x, rz_part, rz_new, rz_old,             \
+                                           alpha_prev, first, pq_part, npq, st))
+    hipError_t e;
+    if (sym)
+        e = z2 ? PSW_CG_PQ3(true, true) : PSW_CG_PQ3(true, false);
+    else
+        e = z2 ? PSW_CG_PQ3(false, true) : PSW_CG_PQ3(false, false);
+#undef PSW_CG_PQ3
+    return e;
+}
+
 // r -= alpha q with alpha = rz / (sum of npq p.q partials); out[0] = p.q, out[1] = alpha,
 // out[2 + b] = block b's partial of r.r (kRedBlocks of them).  The same values go to hout
 // (pinned host memory, device-visible) when given, for the host's stopping test.
@@ -2512,50 +2710,6 @@ __global__ void k_axpy_dev(double *y, const double *a, const double *x, int64_t 
 
 hipError_t launch_axpy_dev(double *y, const double *a, const double *x, int64_t N, hipStream_t st) {
     hipLaunchKernelGGL(k_axpy_dev, dim3(grid_for(N)), dim3(256), 0, st, y, a, x, N);
-    return hipGetLastError();
-}
-
-template <typename Z2>
-__global__ void k_zcomb(double *z, const double *z1, const Z2 *z2, double b, int64_t N) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
-        z[i] = zcomb(z1[i], (double)z2[i], b);
-}
-
-hipError_t launch_zcomb(double *z, const double *z1, const double *z2, double b, int64_t N, hipStream_t st) {
-    hipLaunchKernelGGL(k_zcomb<double>, dim3(grid_for(N)), dim3(256), 0, st, z, z1, z2, b, N);
-    return hipGetLastError();
-}
-
-hipError_t launch_zcomb_f(double *z, const double *z1, const float *z2, double b, int64_t N, hipStream_t st) {
-    hipLaunchKernelGGL(k_zcomb<float>, dim3(grid_for(N)), dim3(256), 0, st, z, z1, z2, b, N);
-    return hipGetLastError();
-}
-
-hipError_t launch_cg_update_p_red(double *p, const double *z, const double *num_partials, double *num,
-                                  const double *den, int64_t N, hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_p_red, dim3(kRedBlocks), dim3(kRedThreads), 0, st, p, z, num_partials, num, den, N);
-    return hipGetLastError();
-}
-
-__global__ void k_cg_p(double *p, const double *z, const double *num, const double *den, int64_t N) {
-    const double beta = num[0] / den[0];
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = z[i] + beta * p[i];
-}
-
-hipError_t launch_cg_update_p(double *p, const double *z, const double *num, const double *den, int64_t N,
-                              hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_p, dim3(grid_for(N)), dim3(256), 0, st, p, z, num, den, N);
-    return hipGetLastError();
-}
-
-__global__ void k_axpy(double *y, double a, const double *x, int64_t N) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
-        y[i] += a * x[i];
-}
-
-hipError_t launch_axpy(double *y, double a, const double *x, int64_t N, hipStream_t st) {
-    hipLaunchKernelGGL(k_axpy, dim3(grid_for(N)), dim3(256), 0, st, y, a, x, N);
     return hipGetLastError();
 }
 
