@@ -7,7 +7,8 @@ bit; the CG / FGMRES loops then read only the upper couplings.  Here:
 * the same operator with one coupling changed in its last bit (no longer symmetric): the general
   SpMV runs, and CG reaches the oracle's solution (1e-6) with its count within 1;
 * a non-symmetric operator (W and E couplings scaled differently, a^P raised to keep diagonal
-  dominance): FGMRES with the preconditioner pair against the oracle's FGMRES.
+  dominance): FGMRES with the preconditioner pair against the oracle's FGMRES;
+* a 3D operator one bit off with FP32 sweeps: CG against the oracle's FP64 CG.
 """
 import numpy as np
 import pytest
@@ -86,3 +87,37 @@ def test_nonsymmetric_user_diagonals_fgmres(dim, n, p):
     assert np.linalg.norm(x - xr) <= 1e-6 * np.linalg.norm(xr)
     rel = np.linalg.norm(f - Aop(x)) / np.linalg.norm(f)
     assert rel <= 1.05e-8
+
+
+def test_nonsymmetric_storage_fp32_sweeps_3d_cg():
+    """3D CG with FP32 sweeps (the LDS-tile passes, whose transposed pair stays a separate FP32 piece of
+    z) on an operator given as user diagonals with one coupling one unit in the last place off: the
+    general operator product inside the fused CG step, against the oracle's FP64 CG on the same
+    perturbed operator (solution within 1e-7, count within 10 %, true residual through the oracle's
+    SpMV)."""
+    import torch
+    dim, n, p = 3, (24, 20, 18), (2, 2, 2)
+    pr = synth.random_small(900 + sum(n), dim, n)
+    diags = [d.copy() for d in O.assemble(dim, n, pr["alphas"])]
+    N = int(np.prod(n))
+    k = N // 3
+    assert diags[6][k] > 0
+    diags[6][k] = np.nextafter(diags[6][k], np.inf)  # one F coupling: no longer symmetric
+    f = pr["f"]
+    Aop = lambda v: O.spmv(dim, n, diags, v)
+    pc = O.Precond("ilu0", dim, n, p, diags, omega=1.0)
+    xr, it_or, _ = O.cg(Aop, pc.apply_sym, f, rtol=1e-8)
+    import paper_1008_3699_amd as P
+    g = P.Problem(dim, n)
+    g.set_diagonals([np.ascontiguousarray(d) for d in diags], prec="f32")
+    g.set_relaxation([1.0])
+    g.set_decomposition(p, overlap=2)
+    u = torch.zeros(N, dtype=torch.float64, device=dev())
+    info = g.solve("cg", "ilu0", to_dev(f), u, rtol=1e-8, maxit=5000)
+    x = to_np(u)
+    rel = np.linalg.norm(f - Aop(x)) / np.linalg.norm(f)
+    err = np.linalg.norm(x - xr) / np.linalg.norm(xr)
+    print(f"iters {info['iters']} (oracle FP64 {it_or}), true relres {rel:.2e}, error {err:.2e}", flush=True)
+    assert info["converged"] and rel <= 1.05e-8
+    assert abs(info["iters"] - it_or) <= max(2, 0.1 * it_or)
+    assert err <= 1e-7
