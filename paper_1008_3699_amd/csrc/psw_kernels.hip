@@ -2282,11 +2282,15 @@ __device__ __forceinline__ void ldv(const double *__restrict__ a, int64_t P, dou
         o[0] = a[P];
     }
 }
+// streaming (nontemporal) stores of one or two doubles: lines written by a pass over the grid and
+// not read again by it, so that they do not take L2 room from the lines it still reads
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
 template <int V> __device__ __forceinline__ void stv(double *__restrict__ a, int64_t P, const double (&v)[V]) {
-    if constexpr (V == 2)
-        *reinterpret_cast<double2 *>(a + P) = make_double2(v[0], v[1]);
-    else
-        a[P] = v[0];
+    if constexpr (V == 2) {
+        nt_d2 t = {v[0], v[1]};
+        __builtin_nontemporal_store(t, reinterpret_cast<nt_d2 *>(a + P));
+    } else
+        __builtin_nontemporal_store(v[0], a + P);
 }
 
 // inputs of the new p on one row (z pieces, old p) and the operator row with x
@@ -2989,6 +2993,7 @@ __global__ void __launch_bounds__(1024) k_tile3(Tile3Args<S, TIN, TOUT> A) {
             }
         }
     }
+    // write-back with streaming stores: the output lines are not read again by this pass
     const T cs = (T)A.cscale;
     if (tc < RPI) {
         for (int x = tx; x < len0; x += XS) {
@@ -2999,7 +3004,7 @@ __global__ void __launch_bounds__(1024) k_tile3(Tile3Args<S, TIN, TOUT> A) {
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int cr = c0 + u * RPI;
-                    if (cr < C) A.out[gi] = (TOUT)(cs * own[cr * pitch + x]);
+                    if (cr < C) __builtin_nontemporal_store((TOUT)(cs * own[cr * pitch + x]), &A.out[gi]);
                     advance(l1w, l2w, gi);
                 }
             }
