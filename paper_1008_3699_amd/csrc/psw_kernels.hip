@@ -2574,14 +2574,15 @@ __global__ void __launch_bounds__(kSp3X *kSp3Y)
                 l2[u] = SPLIT ? elt(z2, Q[u]) : 0.f;
                 lo[u] = elt(pold, Q[u]);
             }
-            const double cP = elt(aP, P);
+            // a^P, a^F and x are read once, by this point's lane: streaming loads
+            const double cP = __builtin_nontemporal_load(&elt(aP, P));
             const double cW = SYM ? elt(aE, P + oW) : elt(D.d[1], P);
             const double cE = elt(aE, P);
             const double cS = SYM ? elt(aN, P + oS) : elt(D.d[3], P);
             const double cN = elt(aN, P);
             const double cB = SYM ? cb : elt(D.d[5], P);
-            const double cF = elt(aF, P);
-            const double xv = elt((const double *)x, P);
+            const double cF = __builtin_nontemporal_load(&elt(aF, P));
+            const double xv = __builtin_nontemporal_load(&elt((const double *)x, P));
             __builtin_amdgcn_sched_barrier(0);
             double pn[5];
 #pragma unroll
@@ -2905,7 +2906,7 @@ __global__ void __launch_bounds__(1024) k_tile3(Tile3Args<S, TIN, TOUT> A) {
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const bool in = c0 + u * RPI < C;
-                    v[u] = A.in[in ? gi : gx];
+                    v[u] = __builtin_nontemporal_load(&A.in[in ? gi : gx]); // read once: streaming load
                     if (in && !on_face(x, l1, l2)) keep |= 1u << u;
                     advance(l1, l2, gi);
                 }
