@@ -2272,14 +2272,17 @@ __device__ __forceinline__ double wave_sum_partials(const double *p, int n) {
     return acc;
 }
 
+// streaming (nontemporal) loads of one or two doubles for the 2D fused CG step: its streams are
+// read once, and without the hint their lines push the next passes' coefficients out of the caches
 template <int V>
 __device__ __forceinline__ void ldv(const double *__restrict__ a, int64_t P, double (&o)[V]) {
     if constexpr (V == 2) {
-        const double2 t = *reinterpret_cast<const double2 *>(a + P);
+        typedef double ntl_d2 __attribute__((ext_vector_type(2)));
+        const ntl_d2 t = __builtin_nontemporal_load(reinterpret_cast<const ntl_d2 *>(a + P));
         o[0] = t.x;
         o[1] = t.y;
     } else {
-        o[0] = a[P];
+        o[0] = __builtin_nontemporal_load(a + P);
     }
 }
 // streaming (nontemporal) stores of one or two doubles: lines written by a pass over the grid and
